@@ -1,0 +1,256 @@
+"""Oracle: Python driver for the plain FP64 Teukolsky solver in teuk_oracle.c.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
+leg of the benchmark import this module; the product path never does.
+
+It builds the chart-T grid (uniform in x = r_*, cell-centred in theta), the
+per-point coefficient tables from the symbolic derivation in
+``oracle.coefficients``, the time-step bound, and calls the C routines for the
+WENO5 right-hand side and SSP-RK(3,3) steps.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import coefficients as coeffs
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "teuk_oracle.c")
+_LIB = os.path.join(_HERE, "_liboracle.so")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def build_oracle(verbose: bool = False) -> str:
+    """Compile teuk_oracle.c with gcc (rounding exactly as written: no
+    contraction, no fast math).  Returns the library path."""
+    cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
+           "-shared", _SRC, "-o", _LIB + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _OracleTeuk(ctypes.Structure):
+    _fields_ = [("nr", ctypes.c_long), ("nth", ctypes.c_long),
+                ("dx", ctypes.c_double), ("dth", ctypes.c_double), ("eps", ctypes.c_double),
+                ("parity", ctypes.c_double)] + [
+                (n, _dp) for n in ("lam1", "lam2", "m3r", "m3i", "btr", "bti", "cr", "ci", "ath", "bth")]
+
+
+RHS_FN = ctypes.CFUNCTYPE(None, _dp, _dp, ctypes.c_void_p)
+
+_lib_handle = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the oracle library, building it first if it is not there."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build_oracle()
+        L = ctypes.CDLL(_LIB)
+        L.oracle_weno5_weights_plus.argtypes = [_dp, ctypes.c_double, _dp]
+        L.oracle_weno5_weights_minus.argtypes = [_dp, ctypes.c_double, _dp]
+        for fn in ("oracle_weno5_flux_plus", "oracle_weno5_flux_minus"):
+            getattr(L, fn).argtypes = [_dp, ctypes.c_double]
+            getattr(L, fn).restype = ctypes.c_double
+        for fn in ("oracle_weno5_combine_plus", "oracle_weno5_combine_minus"):
+            getattr(L, fn).argtypes = [_dp, _dp]
+            getattr(L, fn).restype = ctypes.c_double
+        for fn in ("oracle_dplus", "oracle_dminus"):
+            getattr(L, fn).argtypes = [_dp, ctypes.c_long, ctypes.c_double, ctypes.c_double]
+            getattr(L, fn).restype = ctypes.c_double
+        L.oracle_ssprk3_step.argtypes = [_dp, ctypes.c_long, ctypes.c_double, RHS_FN, ctypes.c_void_p, _dp]
+        L.oracle_advect1d.argtypes = [_dp, ctypes.c_long, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_long, ctypes.c_double]
+        L.oracle_teuk_rhs.argtypes = [ctypes.POINTER(_OracleTeuk), _dp, _dp]
+        L.oracle_teuk_evolve.argtypes = [ctypes.POINTER(_OracleTeuk), _dp, ctypes.c_double, ctypes.c_long,
+                                         ctypes.c_long, ctypes.c_long, _dp, ctypes.c_long]
+        L.oracle_teuk_evolve.restype = ctypes.c_long
+        L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        _lib_handle = L
+    return _lib_handle
+
+
+def ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+# ----------------------------------------------------------------------------- 1D helpers
+def weno5_weights_plus(f5, eps=1e-6):
+    f = np.ascontiguousarray(f5, dtype=np.float64)
+    w = np.zeros(3)
+    lib().oracle_weno5_weights_plus(ptr(f), eps, ptr(w))
+    return w
+
+
+def weno5_weights_minus(f5, eps=1e-6):
+    f = np.ascontiguousarray(f5, dtype=np.float64)
+    w = np.zeros(3)
+    lib().oracle_weno5_weights_minus(ptr(f), eps, ptr(w))
+    return w
+
+
+def weno5_flux_plus(f5, eps=1e-6):
+    f = np.ascontiguousarray(f5, dtype=np.float64)
+    return lib().oracle_weno5_flux_plus(ptr(f), eps)
+
+
+def weno5_flux_minus(f5, eps=1e-6):
+    f = np.ascontiguousarray(f5, dtype=np.float64)
+    return lib().oracle_weno5_flux_minus(ptr(f), eps)
+
+
+def weno5_combine_plus(f5, w):
+    f = np.ascontiguousarray(f5, dtype=np.float64)
+    ww = np.ascontiguousarray(w, dtype=np.float64)
+    return lib().oracle_weno5_combine_plus(ptr(f), ptr(ww))
+
+
+def derivative(p_padded, j, dx, side, eps=1e-6):
+    """D^+ (side=+1) or D^- (side=-1) at point j of a row padded by 3 each side."""
+    p = np.ascontiguousarray(p_padded, dtype=np.float64)
+    base = p.ctypes.data + 3 * 8
+    pp = ctypes.cast(base, _dp)
+    fn = lib().oracle_dplus if side > 0 else lib().oracle_dminus
+    return fn(pp, j, dx, eps)
+
+
+def advect1d(u0, dx, speed, dt, nsteps, eps=1e-6):
+    u = np.ascontiguousarray(u0, dtype=np.float64).copy()
+    lib().oracle_advect1d(ptr(u), u.size, dx, speed, dt, nsteps, eps)
+    return u
+
+
+def ssprk3_step(u0, dt, rhs):
+    """One SSP-RK(3,3) step of the oracle with a Python right-hand side rhs(u)->F."""
+    u = np.ascontiguousarray(u0, dtype=np.float64).copy()
+    n = u.size
+    work = np.zeros(3 * n)
+
+    def cb(up, Fp, _ctx):
+        uu = np.ctypeslib.as_array(up, shape=(n,))
+        FF = np.ctypeslib.as_array(Fp, shape=(n,))
+        FF[:] = rhs(uu.copy())
+
+    f = RHS_FN(cb)
+    lib().oracle_ssprk3_step(ptr(u), n, dt, f, None, ptr(work))
+    return u
+
+
+# ----------------------------------------------------------------------------- Teukolsky
+@dataclass
+class Problem:
+    """A chart-T solve: background (M, a), field (s, m) and the grid."""
+    s: int
+    m: int
+    a: float
+    nr: int
+    nth: int
+    x_min: float
+    x_max: float
+    M: float = 1.0
+    eps: float = 1e-6
+
+    @property
+    def dx(self):
+        return (self.x_max - self.x_min) / (self.nr - 1)
+
+    @property
+    def dth(self):
+        return np.pi / self.nth
+
+    def x(self):
+        """Radial nodes x_j = x_min + j dx (x = r_*)."""
+        return self.x_min + self.dx * np.arange(self.nr)
+
+    def theta(self):
+        """Cell-centred polar nodes theta_k = (k + 1/2) pi / nth; no node on a pole."""
+        return (np.arange(self.nth) + 0.5) * self.dth
+
+    def parity(self):
+        return -1.0 if (self.m + self.s) % 2 else 1.0
+
+
+class TeukOracle:
+    """Chart-T oracle for one Problem: coefficient tables plus the C solver."""
+
+    def __init__(self, prob: Problem):
+        self.prob = prob
+        x = prob.x()
+        self.r, self.y, self.Delta = coeffs.r_of_tortoise(x, prob.M, prob.a)
+        th = prob.theta()
+        R = self.r[None, :]
+        D = self.Delta[None, :]
+        T = th[:, None]
+        c = coeffs.first_order_coefficients(R, D, T, prob.M, prob.a, prob.s, prob.m)
+        shp = (prob.nth, prob.nr)
+        f = lambda v: np.ascontiguousarray(np.broadcast_to(v, shp), dtype=np.float64)
+        self.tab = {
+            "lam1": f(c["lam1"]), "lam2": f(c["lam2"]),
+            "m3r": f(c["m3"].real), "m3i": f(c["m3"].imag),
+            "btr": f(c["Bt"].real), "bti": f(c["Bt"].imag),
+            "cr": f(c["C"].real), "ci": f(c["C"].imag),
+            "ath": f(c["Ath"]), "bth": f(c["Bth"]),
+        }
+        self._s = _OracleTeuk(prob.nr, prob.nth, prob.dx, prob.dth, prob.eps, prob.parity(),
+                              *[ptr(self.tab[n]) for n in ("lam1", "lam2", "m3r", "m3i", "btr",
+                                                           "bti", "cr", "ci", "ath", "bth")])
+
+    # a8: stability bound (reading of the SSP framework of Sec. 3.2)
+    def dt_bound(self, cfl=0.5):
+        """dt = cfl / max_points( max(|lam1|,|lam2|)/dx + sqrt(4 Ath/dth^2 + |Bth|/dth + |C|) ).
+
+        The square root bounds the frequency of the theta part (Gershgorin on
+        the centred theta operator acting through the Phi-pi coupling); the
+        first term is the radial upwind speed over dx.
+        """
+        p, t = self.prob, self.tab
+        lam = np.maximum(np.abs(t["lam1"]), np.abs(t["lam2"]))
+        om = np.sqrt(4.0 * t["ath"] / p.dth**2 + np.abs(t["bth"]) / p.dth + np.hypot(t["cr"], t["ci"]))
+        return cfl / float(np.max(lam / p.dx + om))
+
+    def rhs(self, u):
+        """F(u) for u of shape [4][nth][nr]."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        F = np.empty_like(u)
+        lib().oracle_teuk_rhs(ctypes.byref(self._s), ptr(u), ptr(F))
+        return F
+
+    def extract_index(self, x_e):
+        p = self.prob
+        return int(np.floor((x_e - p.x_min) / p.dx + 0.5))
+
+    def evolve(self, u0, dt, nsteps, x_e=None, every=0, max_samples=0):
+        """Run nsteps SSP-RK3 steps.  Returns (u, wave[n][nth][2] or None)."""
+        u = np.ascontiguousarray(u0, dtype=np.float64).copy()
+        wave = None
+        j_e = 0
+        if x_e is not None and every > 0:
+            j_e = self.extract_index(x_e)
+            if max_samples <= 0:
+                max_samples = nsteps // every + 1
+            wave = np.zeros((max_samples, self.prob.nth, 2))
+        n = lib().oracle_teuk_evolve(ctypes.byref(self._s), ptr(u), dt, nsteps, j_e, every,
+                                     ptr(wave) if wave is not None else None, max_samples)
+        if wave is not None:
+            wave = wave[:n]
+        return u, wave
+
+
+def set_threads(n: int):
+    lib().oracle_set_threads(int(n))
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
