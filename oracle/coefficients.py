@@ -139,9 +139,21 @@ def _lambdified(kind: str):
     return {k: sp.lambdify(args, v, modules="numpy") for k, v in exprs.items()}
 
 
-def _eval(fn, rr, Dd, cc, ss, M, a, s, m):
-    val = fn(rr, Dd, cc, ss, float(M), float(a), int(s), int(m))
-    return np.broadcast_to(np.asarray(val, dtype=np.complex128), np.broadcast(rr, cc).shape).copy()
+def _eval(fn, rr, Dd, th, M, a, s, m):
+    """Evaluate a lambdified coefficient in x87 extended precision, then round.
+
+    The expressions keep eq. teuk0's terms as printed; its three angular terms
+    (1/sin^2 d_phph, 2 i s cos/sin^2 d_ph, -s^2 cot^2) combine into
+    -(m + s cos)^2 / sin^2, which for m = -s (or m = s) nearly vanishes at the
+    pole and is formed from O(m^2/sin^2) pieces.  Evaluating in long double
+    (64-bit significand) and rounding once makes the FP64 tables accurate to
+    about an ulp there as well.
+    """
+    ld = np.longdouble
+    rr, Dd, th = (np.asarray(v, dtype=ld) for v in (rr, Dd, th))
+    val = fn(rr, Dd, np.cos(th), np.sin(th), ld(M), ld(a), int(s), int(m))
+    val = np.asarray(val)
+    return np.broadcast_to(val.astype(np.complex128), np.broadcast(rr, th).shape).copy()
 
 
 def second_order_coefficients(r_, Delta_, theta_, M, a, s, m):
@@ -151,8 +163,7 @@ def second_order_coefficients(r_, Delta_, theta_, M, a, s, m):
     arrays Axx, Ath, Bt, Bx, Bth, C.
     """
     fns = _lambdified("second_order")
-    cc, ss = np.cos(theta_), np.sin(theta_)
-    return {k: _eval(f, r_, Delta_, cc, ss, M, a, s, m) for k, f in fns.items()}
+    return {k: _eval(f, r_, Delta_, theta_, M, a, s, m) for k, f in fns.items()}
 
 
 def first_order_coefficients(r_, Delta_, theta_, M, a, s, m):
@@ -164,10 +175,9 @@ def first_order_coefficients(r_, Delta_, theta_, M, a, s, m):
         d_t pi  = -lam2 d_x pi - m3 d_x Phi + Bt pi + Ath Phi_thth + Bth Phi_th + C Phi
     """
     fns = _lambdified("first_order")
-    cc, ss = np.cos(theta_), np.sin(theta_)
     out = {}
     for k, f in fns.items():
-        v = _eval(f, r_, Delta_, cc, ss, M, a, s, m)
+        v = _eval(f, r_, Delta_, theta_, M, a, s, m)
         out[k] = v.real.copy() if k in ("lam1", "lam2", "Ath", "Bth", "Axx") else v
     return out
 

@@ -227,6 +227,29 @@ def test_spin_weighted_eigenvalues_continuum(s, m):
         np.testing.assert_allclose((G[l] - G[ls[0]]).real, want, rtol=1e-10)
 
 
+@pytest.mark.parametrize("s,m,pole", [(-2, 2, 0), (2, -2, 0), (-1, 1, 0), (-2, -2, 1), (2, 2, 1)])
+def test_angular_potential_accurate_at_the_pole(s, m, pole):
+    # For m = -s (theta -> 0) or m = s (theta -> pi) the angular potential
+    # (m + s cos)^2 / sin^2 stays finite while eq. teuk0 assembles it from
+    # O(m^2 / sin^2) pieces.  The separated operator applied to the l = |s|
+    # harmonic must give the same G as in the interior to ~1e-12 at 2e-3 and
+    # 1e-2 from the pole (harmonic derivatives in 40-digit arithmetic).
+    M = 1.0
+    l = max(abs(s), abs(m))
+    r = np.array([[2.5, 4.0, 12.0]])
+    D = r * (r - 2 * M)
+    near = np.array([0.002, 0.01]) if pole == 0 else np.pi - np.array([0.002, 0.01])
+    thv = np.concatenate([[1.1], near])[:, None]
+    c = C.second_order_coefficients(r, D, thv, M, 0.0, s, m)
+    th, Y = _goldberg(s, l, m)
+    mp.mp.dps = 40
+    Yd = [sp.lambdify(th, e, "mpmath") for e in (Y, sp.diff(Y, th), sp.diff(Y, th, 2))]
+    vals = np.array([[complex(f(mp.mpf(float(t)))) for f in Yd] for t in thv[:, 0]])
+    Yv, Y1, Y2 = (vals[:, i][:, None] for i in range(3))
+    g = (c["Ath"] * Y2 + c["Bth"] * Y1 + c["C"] * Yv) / Yv
+    assert np.max(np.abs(g - g[0:1])) < 2e-12 * np.max(np.abs(g)), np.abs(g - g[0:1])
+
+
 @pytest.mark.parametrize("s,m,l", [(0, 0, 2), (-2, 2, 2), (-2, 1, 3), (-2, 0, 2), (0, 1, 1), (-2, 3, 3)])
 def test_spin_weighted_discrete_theta_operator(s, m, l):
     # Oracle RHS on Phi = g(x) Y(theta), pi = 0 at a = 0: F_pi = g (Ath D2 + Bth D1 + C) Y.
