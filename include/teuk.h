@@ -1,0 +1,201 @@
+/*
+ * teuk.h - C ABI of libteuk, a WENO5 / SSP-RK3 solver for the 2+1D first-order
+ * Teukolsky system on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (paper Sec. 2): the Teukolsky master equation (eq. teuk0) for a field
+ * of spin weight s and azimuthal number m on a Kerr background of mass M and
+ * spin a (0 <= a <= M, a = M extremal), separated in the ingoing-Kerr azimuth
+ * (Sec. 3: exp(i m phi~) dependence), divided by -A^tt (eq. final) and reduced
+ * to first order in time (eq. evln):
+ *
+ *     d_t u + M d_x u + L u + A u = 0,   u = {Phi_R, Phi_I, pi_R, pi_I},
+ *
+ * with pi = d_t Phi + b d_x Phi.  The radial chart is the tortoise coordinate
+ * x = r_* (Sec. 2.2) and Psi = exp(i m phi~) r^-(2s+1) Phi, so that Phi is O(1)
+ * at large r.  The radial derivative is fifth-order WENO of Jiang and Shu
+ * (Sec. 3.1.2), upwinded per row by the sign of its speed (+b for the Phi rows,
+ * -b for the pi rows); theta derivatives are second-order centred (Sec. 3.1);
+ * time stepping is SSP-RK(3,3) in Shu-Osher form (Sec. 3.2).  The WENO
+ * smoothness indicators and weights may be computed in reduced precision with
+ * the weights summing to one in FP64 (Sec. 3.1.3); candidate fluxes, flux
+ * differences, the RK combination and extraction are always FP64.
+ *
+ * Grid: x_j = x_min + j (x_max - x_min)/(nr - 1), j = 0..nr-1;
+ *       theta_k = (k + 1/2) pi / ntheta, k = 0..ntheta-1 (no node on a pole).
+ * Boundaries: three ghost cells per radial side equal to the end value; one
+ *       ghost row per pole equal to (-1)^(m+s) times the mirrored row.
+ * State layout (host arrays across this ABI): four FP64 planes
+ *       [4][ntheta][nr] in the order Phi_R, Phi_I, pi_R, pi_I, radial index
+ *       fastest, densely packed.
+ *
+ * Conventions for every call:
+ *   - Every call returns a teuk_status; nothing aborts, throws or exits across
+ *     the ABI.  On failure teuk_last_error() describes the cause.
+ *   - Host pointers passed in are read (or written) only during the call and
+ *     are never retained.
+ *   - Device work is enqueued on the stream given at creation (the null stream
+ *     if none).  teuk_step returns once the work is enqueued; teuk_extract and
+ *     teuk_info synchronise that stream.
+ *   - One solver must not be used from two threads at once; different solvers
+ *     are independent.
+ */
+#ifndef TEUK_H
+#define TEUK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TEUK_ABI_VERSION 1
+
+typedef struct teuk_solver teuk_solver;   /* opaque; owned by the library */
+
+typedef enum {
+    TEUK_OK = 0,
+    TEUK_ERR_INVALID_ARG = -1,    /* bad configuration, pointer or enum      */
+    TEUK_ERR_OUT_OF_MEMORY = -2,  /* device allocation or workspace too small */
+    TEUK_ERR_DEVICE = -3,         /* a HIP runtime call failed               */
+    TEUK_ERR_STATE = -4,          /* call out of order (e.g. step before set_initial) */
+    TEUK_ERR_NONFINITE = -5,      /* NaN or Inf found in the state or input   */
+    TEUK_ERR_UNSUPPORTED = -6,    /* valid request this build does not offer  */
+    TEUK_ERR_CAPACITY = -7        /* output array smaller than the data       */
+} teuk_status;
+
+/* Radial chart.  Only the tortoise chart (x = r_*) is offered in ABI v1. */
+enum { TEUK_CHART_TORTOISE = 0 };
+
+/* Precision of the WENO smoothness indicators and nonlinear weights
+ * (Sec. 3.1.3).  Candidate fluxes and everything after them stay FP64. */
+enum { TEUK_W_FP64 = 0, TEUK_W_FP32 = 1, TEUK_W_FP16 = 2, TEUK_W_BF16 = 3 };
+
+/* What teuk_extract returns. */
+enum {
+    TEUK_X_STATE = 0,     /* [4][ntheta][nr] current state u^n                        */
+    TEUK_X_WAVEFORM = 1,  /* [n][ntheta][2] (Phi_R, Phi_I) at x_extract, oldest first */
+    TEUK_X_TIMES = 2,     /* [n] times of the waveform samples                        */
+    TEUK_X_COEFFS = 3     /* [TEUK_NCOEF][ntheta][nr] per-point coefficients as the
+                             device evaluates them (diagnostic)                       */
+};
+
+/* Per-point coefficients returned by TEUK_X_COEFFS / teuk_host_coefficients,
+ * plane order: b, Re m3, Im m3, Re B~t, Im B~t, Re C~, Im C~, A~thth, B~th, where
+ *   d_t Phi = pi - b d_x Phi
+ *   d_t pi  = b d_x pi - m3 d_x Phi + B~t pi + A~thth Phi_thth + B~th Phi_th + C~ Phi
+ * (the paper's M, A, L entries: m31 = Re m3, m32 = -Im m3, a31 = -Re C~,
+ *  a32 = Im C~, a33 = -Re B~t, a34 = Im B~t, l31 = -(A~thth d_thth + B~th d_th)). */
+#define TEUK_NCOEF 9
+
+typedef struct {
+    int32_t abi_version;     /* must equal TEUK_ABI_VERSION                          */
+    int32_t s;               /* spin weight, |s| <= 2                                 */
+    int32_t m;               /* azimuthal number, |m| <= 8                            */
+    int32_t chart;           /* TEUK_CHART_TORTOISE                                   */
+    int32_t nr;              /* radial points, 7 <= nr <= 2^24                         */
+    int32_t ntheta;          /* polar points, 2 <= ntheta <= 65536                     */
+    int32_t weight_prec;     /* TEUK_W_*                                              */
+    int32_t extract_every;   /* steps between waveform samples (0: no waveform)        */
+    int32_t max_samples;     /* waveform ring-buffer capacity (samples)                */
+    int32_t rows_per_block;  /* theta rows marched by one workgroup; 0 = library pick  */
+    double M;                /* black-hole mass (> 0)                                  */
+    double a;                /* spin, 0 <= a <= M                                      */
+    double x_min, x_max;     /* radial range of x = r_* (x_min < x_max)                */
+    double dt;               /* > 0: time step used as given; <= 0: cfl * stability bound */
+    double cfl;              /* used when dt <= 0 (e.g. 0.5)                           */
+    double weno_eps;         /* epsilon of the WENO weights (e.g. 1e-6), > 0           */
+    double x_extract;        /* waveform radius; the nearest grid node is sampled       */
+} teuk_config;
+
+typedef struct {
+    void* stream;            /* hipStream_t to enqueue on; NULL = null stream          */
+    void* workspace;         /* caller-owned device memory for every device buffer of
+                                the solver, or NULL to let the library allocate        */
+    size_t workspace_bytes;  /* size of workspace; must be >= teuk_footprint_bytes     */
+} teuk_device_ctx;
+
+typedef struct {
+    double dt;               /* time step in use                                       */
+    double t;                /* current time (steps * dt)                              */
+    int64_t steps;           /* steps taken since teuk_set_initial                     */
+    int64_t samples;         /* waveform samples recorded (may exceed max_samples)     */
+    int32_t j_extract;       /* radial index sampled for the waveform                  */
+    int32_t rows_per_block;  /* launch shape in use                                    */
+    double dt_bound;         /* stability bound (cfl = 1), from the device reduction   */
+} teuk_info_t;
+
+/* Fill cfg with defaults: ABI version, M = 1, chart T, FP64 weights, cfl 0.5,
+ * eps 1e-6, dt from the bound, no waveform.  Sizes and ranges must still be set. */
+void teuk_default_config(teuk_config* cfg);
+
+/* Device bytes one solver needs (three state buffers, coefficient tables,
+ * waveform ring, reduction cells), each carved at 256-byte alignment.  Returns
+ * 0 if cfg is invalid.  Used for admission by HBM footprint. */
+size_t teuk_footprint_bytes(const teuk_config* cfg);
+
+/* Create a solver on the current HIP device: validate cfg, build the chart-T
+ * background r(x), Delta(x) and the radial / polar coefficient tables on the
+ * host in FP64 (Sec. 2.1-2.3), upload them, and compute the stability bound by
+ * a device max-reduction over every grid point (Sec. 3.2, dt <= C dt_FE):
+ *     dt_bound = 1 / max( b/dx + sqrt(4 A~thth/dtheta^2 + |B~th|/dtheta + |C~|) ).
+ * If cfg->dt <= 0 the step is cfl * dt_bound.  ctx may be NULL.  On success
+ * *out owns its device buffers (or lives in ctx->workspace, which the caller
+ * keeps alive until teuk_destroy and which the library never frees).
+ * Errors: INVALID_ARG, OUT_OF_MEMORY (allocation, or workspace too small),
+ * DEVICE.  On error *out is NULL and teuk_last_error(NULL) says why. */
+teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk_solver** out);
+
+/* Set the state u^n (layout above; on_device != 0 means u is a device pointer
+ * with that dense layout, else a host pointer), reset t and the step and
+ * sample counters, and record the first waveform sample (t = 0).  The data
+ * are copied; u is not retained.  Host input is checked for NaN/Inf
+ * (NONFINITE); device input is checked by the device guard.
+ * Errors: INVALID_ARG (NULL), NONFINITE, DEVICE. */
+teuk_status teuk_set_initial(teuk_solver* h, const double* u, int32_t on_device);
+
+/* Advance nsteps SSP-RK(3,3) steps (Sec. 3.2), each three fused stage kernels
+ *     u1 = u + dt F(u);  u2 = 3/4 u + 1/4 (u1 + dt F(u1));  u = 1/3 u + 2/3 (u2 + dt F(u2)),
+ * with F(u) = -(M d_x u + L u + A u) of eq. evln and WENO5 radial derivatives
+ * (Sec. 3.1.2).  A waveform sample is taken after every extract_every-th step.
+ * Asynchronous on the solver's stream.  nsteps = 0 is a no-op.
+ * Errors: STATE (no initial data), INVALID_ARG (nsteps < 0), DEVICE. */
+teuk_status teuk_step(teuk_solver* h, int64_t nsteps);
+
+/* Copy results to the host array out (capacity in doubles); *written receives
+ * the number of doubles written (may be NULL).  Synchronises the stream and
+ * runs the non-finite guard on the state first (NONFINITE if it trips; the
+ * data are still copied for inspection).
+ *   TEUK_X_STATE     4*ntheta*nr doubles
+ *   TEUK_X_WAVEFORM  min(samples, max_samples)*ntheta*2 doubles, oldest first
+ *   TEUK_X_TIMES     min(samples, max_samples) doubles
+ *   TEUK_X_COEFFS    TEUK_NCOEF*ntheta*nr doubles
+ * Errors: INVALID_ARG, CAPACITY (out too small; nothing written), NONFINITE,
+ * DEVICE. */
+teuk_status teuk_extract(teuk_solver* h, int32_t what, double* out, size_t capacity, size_t* written);
+
+/* Solver information (synchronises the stream).  Errors: INVALID_ARG, DEVICE. */
+teuk_status teuk_info(teuk_solver* h, teuk_info_t* info);
+
+/* Run the device non-finite guard on the current state: a max-reduction that
+ * flags any NaN/Inf.  Synchronises.  Errors: NONFINITE, STATE, DEVICE. */
+teuk_status teuk_check_finite(teuk_solver* h);
+
+/* Release the solver and the device memory it allocated.  NULL-safe. */
+void teuk_destroy(teuk_solver* h);
+
+/* Last error message of h, or of the calling thread's last failed
+ * teuk_create / teuk_host_coefficients when h is NULL.  Never NULL. */
+const char* teuk_last_error(const teuk_solver* h);
+
+/* Host-only evaluation, in FP64, of the per-point coefficients (TEUK_X_COEFFS
+ * layout) from the same tables and the same formula the device uses.  Needs no
+ * GPU.  out holds capacity doubles (>= TEUK_NCOEF*ntheta*nr).
+ * Errors: INVALID_ARG, CAPACITY. */
+teuk_status teuk_host_coefficients(const teuk_config* cfg, double* out, size_t capacity);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TEUK_H */

@@ -1,0 +1,259 @@
+"""ctypes binding of libteuk (include/teuk.h): argument marshalling only.
+
+Every computation runs in the HIP library.  PyTorch supplies device memory
+(a workspace tensor the solver lives in) and streams; it is imported before
+the library is loaded so that both share one HIP runtime.  If libteuk.so has
+not been built, importing this module fails: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (plumbing: device memory and streams; loads the HIP runtime first)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libteuk.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                      "python paper_2010_04760_amd/build.py")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+TEUK_ABI_VERSION = 1
+TEUK_OK = 0
+TEUK_ERR_INVALID_ARG = -1
+TEUK_ERR_OUT_OF_MEMORY = -2
+TEUK_ERR_DEVICE = -3
+TEUK_ERR_STATE = -4
+TEUK_ERR_NONFINITE = -5
+TEUK_ERR_UNSUPPORTED = -6
+TEUK_ERR_CAPACITY = -7
+TEUK_CHART_TORTOISE = 0
+TEUK_W_FP64, TEUK_W_FP32, TEUK_W_FP16, TEUK_W_BF16 = 0, 1, 2, 3
+TEUK_X_STATE, TEUK_X_WAVEFORM, TEUK_X_TIMES, TEUK_X_COEFFS = 0, 1, 2, 3
+TEUK_NCOEF = 9
+WEIGHT_PREC = {"fp64": TEUK_W_FP64, "fp32": TEUK_W_FP32, "fp16": TEUK_W_FP16, "bf16": TEUK_W_BF16}
+
+_STATUS_NAMES = {0: "TEUK_OK", -1: "TEUK_ERR_INVALID_ARG", -2: "TEUK_ERR_OUT_OF_MEMORY", -3: "TEUK_ERR_DEVICE",
+                 -4: "TEUK_ERR_STATE", -5: "TEUK_ERR_NONFINITE", -6: "TEUK_ERR_UNSUPPORTED",
+                 -7: "TEUK_ERR_CAPACITY"}
+
+
+class teuk_config(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("s", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("chart", ctypes.c_int32), ("nr", ctypes.c_int32), ("ntheta", ctypes.c_int32),
+                ("weight_prec", ctypes.c_int32), ("extract_every", ctypes.c_int32),
+                ("max_samples", ctypes.c_int32), ("rows_per_block", ctypes.c_int32),
+                ("M", ctypes.c_double), ("a", ctypes.c_double), ("x_min", ctypes.c_double),
+                ("x_max", ctypes.c_double), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("weno_eps", ctypes.c_double), ("x_extract", ctypes.c_double)]
+
+
+class teuk_device_ctx(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+class teuk_info_t(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("t", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("samples", ctypes.c_int64), ("j_extract", ctypes.c_int32), ("rows_per_block", ctypes.c_int32),
+                ("dt_bound", ctypes.c_double)]
+
+
+_P = ctypes.POINTER
+_dp = _P(ctypes.c_double)
+_lib.teuk_default_config.argtypes = [_P(teuk_config)]
+_lib.teuk_default_config.restype = None
+_lib.teuk_footprint_bytes.argtypes = [_P(teuk_config)]
+_lib.teuk_footprint_bytes.restype = ctypes.c_size_t
+_lib.teuk_create.argtypes = [_P(teuk_config), _P(teuk_device_ctx), _P(ctypes.c_void_p)]
+_lib.teuk_create.restype = ctypes.c_int
+_lib.teuk_set_initial.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+_lib.teuk_set_initial.restype = ctypes.c_int
+_lib.teuk_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+_lib.teuk_step.restype = ctypes.c_int
+_lib.teuk_extract.argtypes = [ctypes.c_void_p, ctypes.c_int32, _dp, ctypes.c_size_t, _P(ctypes.c_size_t)]
+_lib.teuk_extract.restype = ctypes.c_int
+_lib.teuk_info.argtypes = [ctypes.c_void_p, _P(teuk_info_t)]
+_lib.teuk_info.restype = ctypes.c_int
+_lib.teuk_check_finite.argtypes = [ctypes.c_void_p]
+_lib.teuk_check_finite.restype = ctypes.c_int
+_lib.teuk_destroy.argtypes = [ctypes.c_void_p]
+_lib.teuk_destroy.restype = None
+_lib.teuk_last_error.argtypes = [ctypes.c_void_p]
+_lib.teuk_last_error.restype = ctypes.c_char_p
+_lib.teuk_host_coefficients.argtypes = [_P(teuk_config), _dp, ctypes.c_size_t]
+_lib.teuk_host_coefficients.restype = ctypes.c_int
+
+EXPORTED = ["teuk_default_config", "teuk_footprint_bytes", "teuk_create", "teuk_set_initial", "teuk_step",
+            "teuk_extract", "teuk_info", "teuk_check_finite", "teuk_destroy", "teuk_last_error",
+            "teuk_host_coefficients"]
+
+
+class TeukError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _check(st: int, h=None):
+    if st != TEUK_OK:
+        raise TeukError(st, _lib.teuk_last_error(h).decode())
+
+
+# ----------------------------------------------------------------------------- same names as the C ABI
+def teuk_default_config() -> teuk_config:
+    c = teuk_config()
+    _lib.teuk_default_config(ctypes.byref(c))
+    return c
+
+
+def teuk_footprint_bytes(cfg: teuk_config) -> int:
+    return int(_lib.teuk_footprint_bytes(ctypes.byref(cfg)))
+
+
+def teuk_create(cfg: teuk_config, ctx: teuk_device_ctx | None = None) -> int:
+    h = ctypes.c_void_p()
+    st = _lib.teuk_create(ctypes.byref(cfg), ctypes.byref(ctx) if ctx is not None else None, ctypes.byref(h))
+    _check(st)
+    return h.value
+
+
+def teuk_set_initial(h: int, u) -> None:
+    if isinstance(u, torch.Tensor):
+        if u.dtype != torch.float64 or not u.is_contiguous() or not u.is_cuda:
+            raise ValueError("device initial data must be a contiguous float64 CUDA tensor")
+        _check(_lib.teuk_set_initial(h, ctypes.c_void_p(u.data_ptr()), 1), h)
+    else:
+        a = np.ascontiguousarray(u, dtype=np.float64)
+        _check(_lib.teuk_set_initial(h, a.ctypes.data_as(ctypes.c_void_p), 0), h)
+
+
+def teuk_step(h: int, nsteps: int) -> None:
+    _check(_lib.teuk_step(h, int(nsteps)), h)
+
+
+def teuk_extract(h: int, what: int, capacity: int) -> np.ndarray:
+    out = np.empty(max(int(capacity), 1), dtype=np.float64)
+    written = ctypes.c_size_t(0)
+    st = _lib.teuk_extract(h, int(what), out.ctypes.data_as(_dp), int(capacity), ctypes.byref(written))
+    if st == TEUK_ERR_NONFINITE:
+        raise TeukError(st, _lib.teuk_last_error(h).decode() + " (state copied for inspection)")
+    _check(st, h)
+    return out[: written.value]
+
+
+def teuk_info(h: int) -> teuk_info_t:
+    info = teuk_info_t()
+    _check(_lib.teuk_info(h, ctypes.byref(info)), h)
+    return info
+
+
+def teuk_check_finite(h: int) -> None:
+    _check(_lib.teuk_check_finite(h), h)
+
+
+def teuk_destroy(h: int | None) -> None:
+    _lib.teuk_destroy(h)
+
+
+def teuk_last_error(h: int | None = None) -> str:
+    return _lib.teuk_last_error(h).decode()
+
+
+def teuk_host_coefficients(cfg: teuk_config) -> np.ndarray:
+    n = cfg.nr * cfg.ntheta
+    out = np.empty(TEUK_NCOEF * n, dtype=np.float64)
+    _check(_lib.teuk_host_coefficients(ctypes.byref(cfg), out.ctypes.data_as(_dp), out.size))
+    return out.reshape(TEUK_NCOEF, cfg.ntheta, cfg.nr)
+
+
+# ----------------------------------------------------------------------------- convenience (marshalling only)
+def make_config(*, s: int, m: int, a: float, nr: int, ntheta: int, x_min: float, x_max: float,
+                M: float = 1.0, dt: float = 0.0, cfl: float = 0.5, weno_eps: float = 1e-6,
+                weight_prec="fp64", x_extract: float | None = None, extract_every: int = 0,
+                max_samples: int = 0, rows_per_block: int = 0) -> teuk_config:
+    c = teuk_default_config()
+    c.s, c.m, c.a, c.M = int(s), int(m), float(a), float(M)
+    c.nr, c.ntheta = int(nr), int(ntheta)
+    c.x_min, c.x_max = float(x_min), float(x_max)
+    c.dt, c.cfl, c.weno_eps = float(dt), float(cfl), float(weno_eps)
+    c.weight_prec = WEIGHT_PREC[weight_prec] if isinstance(weight_prec, str) else int(weight_prec)
+    c.extract_every, c.max_samples = int(extract_every), int(max_samples)
+    c.x_extract = float(x_min if x_extract is None else x_extract)
+    c.rows_per_block = int(rows_per_block)
+    return c
+
+
+class Solver:
+    """One solve on the current CUDA (HIP) device.
+
+    The solver's device buffers live in a torch uint8 workspace tensor held by
+    this object, and its kernels run on `stream` (default: torch's current
+    stream).  Methods map one-to-one onto the C ABI.
+    """
+
+    def __init__(self, cfg: teuk_config, stream: "torch.cuda.Stream | None" = None, device=None):
+        self.cfg = cfg
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        nbytes = teuk_footprint_bytes(cfg)
+        if nbytes == 0:
+            # let the library report why the configuration is invalid
+            teuk_create(cfg, None)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self._ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.ctx = teuk_device_ctx(ctypes.c_void_p(self.stream.cuda_stream), ctypes.c_void_p(aligned), nbytes)
+        self.h = teuk_create(cfg, self.ctx)
+
+    @property
+    def plane_shape(self):
+        return (4, self.cfg.ntheta, self.cfg.nr)
+
+    def set_initial(self, u):
+        teuk_set_initial(self.h, u)
+
+    def step(self, nsteps: int):
+        teuk_step(self.h, nsteps)
+
+    def state(self) -> np.ndarray:
+        n = 4 * self.cfg.ntheta * self.cfg.nr
+        return teuk_extract(self.h, TEUK_X_STATE, n).reshape(self.plane_shape)
+
+    def info(self) -> teuk_info_t:
+        return teuk_info(self.h)
+
+    def waveform(self):
+        inf = self.info()
+        ns = min(inf.samples, self.cfg.max_samples) if self.cfg.extract_every > 0 else 0
+        w = teuk_extract(self.h, TEUK_X_WAVEFORM, ns * self.cfg.ntheta * 2).reshape(ns, self.cfg.ntheta, 2)
+        t = teuk_extract(self.h, TEUK_X_TIMES, ns)
+        return t, w
+
+    def coefficients(self) -> np.ndarray:
+        n = self.cfg.ntheta * self.cfg.nr
+        return teuk_extract(self.h, TEUK_X_COEFFS, TEUK_NCOEF * n).reshape(TEUK_NCOEF, self.cfg.ntheta, self.cfg.nr)
+
+    def check_finite(self):
+        teuk_check_finite(self.h)
+
+    def close(self):
+        if self.h is not None:
+            teuk_destroy(self.h)
+            self.h = None
+            self._ws = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

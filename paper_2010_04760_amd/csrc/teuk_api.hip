@@ -1,0 +1,437 @@
+// C ABI of libteuk (declared in include/teuk.h): validation, device buffers,
+// the SSP-RK(3,3) step loop, waveform ring buffer, guard and extraction.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "teuk_coef.h"
+#include "teuk_internal.h"
+
+using namespace teuk;
+
+struct teuk_solver {
+    teuk_config cfg;
+    hipStream_t stream = nullptr;
+    bool owns = false;
+    void* base = nullptr;
+    size_t bytes = 0;
+    double* u[3] = {nullptr, nullptr, nullptr};   // u^n, u^(1), u^(2)
+    double* rtab = nullptr;
+    double* ttab = nullptr;
+    double* wave = nullptr;
+    unsigned long long* cell = nullptr;             // dt-bound reduction cell
+    int* flag = nullptr;                            // non-finite flag
+    double dx = 0, dth = 0, dt = 0, dt_bound = 0;
+    int j_e = 0;
+    int rows = 0, nstrips = 0, nchunks = 0;
+    long long plane = 0;
+    long long steps = 0, samples = 0;
+    bool have_init = false;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t u, rtab, ttab, wave, cells, total;
+};
+
+Layout layout_of(const teuk_config& c)
+{
+    Layout L;
+    const size_t plane = (size_t)c.nr * (size_t)c.ntheta;
+    L.u = align_up(4 * plane * sizeof(double));
+    L.rtab = align_up((size_t)kNRT * c.nr * sizeof(double));
+    L.ttab = align_up((size_t)kNTT * c.ntheta * sizeof(double));
+    const size_t ns = c.extract_every > 0 ? (size_t)c.max_samples : 0;
+    L.wave = align_up(ns * (size_t)c.ntheta * 2 * sizeof(double));
+    L.cells = kAlign;
+    L.total = 3 * L.u + L.rtab + L.ttab + L.wave + L.cells;
+    return L;
+}
+
+bool validate(const teuk_config* c, std::string& err)
+{
+    if (!c) { err = "cfg is NULL"; return false; }
+    if (c->abi_version != TEUK_ABI_VERSION) { err = "abi_version must be " + std::to_string(TEUK_ABI_VERSION); return false; }
+    if (c->chart != TEUK_CHART_TORTOISE) { err = "only the tortoise chart (TEUK_CHART_TORTOISE) is offered"; return false; }
+    if (c->s < -2 || c->s > 2) { err = "spin weight s must satisfy |s| <= 2"; return false; }
+    if (c->m < -8 || c->m > 8) { err = "azimuthal number m must satisfy |m| <= 8"; return false; }
+    if (c->nr < 7 || c->nr > (1 << 24)) { err = "nr must be in [7, 2^24]"; return false; }
+    if (c->ntheta < 2 || c->ntheta > 65536) { err = "ntheta must be in [2, 65536]"; return false; }
+    if ((long long)c->nr * c->ntheta > (1LL << 34)) { err = "nr * ntheta too large"; return false; }
+    if (c->weight_prec < TEUK_W_FP64 || c->weight_prec > TEUK_W_BF16) { err = "weight_prec must be a TEUK_W_* value"; return false; }
+    if (!(c->M > 0.0) || !std::isfinite(c->M)) { err = "M must be positive and finite"; return false; }
+    if (!(c->a >= 0.0) || !(c->a <= c->M)) { err = "spin a must satisfy 0 <= a <= M"; return false; }
+    if (!std::isfinite(c->x_min) || !std::isfinite(c->x_max) || !(c->x_min < c->x_max)) { err = "need finite x_min < x_max"; return false; }
+    if (!(c->weno_eps > 0.0) || !std::isfinite(c->weno_eps)) { err = "weno_eps must be positive and finite"; return false; }
+    if (!std::isfinite(c->dt)) { err = "dt must be finite"; return false; }
+    if (c->dt <= 0.0 && (!(c->cfl > 0.0) || !std::isfinite(c->cfl))) { err = "cfl must be positive when dt <= 0"; return false; }
+    if (c->extract_every < 0 || c->max_samples < 0) { err = "extract_every and max_samples must be >= 0"; return false; }
+    if (c->extract_every > 0) {
+        if (c->max_samples < 1) { err = "max_samples must be >= 1 when extract_every > 0"; return false; }
+        if (!(c->x_extract >= c->x_min && c->x_extract <= c->x_max)) { err = "x_extract must lie in [x_min, x_max]"; return false; }
+    }
+    if (c->rows_per_block < 0) { err = "rows_per_block must be >= 0"; return false; }
+    return true;
+}
+
+// Rows of theta marched by one workgroup: enough workgroups to fill 256 CUs
+// several times over, rows >= 4 so the theta halo stays small.
+int pick_rows(const teuk_config& c, int nstrips)
+{
+    if (c.rows_per_block > 0) return c.rows_per_block < c.ntheta ? c.rows_per_block : c.ntheta;
+    int rows = 16;
+    while (rows > 4 && (long long)nstrips * ((c.ntheta + rows - 1) / rows) < 8192) rows /= 2;
+    return rows < c.ntheta ? rows : c.ntheta;
+}
+
+teuk_status fail(teuk_solver* h, teuk_status st, const std::string& msg)
+{
+    if (h) h->err = msg; else g_err = msg;
+    return st;
+}
+
+teuk_status hip_fail(teuk_solver* h, int e, const char* what)
+{
+    return fail(h, TEUK_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString((hipError_t)e));
+}
+
+void free_solver(teuk_solver* h)
+{
+    if (!h) return;
+    if (h->owns && h->base) (void)hipFree(h->base);
+    delete h;
+}
+
+teuk_status run_guard(teuk_solver* h)
+{
+    int e = (int)hipMemsetAsync(h->flag, 0, sizeof(int), h->stream);
+    if (e) return hip_fail(h, e, "hipMemsetAsync(flag)");
+    e = launch_guard(h->u[0], 4 * h->plane, h->flag, h->stream);
+    if (e) return hip_fail(h, e, "guard launch");
+    int f = 0;
+    e = (int)hipMemcpyAsync(&f, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e) return hip_fail(h, e, "hipMemcpyAsync(flag)");
+    e = (int)hipStreamSynchronize(h->stream);
+    if (e) return hip_fail(h, e, "hipStreamSynchronize");
+    if (f) return fail(h, TEUK_ERR_NONFINITE, "non-finite value (NaN or Inf) in the state");
+    return TEUK_OK;
+}
+
+teuk_status record_sample(teuk_solver* h)
+{
+    if (h->cfg.extract_every <= 0) return TEUK_OK;
+    const long long slot = h->samples % h->cfg.max_samples;
+    double* dst = h->wave + (size_t)slot * h->cfg.ntheta * 2;
+    int e = launch_extract(h->u[0], h->plane, h->cfg.nr, h->cfg.ntheta, h->j_e, dst, h->stream);
+    if (e) return hip_fail(h, e, "extract launch");
+    ++h->samples;
+    return TEUK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void teuk_default_config(teuk_config* c)
+{
+    if (!c) return;
+    std::memset(c, 0, sizeof(*c));
+    c->abi_version = TEUK_ABI_VERSION;
+    c->chart = TEUK_CHART_TORTOISE;
+    c->weight_prec = TEUK_W_FP64;
+    c->M = 1.0;
+    c->cfl = 0.5;
+    c->weno_eps = 1e-6;
+}
+
+size_t teuk_footprint_bytes(const teuk_config* cfg)
+{
+    std::string err;
+    if (!validate(cfg, err)) return 0;
+    return layout_of(*cfg).total;
+}
+
+teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk_solver** out)
+{
+    if (!out) return fail(nullptr, TEUK_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    std::string err;
+    if (!validate(cfg, err)) return fail(nullptr, TEUK_ERR_INVALID_ARG, err);
+    std::vector<double> rtab, ttab;
+    if (!build_tables(*cfg, rtab, ttab, err)) return fail(nullptr, TEUK_ERR_INVALID_ARG, err);
+
+    teuk_solver* h = new (std::nothrow) teuk_solver();
+    if (!h) return fail(nullptr, TEUK_ERR_OUT_OF_MEMORY, "host allocation failed");
+    h->cfg = *cfg;
+    h->stream = ctx ? (hipStream_t)ctx->stream : nullptr;
+    const Layout L = layout_of(*cfg);
+    h->bytes = L.total;
+    if (ctx && ctx->workspace) {
+        if (ctx->workspace_bytes < L.total) {
+            delete h;
+            return fail(nullptr, TEUK_ERR_OUT_OF_MEMORY,
+                        "workspace holds " + std::to_string(ctx->workspace_bytes) + " bytes, solver needs " +
+                            std::to_string(L.total));
+        }
+        if (((uintptr_t)ctx->workspace) % kAlign) {
+            delete h;
+            return fail(nullptr, TEUK_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+        }
+        h->base = ctx->workspace;
+        h->owns = false;
+    } else {
+        int e = (int)hipMalloc(&h->base, L.total);
+        if (e) {
+            h->base = nullptr;
+            delete h;
+            (void)hipGetLastError();
+            return fail(nullptr, e == (int)hipErrorOutOfMemory ? TEUK_ERR_OUT_OF_MEMORY : TEUK_ERR_DEVICE,
+                        std::string("hipMalloc: ") + hipGetErrorString((hipError_t)e));
+        }
+        h->owns = true;
+    }
+    char* p = (char*)h->base;
+    for (int i = 0; i < 3; ++i) { h->u[i] = (double*)p; p += L.u; }
+    h->rtab = (double*)p; p += L.rtab;
+    h->ttab = (double*)p; p += L.ttab;
+    h->wave = (double*)p; p += L.wave;
+    h->cell = (unsigned long long*)p;
+    h->flag = (int*)(p + 64);
+
+    h->plane = (long long)cfg->nr * cfg->ntheta;
+    h->dx = (cfg->x_max - cfg->x_min) / (cfg->nr - 1);
+    h->dth = M_PI / cfg->ntheta;
+    h->nstrips = (cfg->nr + kStripPoints - 1) / kStripPoints;
+    h->rows = pick_rows(*cfg, h->nstrips);
+    h->nchunks = (cfg->ntheta + h->rows - 1) / h->rows;
+    while ((long long)h->nstrips * h->nchunks > (1LL << 30)) {   // keep the grid below 2^31 workgroups
+        h->rows *= 2;
+        h->nchunks = (cfg->ntheta + h->rows - 1) / h->rows;
+    }
+    h->j_e = cfg->extract_every > 0 ? (int)std::floor((cfg->x_extract - cfg->x_min) / h->dx + 0.5) : 0;
+    if (h->j_e > cfg->nr - 1) h->j_e = cfg->nr - 1;
+
+    int e = (int)hipMemcpyAsync(h->rtab, rtab.data(), rtab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (!e) e = (int)hipMemcpyAsync(h->ttab, ttab.data(), ttab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (!e) e = (int)hipMemsetAsync(h->cell, 0, sizeof(unsigned long long), h->stream);
+    if (!e) e = launch_dt_bound(h->rtab, h->ttab, cfg->nr, cfg->ntheta, h->dx, h->dth, h->cell, h->stream);
+    unsigned long long bits = 0;
+    if (!e) e = (int)hipMemcpyAsync(&bits, h->cell, sizeof(bits), hipMemcpyDeviceToHost, h->stream);
+    if (!e) e = (int)hipStreamSynchronize(h->stream);
+    if (e) {
+        std::string msg = std::string("device setup: ") + hipGetErrorString((hipError_t)e);
+        free_solver(h);
+        return fail(nullptr, TEUK_ERR_DEVICE, msg);
+    }
+    double mx;
+    std::memcpy(&mx, &bits, sizeof(mx));
+    if (!(mx > 0.0) || !std::isfinite(mx)) {
+        free_solver(h);
+        return fail(nullptr, TEUK_ERR_NONFINITE, "stability bound is not finite");
+    }
+    h->dt_bound = 1.0 / mx;
+    h->dt = cfg->dt > 0.0 ? cfg->dt : cfg->cfl * h->dt_bound;
+    *out = h;
+    return TEUK_OK;
+}
+
+teuk_status teuk_set_initial(teuk_solver* h, const double* u, int32_t on_device)
+{
+    if (!h) return fail(nullptr, TEUK_ERR_INVALID_ARG, "solver is NULL");
+    if (!u) return fail(h, TEUK_ERR_INVALID_ARG, "u is NULL");
+    const size_t n = 4 * (size_t)h->plane;
+    if (!on_device) {
+        for (size_t i = 0; i < n; ++i)
+            if (!std::isfinite(u[i])) return fail(h, TEUK_ERR_NONFINITE, "initial data contain NaN or Inf");
+    }
+    int e = (int)hipMemcpyAsync(h->u[0], u, n * sizeof(double),
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream);
+    if (e) return hip_fail(h, e, "hipMemcpyAsync(initial state)");
+    if (!on_device) {
+        e = (int)hipStreamSynchronize(h->stream);   // host array may be released after return
+        if (e) return hip_fail(h, e, "hipStreamSynchronize");
+    } else {
+        teuk_status st = run_guard(h);
+        if (st != TEUK_OK) return st;
+    }
+    h->steps = 0;
+    h->samples = 0;
+    h->have_init = true;
+    return record_sample(h);
+}
+
+teuk_status teuk_step(teuk_solver* h, int64_t nsteps)
+{
+    if (!h) return fail(nullptr, TEUK_ERR_INVALID_ARG, "solver is NULL");
+    if (nsteps < 0) return fail(h, TEUK_ERR_INVALID_ARG, "nsteps must be >= 0");
+    if (!h->have_init) return fail(h, TEUK_ERR_STATE, "teuk_step before teuk_set_initial");
+    const teuk_config& c = h->cfg;
+    StageArgs a;
+    a.rtab = h->rtab;
+    a.ttab = h->ttab;
+    a.plane = h->plane;
+    a.nr = c.nr;
+    a.nth = c.ntheta;
+    a.nstrips = h->nstrips;
+    a.nchunks = h->nchunks;
+    a.rows = h->rows;
+    a.inv6dx = 1.0 / (6.0 * h->dx);
+    a.ih1 = 1.0 / (2.0 * h->dth);
+    a.ih2 = 1.0 / (h->dth * h->dth);
+    a.dt = h->dt;
+    a.eps = c.weno_eps;
+    a.parity = ((c.m + c.s) % 2 != 0) ? -1.0 : 1.0;
+    for (int64_t n = 0; n < nsteps; ++n) {
+        // u1 = u + dt F(u)
+        a.uk = h->u[0]; a.un = h->u[0]; a.out = h->u[1]; a.ca = 0.0; a.cb = 1.0;
+        int e = launch_stage(a, 1, c.weight_prec, h->stream);
+        // u2 = 3/4 u + 1/4 (u1 + dt F(u1))
+        if (!e) { a.uk = h->u[1]; a.un = h->u[0]; a.out = h->u[2]; a.ca = 0.75; a.cb = 0.25;
+                  e = launch_stage(a, 2, c.weight_prec, h->stream); }
+        // u = 1/3 u + 2/3 (u2 + dt F(u2)), in place (u^n is read only at the own point)
+        if (!e) { a.uk = h->u[2]; a.un = h->u[0]; a.out = h->u[0]; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0;
+                  e = launch_stage(a, 3, c.weight_prec, h->stream); }
+        if (e) {
+            if (e == (int)hipErrorInvalidValue && c.weight_prec != TEUK_W_FP64)
+                return fail(h, TEUK_ERR_UNSUPPORTED, "weight precision not built");
+            return hip_fail(h, e, "stage launch");
+        }
+        ++h->steps;
+        if (c.extract_every > 0 && h->steps % c.extract_every == 0) {
+            teuk_status st = record_sample(h);
+            if (st != TEUK_OK) return st;
+        }
+    }
+    return TEUK_OK;
+}
+
+teuk_status teuk_extract(teuk_solver* h, int32_t what, double* out, size_t capacity, size_t* written)
+{
+    if (written) *written = 0;
+    if (!h) return fail(nullptr, TEUK_ERR_INVALID_ARG, "solver is NULL");
+    if (!out) return fail(h, TEUK_ERR_INVALID_ARG, "out is NULL");
+    const teuk_config& c = h->cfg;
+    const long long nsamp = c.extract_every > 0 ? (h->samples < c.max_samples ? h->samples : c.max_samples) : 0;
+    size_t need = 0;
+    switch (what) {
+    case TEUK_X_STATE: need = 4 * (size_t)h->plane; break;
+    case TEUK_X_WAVEFORM: need = (size_t)nsamp * c.ntheta * 2; break;
+    case TEUK_X_TIMES: need = (size_t)nsamp; break;
+    case TEUK_X_COEFFS: need = (size_t)TEUK_NCOEF * h->plane; break;
+    default: return fail(h, TEUK_ERR_INVALID_ARG, "unknown extract kind");
+    }
+    if (capacity < need) return fail(h, TEUK_ERR_CAPACITY, "output holds " + std::to_string(capacity) +
+                                                              " doubles, need " + std::to_string(need));
+    if ((what == TEUK_X_STATE || what == TEUK_X_WAVEFORM) && !h->have_init)
+        return fail(h, TEUK_ERR_STATE, "no state: call teuk_set_initial first");
+    int e = 0;
+    teuk_status guard = TEUK_OK;
+    if (what == TEUK_X_STATE) {
+        guard = run_guard(h);
+        if (guard == TEUK_ERR_DEVICE) return guard;
+        e = (int)hipMemcpyAsync(out, h->u[0], need * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    } else if (what == TEUK_X_WAVEFORM) {
+        const long long first = h->samples - nsamp;          // oldest sample kept
+        const size_t per = (size_t)c.ntheta * 2;
+        for (long long i = 0; i < nsamp && !e; ++i) {
+            const long long slot = (first + i) % c.max_samples;
+            e = (int)hipMemcpyAsync(out + i * per, h->wave + slot * per, per * sizeof(double),
+                                    hipMemcpyDeviceToHost, h->stream);
+        }
+    } else if (what == TEUK_X_TIMES) {
+        const long long first = h->samples - nsamp;
+        for (long long i = 0; i < nsamp; ++i) out[i] = (double)((first + i) * (long long)c.extract_every) * h->dt;
+    } else {
+        double* tmp = nullptr;
+        e = (int)hipMalloc(&tmp, need * sizeof(double));
+        if (!e) e = launch_coef_dump(h->rtab, h->ttab, c.nr, c.ntheta, tmp, h->stream);
+        if (!e) e = (int)hipMemcpyAsync(out, tmp, need * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+        if (!e) e = (int)hipStreamSynchronize(h->stream);
+        if (tmp) (void)hipFree(tmp);
+    }
+    if (!e) e = (int)hipStreamSynchronize(h->stream);
+    if (e) return hip_fail(h, e, "extract copy");
+    if (written) *written = need;
+    return guard;
+}
+
+teuk_status teuk_info(teuk_solver* h, teuk_info_t* info)
+{
+    if (!h) return fail(nullptr, TEUK_ERR_INVALID_ARG, "solver is NULL");
+    if (!info) return fail(h, TEUK_ERR_INVALID_ARG, "info is NULL");
+    int e = (int)hipStreamSynchronize(h->stream);
+    if (e) return hip_fail(h, e, "hipStreamSynchronize");
+    info->dt = h->dt;
+    info->t = (double)h->steps * h->dt;
+    info->steps = h->steps;
+    info->samples = h->samples;
+    info->j_extract = h->j_e;
+    info->rows_per_block = h->rows;
+    info->dt_bound = h->dt_bound;
+    return TEUK_OK;
+}
+
+teuk_status teuk_check_finite(teuk_solver* h)
+{
+    if (!h) return fail(nullptr, TEUK_ERR_INVALID_ARG, "solver is NULL");
+    if (!h->have_init) return fail(h, TEUK_ERR_STATE, "no state: call teuk_set_initial first");
+    return run_guard(h);
+}
+
+void teuk_destroy(teuk_solver* h)
+{
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    free_solver(h);
+}
+
+const char* teuk_last_error(const teuk_solver* h)
+{
+    return h ? h->err.c_str() : g_err.c_str();
+}
+
+teuk_status teuk_host_coefficients(const teuk_config* cfg, double* out, size_t capacity)
+{
+    std::string err;
+    if (!validate(cfg, err)) return fail(nullptr, TEUK_ERR_INVALID_ARG, err);
+    if (!out) return fail(nullptr, TEUK_ERR_INVALID_ARG, "out is NULL");
+    const size_t n = (size_t)cfg->nr * cfg->ntheta;
+    if (capacity < TEUK_NCOEF * n) return fail(nullptr, TEUK_ERR_CAPACITY, "out too small");
+    std::vector<double> rtab, ttab;
+    if (!build_tables(*cfg, rtab, ttab, err)) return fail(nullptr, TEUK_ERR_INVALID_ARG, err);
+    const int nr = cfg->nr, nth = cfg->ntheta;
+    for (int k = 0; k < nth; ++k) {
+        const double sn2 = ttab[kSn2 * nth + k], cs = ttab[kCs * nth + k];
+        const double cot = ttab[kCot * nth + k], th = ttab[kTh * nth + k];
+        for (int j = 0; j < nr; ++j) {
+            double rt[kNRT];
+            for (int t = 0; t < kNRT; ++t) rt[t] = rtab[(size_t)t * nr + j];
+            const PointCoef c = point_coef(rt, sn2, cs, cot, th, 1.0 / std::sqrt(sigma2(rt, sn2)));
+            const size_t i = (size_t)k * nr + j;
+            out[0 * n + i] = c.b;
+            out[1 * n + i] = c.m3r;
+            out[2 * n + i] = c.m3i;
+            out[3 * n + i] = c.btr;
+            out[4 * n + i] = c.bti;
+            out[5 * n + i] = c.cr;
+            out[6 * n + i] = c.ci;
+            out[7 * n + i] = c.ath;
+            out[8 * n + i] = c.bth;
+        }
+    }
+    return TEUK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,50 @@
+// Internal declarations shared by the C ABI (teuk_api.hip), the host tables
+// (teuk_background.cpp) and the device kernels (teuk_kernels.hip).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/teuk.h"
+
+namespace teuk {
+
+// Build the radial [kNRT][nr] and polar [kNTT][ntheta] tables of teuk_coef.h
+// for a validated chart-T configuration.  Returns false (with err) if a radial
+// node is too close to the horizon for FP64.
+bool build_tables(const teuk_config& c, std::vector<double>& rtab, std::vector<double>& ttab,
+                  std::string& err);
+
+// Points per radial strip of one stage workgroup (one wave of 64 lanes computes
+// 64 interface fluxes and 63 point updates).
+constexpr int kStripPoints = 63;
+
+// Arguments of one fused SSP-RK stage launch.
+struct StageArgs {
+    const double* uk;      // u^(k): 4 planes [4][nth][nr]
+    const double* un;      // u^n, read at the own point only (stages 2, 3)
+    double* out;           // u^(k+1); may alias un (stage 3 writes in place)
+    const double* rtab;    // radial table [kNRT][nr]
+    const double* ttab;    // polar table [kNTT][nth]
+    long long plane;       // nth * nr
+    int nr, nth;
+    int nstrips, nchunks, rows;
+    double inv6dx;         // 1 / (6 dx): candidate fluxes are carried times 6
+    double ih1, ih2;       // 1/(2 dtheta), 1/dtheta^2
+    double dt, ca, cb;     // out = ca un + cb (uk + dt F)
+    double eps, parity;    // WENO epsilon, (-1)^(m+s)
+};
+
+// Launchers (all asynchronous on `stream`; they return the hipError_t as int).
+int launch_stage(const StageArgs& a, int stage, int weight_prec, void* stream);
+int launch_dt_bound(const double* rtab, const double* ttab, int nr, int nth, double dx, double dth,
+                    unsigned long long* cell, void* stream);
+int launch_guard(const double* u, long long n, int* flag, void* stream);
+int launch_extract(const double* u, long long plane, int nr, int nth, int j_e, double* wave_slot,
+                   void* stream);
+int launch_coef_dump(const double* rtab, const double* ttab, int nr, int nth, double* out,
+                     void* stream);
+
+}  // namespace teuk
