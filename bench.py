@@ -76,7 +76,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20000, help="timed SSP-RK3 steps (workload length: 20000)")
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--weights", default="fp64", choices=["fp64", "fp32", "fp16", "bf16"])
-    ap.add_argument("--rows", type=int, default=0, help="theta rows per workgroup (0: library choice)")
+    ap.add_argument("--workgroups", type=int, default=0, help="stage-kernel workgroups (0: all the GPU holds at once)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
@@ -95,7 +95,7 @@ def main():
     total = args.warmup + args.steps
     cfg = T.make_config(s=wl.s, m=wl.m, a=wl.a, nr=wl.nr, ntheta=wl.nth, x_min=wl.x_min, x_max=wl.x_max,
                         M=wl.M, dt=0.0, cfl=0.5, weight_prec=args.weights, x_extract=wl.x_e,
-                        extract_every=wl.every, max_samples=total // wl.every + 1, rows_per_block=args.rows)
+                        extract_every=wl.every, max_samples=total // wl.every + 1, workgroups=args.workgroups)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
@@ -145,7 +145,7 @@ def main():
         "dtype": "f64" if args.weights == "fp64" else f"f64 (weights {args.weights})",
         "data": "synthetic",
         "config": {"workload": wl.name, "nr": wl.nr, "ntheta": wl.nth, "s": wl.s, "m": wl.m, "a": wl.a,
-                   "weights": args.weights, "dt": info.dt, "rows_per_block": info.rows_per_block,
+                   "weights": args.weights, "dt": info.dt, "workgroups": info.workgroups,
                    "extract_every": wl.every, "seed": wl.seed},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -68,7 +68,8 @@ typedef enum {
 enum { TEUK_CHART_TORTOISE = 0 };
 
 /* Precision of the WENO smoothness indicators and nonlinear weights
- * (Sec. 3.1.3).  Candidate fluxes and everything after them stay FP64. */
+ * (Sec. 3.1.3).  The six stencil differences, the candidate fluxes and
+ * everything after them stay FP64; omega_2 = 1 - omega_0 - omega_1 in FP64. */
 enum { TEUK_W_FP64 = 0, TEUK_W_FP32 = 1, TEUK_W_FP16 = 2, TEUK_W_BF16 = 3 };
 
 /* What teuk_extract returns. */
@@ -76,8 +77,10 @@ enum {
     TEUK_X_STATE = 0,     /* [4][ntheta][nr] current state u^n                        */
     TEUK_X_WAVEFORM = 1,  /* [n][ntheta][2] (Phi_R, Phi_I) at x_extract, oldest first */
     TEUK_X_TIMES = 2,     /* [n] times of the waveform samples                        */
-    TEUK_X_COEFFS = 3     /* [TEUK_NCOEF][ntheta][nr] per-point coefficients as the
+    TEUK_X_COEFFS = 3,    /* [TEUK_NCOEF][ntheta][nr] per-point coefficients as the
                              device evaluates them (diagnostic)                       */
+    TEUK_X_RHS = 4        /* [4][ntheta][nr] F(u^n) = -(M d_x u + L u + A u) of the
+                             current state, by the stage kernel (diagnostic)           */
 };
 
 /* Per-point coefficients returned by TEUK_X_COEFFS / teuk_host_coefficients,
@@ -98,7 +101,7 @@ typedef struct {
     int32_t weight_prec;     /* TEUK_W_*                                              */
     int32_t extract_every;   /* steps between waveform samples (0: no waveform)        */
     int32_t max_samples;     /* waveform ring-buffer capacity (samples)                */
-    int32_t rows_per_block;  /* theta rows marched by one workgroup; 0 = library pick  */
+    int32_t workgroups;      /* stage-kernel workgroups; 0 = all the GPU holds at once */
     double M;                /* black-hole mass (> 0)                                  */
     double a;                /* spin, 0 <= a <= M                                      */
     double x_min, x_max;     /* radial range of x = r_* (x_min < x_max)                */
@@ -121,7 +124,7 @@ typedef struct {
     int64_t steps;           /* steps taken since teuk_set_initial                     */
     int64_t samples;         /* waveform samples recorded (may exceed max_samples)     */
     int32_t j_extract;       /* radial index sampled for the waveform                  */
-    int32_t rows_per_block;  /* launch shape in use                                    */
+    int32_t workgroups;      /* stage-kernel workgroups in use (stages 2-3)             */
     double dt_bound;         /* stability bound (cfl = 1), from the device reduction   */
 } teuk_info_t;
 
@@ -170,6 +173,8 @@ teuk_status teuk_step(teuk_solver* h, int64_t nsteps);
  *   TEUK_X_WAVEFORM  min(samples, max_samples)*ntheta*2 doubles, oldest first
  *   TEUK_X_TIMES     min(samples, max_samples) doubles
  *   TEUK_X_COEFFS    TEUK_NCOEF*ntheta*nr doubles
+ *   TEUK_X_RHS       4*ntheta*nr doubles (uses the stage scratch buffer; the
+ *                    state is unchanged)
  * Errors: INVALID_ARG, CAPACITY (out too small; nothing written), NONFINITE,
  * DEVICE. */
 teuk_status teuk_extract(teuk_solver* h, int32_t what, double* out, size_t capacity, size_t* written);

@@ -33,7 +33,7 @@ TEUK_ERR_UNSUPPORTED = -6
 TEUK_ERR_CAPACITY = -7
 TEUK_CHART_TORTOISE = 0
 TEUK_W_FP64, TEUK_W_FP32, TEUK_W_FP16, TEUK_W_BF16 = 0, 1, 2, 3
-TEUK_X_STATE, TEUK_X_WAVEFORM, TEUK_X_TIMES, TEUK_X_COEFFS = 0, 1, 2, 3
+TEUK_X_STATE, TEUK_X_WAVEFORM, TEUK_X_TIMES, TEUK_X_COEFFS, TEUK_X_RHS = 0, 1, 2, 3, 4
 TEUK_NCOEF = 9
 WEIGHT_PREC = {"fp64": TEUK_W_FP64, "fp32": TEUK_W_FP32, "fp16": TEUK_W_FP16, "bf16": TEUK_W_BF16}
 
@@ -46,7 +46,7 @@ class teuk_config(ctypes.Structure):
     _fields_ = [("abi_version", ctypes.c_int32), ("s", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("chart", ctypes.c_int32), ("nr", ctypes.c_int32), ("ntheta", ctypes.c_int32),
                 ("weight_prec", ctypes.c_int32), ("extract_every", ctypes.c_int32),
-                ("max_samples", ctypes.c_int32), ("rows_per_block", ctypes.c_int32),
+                ("max_samples", ctypes.c_int32), ("workgroups", ctypes.c_int32),
                 ("M", ctypes.c_double), ("a", ctypes.c_double), ("x_min", ctypes.c_double),
                 ("x_max", ctypes.c_double), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("weno_eps", ctypes.c_double), ("x_extract", ctypes.c_double)]
@@ -58,7 +58,7 @@ class teuk_device_ctx(ctypes.Structure):
 
 class teuk_info_t(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("t", ctypes.c_double), ("steps", ctypes.c_int64),
-                ("samples", ctypes.c_int64), ("j_extract", ctypes.c_int32), ("rows_per_block", ctypes.c_int32),
+                ("samples", ctypes.c_int64), ("j_extract", ctypes.c_int32), ("workgroups", ctypes.c_int32),
                 ("dt_bound", ctypes.c_double)]
 
 
@@ -174,7 +174,7 @@ def teuk_host_coefficients(cfg: teuk_config) -> np.ndarray:
 def make_config(*, s: int, m: int, a: float, nr: int, ntheta: int, x_min: float, x_max: float,
                 M: float = 1.0, dt: float = 0.0, cfl: float = 0.5, weno_eps: float = 1e-6,
                 weight_prec="fp64", x_extract: float | None = None, extract_every: int = 0,
-                max_samples: int = 0, rows_per_block: int = 0) -> teuk_config:
+                max_samples: int = 0, workgroups: int = 0) -> teuk_config:
     c = teuk_default_config()
     c.s, c.m, c.a, c.M = int(s), int(m), float(a), float(M)
     c.nr, c.ntheta = int(nr), int(ntheta)
@@ -183,7 +183,7 @@ def make_config(*, s: int, m: int, a: float, nr: int, ntheta: int, x_min: float,
     c.weight_prec = WEIGHT_PREC[weight_prec] if isinstance(weight_prec, str) else int(weight_prec)
     c.extract_every, c.max_samples = int(extract_every), int(max_samples)
     c.x_extract = float(x_min if x_extract is None else x_extract)
-    c.rows_per_block = int(rows_per_block)
+    c.workgroups = int(workgroups)
     return c
 
 
@@ -232,6 +232,11 @@ class Solver:
         w = teuk_extract(self.h, TEUK_X_WAVEFORM, ns * self.cfg.ntheta * 2).reshape(ns, self.cfg.ntheta, 2)
         t = teuk_extract(self.h, TEUK_X_TIMES, ns)
         return t, w
+
+    def rhs(self) -> np.ndarray:
+        """F(u^n) as the stage kernel evaluates it (the state is unchanged)."""
+        n = 4 * self.cfg.ntheta * self.cfg.nr
+        return teuk_extract(self.h, TEUK_X_RHS, n).reshape(self.plane_shape)
 
     def coefficients(self) -> np.ndarray:
         n = self.cfg.ntheta * self.cfg.nr

@@ -28,7 +28,8 @@ struct teuk_solver {
     int* flag = nullptr;                            // non-finite flag
     double dx = 0, dth = 0, dt = 0, dt_bound = 0;
     int j_e = 0;
-    int rows = 0, nstrips = 0, nchunks = 0;
+    int nstrips = 0;
+    int grid[2] = {0, 0};                           // workgroups: stage 1, stages 2-3
     long long plane = 0;
     long long steps = 0, samples = 0;
     bool have_init = false;
@@ -82,18 +83,20 @@ bool validate(const teuk_config* c, std::string& err)
         if (c->max_samples < 1) { err = "max_samples must be >= 1 when extract_every > 0"; return false; }
         if (!(c->x_extract >= c->x_min && c->x_extract <= c->x_max)) { err = "x_extract must lie in [x_min, x_max]"; return false; }
     }
-    if (c->rows_per_block < 0) { err = "rows_per_block must be >= 0"; return false; }
+    if (c->workgroups < 0) { err = "workgroups must be >= 0"; return false; }
     return true;
 }
 
-// Rows of theta marched by one workgroup: enough workgroups to fill 256 CUs
-// several times over, rows >= 4 so the theta halo stays small.
-int pick_rows(const teuk_config& c, int nstrips)
+// Workgroups of the persistent stage grid: the resident capacity of the
+// kernel on this device (or the caller's count), never more than the number
+// of (strip, theta row) units.
+int pick_grid(const teuk_config& c, int nstrips, int weight_prec, bool first)
 {
-    if (c.rows_per_block > 0) return c.rows_per_block < c.ntheta ? c.rows_per_block : c.ntheta;
-    int rows = 16;
-    while (rows > 4 && (long long)nstrips * ((c.ntheta + rows - 1) / rows) < 8192) rows /= 2;
-    return rows < c.ntheta ? rows : c.ntheta;
+    const long long units = (long long)nstrips * c.ntheta;
+    long long g = c.workgroups > 0 ? c.workgroups : stage_grid(weight_prec, first);
+    if (g <= 0) return 0;
+    if (g > units) g = units;
+    return (int)g;
 }
 
 teuk_status fail(teuk_solver* h, teuk_status st, const std::string& msg)
@@ -214,11 +217,11 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     h->dx = (cfg->x_max - cfg->x_min) / (cfg->nr - 1);
     h->dth = M_PI / cfg->ntheta;
     h->nstrips = (cfg->nr + kStripPoints - 1) / kStripPoints;
-    h->rows = pick_rows(*cfg, h->nstrips);
-    h->nchunks = (cfg->ntheta + h->rows - 1) / h->rows;
-    while ((long long)h->nstrips * h->nchunks > (1LL << 30)) {   // keep the grid below 2^31 workgroups
-        h->rows *= 2;
-        h->nchunks = (cfg->ntheta + h->rows - 1) / h->rows;
+    h->grid[0] = pick_grid(*cfg, h->nstrips, cfg->weight_prec, true);
+    h->grid[1] = pick_grid(*cfg, h->nstrips, cfg->weight_prec, false);
+    if (h->grid[0] <= 0 || h->grid[1] <= 0) {
+        free_solver(h);
+        return fail(nullptr, TEUK_ERR_UNSUPPORTED, "weight precision not built (or occupancy query failed)");
     }
     h->j_e = cfg->extract_every > 0 ? (int)std::floor((cfg->x_extract - cfg->x_min) / h->dx + 0.5) : 0;
     if (h->j_e > cfg->nr - 1) h->j_e = cfg->nr - 1;
@@ -272,11 +275,8 @@ teuk_status teuk_set_initial(teuk_solver* h, const double* u, int32_t on_device)
     return record_sample(h);
 }
 
-teuk_status teuk_step(teuk_solver* h, int64_t nsteps)
+static StageArgs stage_args(const teuk_solver* h)
 {
-    if (!h) return fail(nullptr, TEUK_ERR_INVALID_ARG, "solver is NULL");
-    if (nsteps < 0) return fail(h, TEUK_ERR_INVALID_ARG, "nsteps must be >= 0");
-    if (!h->have_init) return fail(h, TEUK_ERR_STATE, "teuk_step before teuk_set_initial");
     const teuk_config& c = h->cfg;
     StageArgs a;
     a.rtab = h->rtab;
@@ -285,29 +285,38 @@ teuk_status teuk_step(teuk_solver* h, int64_t nsteps)
     a.nr = c.nr;
     a.nth = c.ntheta;
     a.nstrips = h->nstrips;
-    a.nchunks = h->nchunks;
-    a.rows = h->rows;
+    a.grid = h->grid[0];
     a.inv6dx = 1.0 / (6.0 * h->dx);
     a.ih1 = 1.0 / (2.0 * h->dth);
     a.ih2 = 1.0 / (h->dth * h->dth);
     a.dt = h->dt;
+    a.ca = 0.0;
+    a.cb = 1.0;
     a.eps = c.weno_eps;
     a.parity = ((c.m + c.s) % 2 != 0) ? -1.0 : 1.0;
+    a.uk = a.un = h->u[0];
+    a.out = h->u[1];
+    return a;
+}
+
+teuk_status teuk_step(teuk_solver* h, int64_t nsteps)
+{
+    if (!h) return fail(nullptr, TEUK_ERR_INVALID_ARG, "solver is NULL");
+    if (nsteps < 0) return fail(h, TEUK_ERR_INVALID_ARG, "nsteps must be >= 0");
+    if (!h->have_init) return fail(h, TEUK_ERR_STATE, "teuk_step before teuk_set_initial");
+    const teuk_config& c = h->cfg;
+    StageArgs a = stage_args(h);
     for (int64_t n = 0; n < nsteps; ++n) {
         // u1 = u + dt F(u)
-        a.uk = h->u[0]; a.un = h->u[0]; a.out = h->u[1]; a.ca = 0.0; a.cb = 1.0;
+        a.uk = h->u[0]; a.un = h->u[0]; a.out = h->u[1]; a.ca = 0.0; a.cb = 1.0; a.grid = h->grid[0];
         int e = launch_stage(a, 1, c.weight_prec, h->stream);
         // u2 = 3/4 u + 1/4 (u1 + dt F(u1))
-        if (!e) { a.uk = h->u[1]; a.un = h->u[0]; a.out = h->u[2]; a.ca = 0.75; a.cb = 0.25;
+        if (!e) { a.uk = h->u[1]; a.un = h->u[0]; a.out = h->u[2]; a.ca = 0.75; a.cb = 0.25; a.grid = h->grid[1];
                   e = launch_stage(a, 2, c.weight_prec, h->stream); }
         // u = 1/3 u + 2/3 (u2 + dt F(u2)), in place (u^n is read only at the own point)
-        if (!e) { a.uk = h->u[2]; a.un = h->u[0]; a.out = h->u[0]; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0;
+        if (!e) { a.uk = h->u[2]; a.un = h->u[0]; a.out = h->u[0]; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0; a.grid = h->grid[1];
                   e = launch_stage(a, 3, c.weight_prec, h->stream); }
-        if (e) {
-            if (e == (int)hipErrorInvalidValue && c.weight_prec != TEUK_W_FP64)
-                return fail(h, TEUK_ERR_UNSUPPORTED, "weight precision not built");
-            return hip_fail(h, e, "stage launch");
-        }
+        if (e) return hip_fail(h, e, "stage launch");
         ++h->steps;
         if (c.extract_every > 0 && h->steps % c.extract_every == 0) {
             teuk_status st = record_sample(h);
@@ -330,11 +339,12 @@ teuk_status teuk_extract(teuk_solver* h, int32_t what, double* out, size_t capac
     case TEUK_X_WAVEFORM: need = (size_t)nsamp * c.ntheta * 2; break;
     case TEUK_X_TIMES: need = (size_t)nsamp; break;
     case TEUK_X_COEFFS: need = (size_t)TEUK_NCOEF * h->plane; break;
+    case TEUK_X_RHS: need = 4 * (size_t)h->plane; break;
     default: return fail(h, TEUK_ERR_INVALID_ARG, "unknown extract kind");
     }
     if (capacity < need) return fail(h, TEUK_ERR_CAPACITY, "output holds " + std::to_string(capacity) +
                                                               " doubles, need " + std::to_string(need));
-    if ((what == TEUK_X_STATE || what == TEUK_X_WAVEFORM) && !h->have_init)
+    if ((what == TEUK_X_STATE || what == TEUK_X_WAVEFORM || what == TEUK_X_RHS) && !h->have_init)
         return fail(h, TEUK_ERR_STATE, "no state: call teuk_set_initial first");
     int e = 0;
     teuk_status guard = TEUK_OK;
@@ -350,6 +360,12 @@ teuk_status teuk_extract(teuk_solver* h, int32_t what, double* out, size_t capac
             e = (int)hipMemcpyAsync(out + i * per, h->wave + slot * per, per * sizeof(double),
                                     hipMemcpyDeviceToHost, h->stream);
         }
+    } else if (what == TEUK_X_RHS) {
+        // F(u^n) by the stage kernel itself, written into the u^(1) buffer
+        // (scratch between steps), then copied out
+        StageArgs a = stage_args(h);
+        e = launch_stage(a, 0, h->cfg.weight_prec, h->stream);
+        if (!e) e = (int)hipMemcpyAsync(out, h->u[1], need * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     } else if (what == TEUK_X_TIMES) {
         const long long first = h->samples - nsamp;
         for (long long i = 0; i < nsamp; ++i) out[i] = (double)((first + i) * (long long)c.extract_every) * h->dt;
@@ -378,7 +394,7 @@ teuk_status teuk_info(teuk_solver* h, teuk_info_t* info)
     info->steps = h->steps;
     info->samples = h->samples;
     info->j_extract = h->j_e;
-    info->rows_per_block = h->rows;
+    info->workgroups = h->grid[1];
     info->dt_bound = h->dt_bound;
     return TEUK_OK;
 }

@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/teuk.h"
+#include "teuk.h"
 
 namespace teuk {
 
@@ -30,14 +30,20 @@ struct StageArgs {
     const double* ttab;    // polar table [kNTT][nth]
     long long plane;       // nth * nr
     int nr, nth;
-    int nstrips, nchunks, rows;
+    int nstrips;           // radial strips of kStripPoints
+    int grid;              // workgroups launched (balanced persistent grid)
     double inv6dx;         // 1 / (6 dx): candidate fluxes are carried times 6
     double ih1, ih2;       // 1/(2 dtheta), 1/dtheta^2
     double dt, ca, cb;     // out = ca un + cb (uk + dt F)
     double eps, parity;    // WENO epsilon, (-1)^(m+s)
 };
 
+// Resident workgroup count of a stage-kernel instantiation on the current
+// device (0 if the weight precision is not built).
+int stage_grid(int weight_prec, bool first);
+
 // Launchers (all asynchronous on `stream`; they return the hipError_t as int).
+// stage: 1 = first SSP stage, 2/3 = later stages, 0 = write F(u) only.
 int launch_stage(const StageArgs& a, int stage, int weight_prec, void* stream);
 int launch_dt_bound(const double* rtab, const double* ttab, int nr, int nth, double dx, double dth,
                     unsigned long long* cell, void* stream);

@@ -35,6 +35,11 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kRow = kWave + 5;   // staged positions j0-3 .. j0+65
 
+// What a stage launch writes.
+constexpr int kStageFirst = 0;    // out = u + dt F(u)
+constexpr int kStageLater = 1;    // out = ca u^n + cb (u^(k) + dt F(u^(k)))
+constexpr int kRhsOnly = 2;       // out = F(u)
+
 // 1/x to full FP64 precision: hardware estimate refined by two Newton steps.
 __device__ __forceinline__ double rcp64(double x)
 {
@@ -97,78 +102,250 @@ struct Weno<TEUK_W_FP64> {
     }
 };
 
+// ---------------------------------------------------------------- reduced-precision weights
+// Sec. 3.1.3: the smoothness indicators and nonlinear weights are computed in a
+// lower precision and the weights are made to sum to one in FP64.  Here the six
+// stencil differences of IS_k are taken in FP64 (differencing first keeps the
+// information the low format would lose to cancellation), converted, and
+// IS_k, alpha_k and omega_0, omega_1 are formed in the low format; omega_2 is
+// the FP64 complement and the candidate fluxes stay FP64.
+//
+// The weights use the ratio form
+//     alpha'_k = d_k (tau_min / tau_k)^2,   tau_k = eps + IS_k,
+// which equals alpha_k tau_min^2 (so omega is unchanged in exact arithmetic)
+// and keeps every intermediate in [0, 1] whatever the magnitude of the data.
+// rho_k = 1 where tau_k equals tau_min (also when both are zero).
+
+// Arithmetic in the low format: every result rounded to it.
+struct LowF32 {
+    typedef float T;
+    __device__ static T cvt(float x) { return x; }
+    __device__ static T rcp(T x) { return __builtin_amdgcn_rcpf(x); }
+    __device__ static float f(T x) { return x; }
+};
+struct LowF16 {
+    typedef _Float16 T;
+    __device__ static T cvt(float x) { return (_Float16)x; }
+    __device__ static T rcp(T x) { return (_Float16)1.0 / x; }
+    __device__ static float f(T x) { return (float)x; }
+};
+// BF16 arithmetic: compute in FP32 and round each result to BF16 (round to
+// nearest even).  FP32 carries more than 2p+2 bits for p = 8, so this equals a
+// correctly rounded BF16 operation for +, -, * and /.
+struct Bf16Val {
+    float v;
+};
+__device__ __forceinline__ float bf16_round(float x)
+{
+    return (float)(__bf16)x;
+}
+__device__ __forceinline__ Bf16Val operator+(Bf16Val a, Bf16Val b) { return {bf16_round(a.v + b.v)}; }
+__device__ __forceinline__ Bf16Val operator*(Bf16Val a, Bf16Val b) { return {bf16_round(a.v * b.v)}; }
+__device__ __forceinline__ bool operator<(Bf16Val a, Bf16Val b) { return a.v < b.v; }
+__device__ __forceinline__ bool operator==(Bf16Val a, Bf16Val b) { return a.v == b.v; }
+struct LowBF16 {
+    typedef Bf16Val T;
+    __device__ static T cvt(float x) { return {bf16_round(x)}; }
+    __device__ static T rcp(T x) { return {bf16_round(1.0f / x.v)}; }
+    __device__ static float f(T x) { return x.v; }
+};
+
+template <class L, bool kScale>
+__device__ __forceinline__ void low_weights(double d0, double d1, double d2, double e0, double e1, double e2,
+                                            double eps, double* w0, double* w1)
+{
+    typedef typename L::T T;
+    float fd0 = (float)d0, fd1 = (float)d1, fd2 = (float)d2;
+    float fe0 = (float)e0, fe1 = (float)e1, fe2 = (float)e2;
+    float feps = (float)eps;
+    if (kScale) {
+        // Scale by an exact power of two so that the largest of the differences
+        // and sqrt(eps) is O(1): IS' = sigma^2 IS and eps' = sigma^2 eps leave the
+        // weights unchanged and keep a 16-bit format away from overflow.
+        float m = fmaxf(fmaxf(fmaxf(fabsf(fd0), fabsf(fd1)), fmaxf(fabsf(fd2), fabsf(fe0))),
+                        fmaxf(fmaxf(fabsf(fe1), fabsf(fe2)), sqrtf(feps)));
+        const int ex = __builtin_amdgcn_frexp_expf(m);
+        fd0 = ldexpf(fd0, -ex); fd1 = ldexpf(fd1, -ex); fd2 = ldexpf(fd2, -ex);
+        fe0 = ldexpf(fe0, -ex); fe1 = ldexpf(fe1, -ex); fe2 = ldexpf(fe2, -ex);
+        feps = ldexpf(feps, -2 * ex);
+    }
+    const T c1312 = L::cvt(13.0f / 12.0f), c14 = L::cvt(0.25f);
+    const T D0 = L::cvt(fd0), D1 = L::cvt(fd1), D2 = L::cvt(fd2);
+    const T E0 = L::cvt(fe0), E1 = L::cvt(fe1), E2 = L::cvt(fe2);
+    const T ep = L::cvt(feps);
+    const T t0 = ep + (c1312 * (D0 * D0) + c14 * (E0 * E0));
+    const T t1 = ep + (c1312 * (D1 * D1) + c14 * (E1 * E1));
+    const T t2 = ep + (c1312 * (D2 * D2) + c14 * (E2 * E2));
+    T tm = t0 < t1 ? t0 : t1;
+    tm = t2 < tm ? t2 : tm;
+    const T one = L::cvt(1.0f);
+    const T r0 = t0 == tm ? one : tm * L::rcp(t0);
+    const T r1 = t1 == tm ? one : tm * L::rcp(t1);
+    const T r2 = t2 == tm ? one : tm * L::rcp(t2);
+    const T a0 = L::cvt(0.1f) * (r0 * r0);
+    const T a1 = L::cvt(0.6f) * (r1 * r1);
+    const T a2 = L::cvt(0.3f) * (r2 * r2);
+    const T inv = L::rcp(a0 + a1 + a2);
+    *w0 = (double)L::f(a0 * inv);
+    *w1 = (double)L::f(a1 * inv);
+}
+
+template <class L, bool kScale>
+struct WenoLow {
+    __device__ __forceinline__ static double flux6(double v0, double v1, double v2, double v3, double v4,
+                                                    double eps)
+    {
+        const double d0 = v0 - 2.0 * v1 + v2;
+        const double d1 = v1 - 2.0 * v2 + v3;
+        const double d2 = v2 - 2.0 * v3 + v4;
+        const double e0 = v0 - 4.0 * v1 + 3.0 * v2;
+        const double e1 = v1 - v3;
+        const double e2 = 3.0 * v2 - 4.0 * v3 + v4;
+        double w0, w1;
+        low_weights<L, kScale>(d0, d1, d2, e0, e1, e2, eps, &w0, &w1);
+        const double q0 = 2.0 * v0 - 7.0 * v1 + 11.0 * v2;
+        const double q1 = -v1 + 5.0 * v2 + 2.0 * v3;
+        const double q2 = 2.0 * v2 + 5.0 * v3 - v4;
+        return q2 + w0 * (q0 - q2) + w1 * (q1 - q2);
+    }
+};
+
+template <>
+struct Weno<TEUK_W_FP32> : WenoLow<LowF32, false> {};
+template <>
+struct Weno<TEUK_W_FP16> : WenoLow<LowF16, true> {};
+template <>
+struct Weno<TEUK_W_BF16> : WenoLow<LowBF16, true> {};
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-template <int WP, bool kFirstStage>
-__global__ __launch_bounds__(kWave) void stage_kernel(StageArgs A)
+// Barrier that orders LDS only.  __syncthreads() is also a workgroup fence on
+// global memory, which makes every wave drain its outstanding global loads
+// (s_waitcnt vmcnt(0)) before the barrier: that would serialise the row
+// prefetch below with the arithmetic it is meant to overlap.
+__device__ __forceinline__ void lds_sync()
 {
-    __shared__ double s[4][kRow];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Load a double at a byte offset from a uniform base: the 32-bit offset lets
+// the compiler use the scalar-base addressing form (no 64-bit address math).
+__device__ __forceinline__ double ldb(const double* base, unsigned off)
+{
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + off);
+}
+__device__ __forceinline__ void stb(double* base, unsigned off, double v)
+{
+    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + off) = v;
+}
+
+// One radial strip [j0, j0 + 63) marched over theta rows [k0, k1).  Rows are
+// staged in a two-row LDS ring: while row k is computed from LDS, the loads of
+// row k+2 and of u^n at row k are already in flight and are consumed at the
+// end of the iteration, so each wave always has the next rows' memory traffic
+// overlapping its arithmetic.
+template <int WP, int kMode>
+__device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][kRow], int strip, int k0, int k1)
+{
     const int l = threadIdx.x;
-
-    // XCD-aware tile order: block ids are dealt round-robin to the 8 XCDs, so
-    // give XCD x the contiguous tile range [x q + min(x, r), ...).
-    const int total = A.nstrips * A.nchunks;
-    const int bid = blockIdx.x;
-    const int xcd = bid & 7, loc = bid >> 3;
-    const int q8 = total >> 3, r8 = total & 7;
-    const int tile = xcd * q8 + (xcd < r8 ? xcd : r8) + loc;
-    const int strip = tile / A.nchunks;
-    const int chunk = tile - strip * A.nchunks;
+    const int nr = A.nr, nth = A.nth;
+    const long long P = A.plane;
     const int j0 = strip * kStripPoints;
-    const int k0 = chunk * A.rows;
-    const int k1 = min(k0 + A.rows, A.nth);
-
-    const int nr = A.nr;
     const int j = j0 + l;
     const bool active = (l < kStripPoints) && (j < nr);
     const int jc = min(j, nr - 1);
-    const int pa = clampi(j0 - 3 + l, 0, nr - 1);    // LDS index l
-    const int pb = clampi(j0 + 61 + l, 0, nr - 1);   // LDS index 64 + l, l < 5
+    // byte offsets within a row (rows are < 2^27 doubles, so these fit in 32 bits)
+    const unsigned oa = (unsigned)clampi(j0 - 3 + l, 0, nr - 1) * 8u;    // LDS index l
+    const unsigned ob = (unsigned)clampi(j0 + 61 + l, 0, nr - 1) * 8u;   // LDS index 64 + l, l < 5
+    const unsigned oc = (unsigned)jc * 8u;                                 // own point
+    const bool halo = l < 5;
+    const double* __restrict__ ukp[4] = {A.uk, A.uk + P, A.uk + 2 * P, A.uk + 3 * P};
+    const double* unp[4] = {A.un, A.un + P, A.un + 2 * P, A.un + 3 * P};   // read in kStageLater only
+    double* outp[4] = {A.out, A.out + P, A.out + 2 * P, A.out + 3 * P};
 
     double rt[kNRT];
 #pragma unroll
-    for (int i = 0; i < kNRT; ++i) rt[i] = A.rtab[(size_t)i * nr + jc];
+    for (int i = 0; i < kNRT; ++i) rt[i] = ldb(A.rtab + (size_t)i * nr, oc);
+    // The polar table is read-only for the whole launch: reading it through the
+    // constant address space makes its (uniform) loads scalar.
+    const __attribute__((address_space(4))) double* tt =
+        (const __attribute__((address_space(4))) double*)A.ttab;
 
-    const long long P = A.plane;
-    const double* __restrict__ uk = A.uk;
-    const double* un = A.un;
-    double* out = A.out;
-
-    // Phi at the own point on the row below the first row of the chunk.
+    // Phi at the own point on the row below k0 (pole ghost at k0 = 0).
     double prvR, prvI;
     if (k0 > 0) {
-        prvR = uk[(size_t)(k0 - 1) * nr + jc];
-        prvI = uk[P + (size_t)(k0 - 1) * nr + jc];
+        prvR = ldb(ukp[0] + (size_t)(k0 - 1) * nr, oc);
+        prvI = ldb(ukp[1] + (size_t)(k0 - 1) * nr, oc);
     } else {
-        prvR = A.parity * uk[jc];
-        prvI = A.parity * uk[P + jc];
+        prvR = A.parity * ldb(ukp[0], oc);
+        prvI = A.parity * ldb(ukp[1], oc);
+    }
+
+    // Rows staged: k0 .. klast (klast = k1, the theta neighbour of the last
+    // computed row, unless k1 is past the pole).
+    const int klast = min(k1, nth - 1);
+    double xa[4], xb[4];
+    auto load_row = [&](int k) {
+        const size_t row = (size_t)k * nr;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) xa[p] = ldb(ukp[p] + row, oa);
+        if (halo) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) xb[p] = ldb(ukp[p] + row, ob);
+        }
+    };
+    auto store_row = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) s[buf][p][l] = xa[p];
+        if (halo) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) s[buf][p][kWave + l] = xb[p];
+        }
+    };
+    load_row(k0);
+    store_row(0);
+    if (k0 + 1 <= klast) {
+        load_row(k0 + 1);
+        store_row(1);
     }
 
     for (int k = k0; k < k1; ++k) {
+        const int b = (k - k0) & 1;
         const size_t row = (size_t)k * nr;
-#pragma unroll
-        for (int p = 0; p < 4; ++p) s[p][l] = uk[p * P + row + pa];
-        if (l < 5) {
-#pragma unroll
-            for (int p = 0; p < 4; ++p) s[p][kWave + l] = uk[p * P + row + pb];
+        // polar factors of the row: uniform, read before the vector loads are
+        // queued so that waiting for them never waits for the prefetch
+        const double sn2 = tt[kSn2 * nth + k];
+        const double cs = tt[kCs * nth + k];
+        const double cot = tt[kCot * nth + k];
+        const double th = tt[kTh * nth + k];
+        // next rows' traffic, consumed at the end of this iteration
+        const bool pre = k + 2 <= klast;
+        if (pre) load_row(k + 2);
+        double n0, n1, n2, n3;
+        if (kMode == kStageLater) {
+            n0 = ldb(unp[0] + row, oc);
+            n1 = ldb(unp[1] + row, oc);
+            n2 = ldb(unp[2] + row, oc);
+            n3 = ldb(unp[3] + row, oc);
         }
-        double nxtR, nxtI;
-        if (k + 1 < A.nth) {
-            nxtR = uk[row + nr + jc];
-            nxtI = uk[P + row + nr + jc];
-        } else {
-            nxtR = A.parity * uk[row + jc];
-            nxtI = A.parity * uk[P + row + jc];
-        }
-        __syncthreads();
+        lds_sync();
 
-        const double fR = Weno<WP>::flux6(s[0][l], s[0][l + 1], s[0][l + 2], s[0][l + 3], s[0][l + 4], A.eps);
-        const double fI = Weno<WP>::flux6(s[1][l], s[1][l + 1], s[1][l + 2], s[1][l + 3], s[1][l + 4], A.eps);
-        const double gR = Weno<WP>::flux6(s[2][l + 5], s[2][l + 4], s[2][l + 3], s[2][l + 2], s[2][l + 1], A.eps);
-        const double gI = Weno<WP>::flux6(s[3][l + 5], s[3][l + 4], s[3][l + 3], s[3][l + 2], s[3][l + 1], A.eps);
-        const double phR = s[0][l + 3], phI = s[1][l + 3];
-        const double piR = s[2][l + 3], piI = s[3][l + 3];
-        __syncthreads();
+        const double fR = Weno<WP>::flux6(s[b][0][l], s[b][0][l + 1], s[b][0][l + 2], s[b][0][l + 3], s[b][0][l + 4], A.eps);
+        const double fI = Weno<WP>::flux6(s[b][1][l], s[b][1][l + 1], s[b][1][l + 2], s[b][1][l + 3], s[b][1][l + 4], A.eps);
+        const double gR = Weno<WP>::flux6(s[b][2][l + 5], s[b][2][l + 4], s[b][2][l + 3], s[b][2][l + 2], s[b][2][l + 1], A.eps);
+        const double gI = Weno<WP>::flux6(s[b][3][l + 5], s[b][3][l + 4], s[b][3][l + 3], s[b][3][l + 2], s[b][3][l + 1], A.eps);
+        const double phR = s[b][0][l + 3], phI = s[b][1][l + 3];
+        const double piR = s[b][2][l + 3], piI = s[b][3][l + 3];
+        double nxtR, nxtI;
+        if (k + 1 < nth) {
+            nxtR = s[b ^ 1][0][l + 3];
+            nxtI = s[b ^ 1][1][l + 3];
+        } else {
+            nxtR = A.parity * phR;
+            nxtI = A.parity * phI;
+        }
 
         const double fR1 = __shfl_down(fR, 1);
         const double fI1 = __shfl_down(fI, 1);
@@ -181,10 +358,6 @@ __global__ __launch_bounds__(kWave) void stage_kernel(StageArgs A)
             const double dPiR = (gR1 - gR) * A.inv6dx;
             const double dPiI = (gI1 - gI) * A.inv6dx;
 
-            const double sn2 = A.ttab[kSn2 * A.nth + k];
-            const double cs = A.ttab[kCs * A.nth + k];
-            const double cot = A.ttab[kCot * A.nth + k];
-            const double th = A.ttab[kTh * A.nth + k];
             const PointCoef c = point_coef(rt, sn2, cs, cot, th, rsq64(sigma2(rt, sn2)));
 
             const double d1R = (nxtR - prvR) * A.ih1, d1I = (nxtI - prvI) * A.ih1;
@@ -200,22 +373,57 @@ __global__ __launch_bounds__(kWave) void stage_kernel(StageArgs A)
             const double FpiI = c.b * dPiI - (c.m3r * dPhI + c.m3i * dPhR) + (c.btr * piI + c.bti * piR) +
                                 c.ath * d2I + c.bth * d1I + (c.cr * phI + c.ci * phR);
 
-            const size_t o = row + j;
-            if (kFirstStage) {
-                out[o] = phR + A.dt * FphR;
-                out[P + o] = phI + A.dt * FphI;
-                out[2 * P + o] = piR + A.dt * FpiR;
-                out[3 * P + o] = piI + A.dt * FpiI;
+            if (kMode == kRhsOnly) {
+                stb(outp[0] + row, oc, FphR);
+                stb(outp[1] + row, oc, FphI);
+                stb(outp[2] + row, oc, FpiR);
+                stb(outp[3] + row, oc, FpiI);
+            } else if (kMode == kStageFirst) {
+                stb(outp[0] + row, oc, phR + A.dt * FphR);
+                stb(outp[1] + row, oc, phI + A.dt * FphI);
+                stb(outp[2] + row, oc, piR + A.dt * FpiR);
+                stb(outp[3] + row, oc, piI + A.dt * FpiI);
             } else {
-                const double u0 = un[o], u1 = un[P + o], u2 = un[2 * P + o], u3 = un[3 * P + o];
-                out[o] = A.ca * u0 + A.cb * (phR + A.dt * FphR);
-                out[P + o] = A.ca * u1 + A.cb * (phI + A.dt * FphI);
-                out[2 * P + o] = A.ca * u2 + A.cb * (piR + A.dt * FpiR);
-                out[3 * P + o] = A.ca * u3 + A.cb * (piI + A.dt * FpiI);
+                stb(outp[0] + row, oc, A.ca * n0 + A.cb * (phR + A.dt * FphR));
+                stb(outp[1] + row, oc, A.ca * n1 + A.cb * (phI + A.dt * FphI));
+                stb(outp[2] + row, oc, A.ca * n2 + A.cb * (piR + A.dt * FpiR));
+                stb(outp[3] + row, oc, A.ca * n3 + A.cb * (piI + A.dt * FpiI));
             }
         }
         prvR = phR;
         prvI = phI;
+        lds_sync();               // every lane is done reading s[b] (row k)
+        if (pre) store_row(b);    // row k+2 takes its place
+    }
+}
+
+// Persistent, balanced launch: the grid is the number of workgroups the GPU
+// holds at once.  The work is the list of (strip, theta row) units in
+// strip-major order; workgroup `rank` takes the contiguous range
+// [total*rank/G, total*(rank+1)/G), so every workgroup does the same number of
+// rows (to within one) and none waits for a second round.  Ranks are dealt so
+// that each XCD (which receives every eighth workgroup id) owns a contiguous
+// block of ranges: its concurrently running rows are neighbours in theta and
+// share their boundary rows in that XCD's L2.
+template <int WP, int kMode>
+__global__ __launch_bounds__(kWave) void stage_kernel(StageArgs A)
+{
+    __shared__ double s[2][4][kRow];
+    const int G = (int)gridDim.x;
+    const int bid = (int)blockIdx.x;
+    const int xcd = bid & 7, loc = bid >> 3;
+    const int q8 = G >> 3, r8 = G & 7;
+    const int rank = xcd * q8 + (xcd < r8 ? xcd : r8) + loc;
+    const long long total = (long long)A.nstrips * A.nth;
+    long long u = total * rank / G;
+    const long long u_end = total * (rank + 1) / G;
+    while (u < u_end) {
+        const int strip = (int)(u / A.nth);
+        const int k0 = (int)(u - (long long)strip * A.nth);
+        const long long left = u_end - u;
+        const int k1 = (int)min((long long)A.nth, (long long)k0 + left);
+        march_strip<WP, kMode>(A, s, strip, k0, k1);
+        u += k1 - k0;
     }
 }
 
@@ -296,21 +504,54 @@ __global__ __launch_bounds__(256) void coef_dump_kernel(const double* __restrict
 
 }  // namespace
 
+int stage_grid(int weight_prec, bool first)
+{
+    // resident workgroups of one stage-kernel instantiation on the current device
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    hipError_t e = hipErrorInvalidValue;
+#define TEUK_OCC(W)                                                                                   \
+    case W:                                                                                          \
+        e = first ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<W, kStageFirst>, kWave, 0) \
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<W, kStageLater>, kWave, 0); \
+        break;
+    switch (weight_prec) {
+        TEUK_OCC(TEUK_W_FP64)
+        TEUK_OCC(TEUK_W_FP32)
+        TEUK_OCC(TEUK_W_FP16)
+        TEUK_OCC(TEUK_W_BF16)
+    default:
+        break;
+    }
+#undef TEUK_OCC
+    if (e != hipSuccess || per_cu < 1) return 0;
+    return cus * per_cu;
+}
+
 int launch_stage(const StageArgs& a, int stage, int weight_prec, void* stream)
 {
-    const dim3 grid((unsigned)(a.nstrips * a.nchunks)), block(kWave);
+    const dim3 grid((unsigned)a.grid), block(kWave);
     hipStream_t st = (hipStream_t)stream;
     (void)hipGetLastError();   // report only what this launch does
-    switch (weight_prec) {
-    case TEUK_W_FP64:
-        if (stage == 1)
-            hipLaunchKernelGGL((stage_kernel<TEUK_W_FP64, true>), grid, block, 0, st, a);
-        else
-            hipLaunchKernelGGL((stage_kernel<TEUK_W_FP64, false>), grid, block, 0, st, a);
+#define TEUK_LAUNCH(W)                                                                  \
+    case W:                                                                            \
+        if (stage == 1)                                                                \
+            hipLaunchKernelGGL((stage_kernel<W, kStageFirst>), grid, block, 0, st, a); \
+        else if (stage == 0)                                                           \
+            hipLaunchKernelGGL((stage_kernel<W, kRhsOnly>), grid, block, 0, st, a);    \
+        else                                                                           \
+            hipLaunchKernelGGL((stage_kernel<W, kStageLater>), grid, block, 0, st, a); \
         break;
+    switch (weight_prec) {
+        TEUK_LAUNCH(TEUK_W_FP64)
+        TEUK_LAUNCH(TEUK_W_FP32)
+        TEUK_LAUNCH(TEUK_W_FP16)
+        TEUK_LAUNCH(TEUK_W_BF16)
     default:
         return (int)hipErrorInvalidValue;
     }
+#undef TEUK_LAUNCH
     return (int)hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ int main(void) {
   printf("teuk_config %zu\\n", sizeof(teuk_config));
   printf("teuk_device_ctx %zu\\n", sizeof(teuk_device_ctx));
   printf("teuk_info_t %zu\\n", sizeof(teuk_info_t));
-  F(teuk_config, M) F(teuk_config, a) F(teuk_config, x_extract) F(teuk_config, rows_per_block)
+  F(teuk_config, M) F(teuk_config, a) F(teuk_config, x_extract) F(teuk_config, workgroups)
   F(teuk_info_t, samples) F(teuk_info_t, dt_bound) F(teuk_device_ctx, workspace_bytes)
   return 0; }
 """)

@@ -82,6 +82,20 @@ def test_random_state_steps(nr, nth, s, m, a):
         assert_parity(got, ref, what=(nr, nth, n))
 
 
+@pytest.mark.parametrize("nr,nth,s,m,a", RAGGED)
+def test_rhs_random_state(nr, nth, s, m, a):
+    # F(u) itself (TEUK_X_RHS evaluates it with the stage kernel) against the oracle
+    say("case rhs", nr, nth, s, m, a)
+    prob = S.Problem(s, m, a, nr, nth, -30.0, 50.0)
+    o = S.TeukOracle(prob)
+    u0 = W.random_state(nr, nth, seed=nr * 7 + nth)
+    with T.Solver(cfg_for(prob, 0.01)) as sv:
+        sv.set_initial(u0)
+        F = sv.rhs()
+        assert np.array_equal(sv.state(), u0)          # the state is untouched
+    assert_parity(F, o.rhs(u0), what=("rhs", nr, nth))
+
+
 def test_c1_workload_full_run():
     wl = W.C1
     say("case C1 full", wl.name)
@@ -127,7 +141,7 @@ def test_launch_shape_invariance():
     o = S.TeukOracle(prob)
     dt = 0.4 * o.dt_bound(1.0)
     u0 = W.random_state(300, 37, seed=5, smooth=True)
-    outs = [run_gpu(cfg_for(prob, dt, rows_per_block=r), u0, 4) for r in (1, 3, 8, 37, 64)]
+    outs = [run_gpu(cfg_for(prob, dt, workgroups=r), u0, 4) for r in (1, 3, 8, 37, 64)]
     for g in outs[1:]:
         assert np.array_equal(g, outs[0])
 
