@@ -29,7 +29,7 @@ struct teuk_solver {
     double dx = 0, dth = 0, dt = 0, dt_bound = 0;
     int j_e = 0;
     int nstrips = 0;
-    int grid[2] = {0, 0};                           // workgroups: stage 1, stages 2-3
+    int segs[2] = {0, 0};                           // theta segments per strip: stage 1, stages 2-3
     long long plane = 0;
     long long steps = 0, samples = 0;
     bool have_init = false;
@@ -87,16 +87,18 @@ bool validate(const teuk_config* c, std::string& err)
     return true;
 }
 
-// Workgroups of the persistent stage grid: the resident capacity of the
-// kernel on this device (or the caller's count), never more than the number
-// of (strip, theta row) units.
-int pick_grid(const teuk_config& c, int nstrips, int weight_prec, bool first)
+// Theta segments per radial strip: as many as fit the workgroups the GPU holds
+// at once (or the caller's workgroup count), an even number when more than
+// one so that neighbouring segments pair up, and at most one per theta row.
+int pick_segs(const teuk_config& c, int nstrips, int weight_prec, bool first)
 {
-    const long long units = (long long)nstrips * c.ntheta;
-    long long g = c.workgroups > 0 ? c.workgroups : stage_grid(weight_prec, first);
-    if (g <= 0) return 0;
-    if (g > units) g = units;
-    return (int)g;
+    long long cap = c.workgroups > 0 ? c.workgroups : stage_grid(weight_prec, first);
+    if (cap <= 0) return 0;
+    long long segs = cap / nstrips;
+    if (segs > c.ntheta) segs = c.ntheta;
+    if (segs > 1) segs &= ~1LL;
+    if (segs < 1) segs = 1;
+    return (int)segs;
 }
 
 teuk_status fail(teuk_solver* h, teuk_status st, const std::string& msg)
@@ -217,9 +219,10 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     h->dx = (cfg->x_max - cfg->x_min) / (cfg->nr - 1);
     h->dth = M_PI / cfg->ntheta;
     h->nstrips = (cfg->nr + kStripPoints - 1) / kStripPoints;
-    h->grid[0] = pick_grid(*cfg, h->nstrips, cfg->weight_prec, true);
-    h->grid[1] = pick_grid(*cfg, h->nstrips, cfg->weight_prec, false);
-    if (h->grid[0] <= 0 || h->grid[1] <= 0) {
+    h->segs[0] = pick_segs(*cfg, h->nstrips, cfg->weight_prec, true);
+    h->segs[1] = pick_segs(*cfg, h->nstrips, cfg->weight_prec, false);
+    if (h->segs[0] <= 0 || h->segs[1] <= 0 || (long long)h->nstrips * h->segs[0] > (1LL << 31) - 1 ||
+        (long long)h->nstrips * h->segs[1] > (1LL << 31) - 1) {
         free_solver(h);
         return fail(nullptr, TEUK_ERR_UNSUPPORTED, "weight precision not built (or occupancy query failed)");
     }
@@ -285,7 +288,8 @@ static StageArgs stage_args(const teuk_solver* h)
     a.nr = c.nr;
     a.nth = c.ntheta;
     a.nstrips = h->nstrips;
-    a.grid = h->grid[0];
+    a.segs = h->segs[0];
+    a.grid = h->nstrips * h->segs[0];
     a.inv6dx = 1.0 / (6.0 * h->dx);
     a.ih1 = 1.0 / (2.0 * h->dth);
     a.ih2 = 1.0 / (h->dth * h->dth);
@@ -308,13 +312,13 @@ teuk_status teuk_step(teuk_solver* h, int64_t nsteps)
     StageArgs a = stage_args(h);
     for (int64_t n = 0; n < nsteps; ++n) {
         // u1 = u + dt F(u)
-        a.uk = h->u[0]; a.un = h->u[0]; a.out = h->u[1]; a.ca = 0.0; a.cb = 1.0; a.grid = h->grid[0];
+        a.uk = h->u[0]; a.un = h->u[0]; a.out = h->u[1]; a.ca = 0.0; a.cb = 1.0; a.segs = h->segs[0]; a.grid = h->nstrips * h->segs[0];
         int e = launch_stage(a, 1, c.weight_prec, h->stream);
         // u2 = 3/4 u + 1/4 (u1 + dt F(u1))
-        if (!e) { a.uk = h->u[1]; a.un = h->u[0]; a.out = h->u[2]; a.ca = 0.75; a.cb = 0.25; a.grid = h->grid[1];
+        if (!e) { a.uk = h->u[1]; a.un = h->u[0]; a.out = h->u[2]; a.ca = 0.75; a.cb = 0.25; a.segs = h->segs[1]; a.grid = h->nstrips * h->segs[1];
                   e = launch_stage(a, 2, c.weight_prec, h->stream); }
         // u = 1/3 u + 2/3 (u2 + dt F(u2)), in place (u^n is read only at the own point)
-        if (!e) { a.uk = h->u[2]; a.un = h->u[0]; a.out = h->u[0]; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0; a.grid = h->grid[1];
+        if (!e) { a.uk = h->u[2]; a.un = h->u[0]; a.out = h->u[0]; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0; a.segs = h->segs[1]; a.grid = h->nstrips * h->segs[1];
                   e = launch_stage(a, 3, c.weight_prec, h->stream); }
         if (e) return hip_fail(h, e, "stage launch");
         ++h->steps;
@@ -394,7 +398,7 @@ teuk_status teuk_info(teuk_solver* h, teuk_info_t* info)
     info->steps = h->steps;
     info->samples = h->samples;
     info->j_extract = h->j_e;
-    info->workgroups = h->grid[1];
+    info->workgroups = h->nstrips * h->segs[1];
     info->dt_bound = h->dt_bound;
     return TEUK_OK;
 }

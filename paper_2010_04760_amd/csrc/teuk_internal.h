@@ -31,7 +31,8 @@ struct StageArgs {
     long long plane;       // nth * nr
     int nr, nth;
     int nstrips;           // radial strips of kStripPoints
-    int grid;              // workgroups launched (balanced persistent grid)
+    int segs;              // theta segments per strip (grid = nstrips * segs)
+    int grid;              // workgroups launched
     double inv6dx;         // 1 / (6 dx): candidate fluxes are carried times 6
     double ih1, ih2;       // 1/(2 dtheta), 1/dtheta^2
     double dt, ca, cb;     // out = ca un + cb (uk + dt F)
@@ -39,7 +40,8 @@ struct StageArgs {
 };
 
 // Resident workgroup count of a stage-kernel instantiation on the current
-// device (0 if the weight precision is not built).
+// device (0 if the weight precision is not built).  The launch uses
+// nstrips * segs workgroups with segs chosen from it.
 int stage_grid(int weight_prec, bool first);
 
 // Launchers (all asynchronous on `stream`; they return the hipError_t as int).

@@ -241,13 +241,15 @@ __device__ __forceinline__ void stb(double* base, unsigned off, double v)
     *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + off) = v;
 }
 
-// One radial strip [j0, j0 + 63) marched over theta rows [k0, k1).  Rows are
-// staged in a two-row LDS ring: while row k is computed from LDS, the loads of
-// row k+2 and of u^n at row k are already in flight and are consumed at the
-// end of the iteration, so each wave always has the next rows' memory traffic
+// One radial strip [j0, j0 + 63) marched over the theta rows [k0, k1), upward
+// (dir = +1, from k0) or downward (dir = -1, from k1 - 1).  Rows are staged in
+// a two-row LDS ring: while row k is computed from LDS, the loads of row
+// k + 2 dir and of u^n at row k are already in flight and are consumed at the
+// end of the iteration, so each wave always has its next rows' memory traffic
 // overlapping its arithmetic.
 template <int WP, int kMode>
-__device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][kRow], int strip, int k0, int k1)
+__device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][kRow], int strip, int k0, int k1,
+                                            int dir)
 {
     const int l = threadIdx.x;
     const int nr = A.nr, nth = A.nth;
@@ -273,19 +275,27 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
     const __attribute__((address_space(4))) double* tt =
         (const __attribute__((address_space(4))) double*)A.ttab;
 
-    // Phi at the own point on the row below k0 (pole ghost at k0 = 0).
-    double prvR, prvI;
-    if (k0 > 0) {
-        prvR = ldb(ukp[0] + (size_t)(k0 - 1) * nr, oc);
-        prvI = ldb(ukp[1] + (size_t)(k0 - 1) * nr, oc);
-    } else {
-        prvR = A.parity * ldb(ukp[0], oc);
-        prvI = A.parity * ldb(ukp[1], oc);
+    const int n = k1 - k0;
+    const int first = dir > 0 ? k0 : k1 - 1;
+    // Phi at the own point on the row behind the first one (pole ghost past
+    // either pole).
+    double bhR, bhI;
+    {
+        const int kb = first - dir;
+        if (kb >= 0 && kb < nth) {
+            bhR = ldb(ukp[0] + (size_t)kb * nr, oc);
+            bhI = ldb(ukp[1] + (size_t)kb * nr, oc);
+        } else {
+            bhR = A.parity * ldb(ukp[0] + (size_t)first * nr, oc);
+            bhI = A.parity * ldb(ukp[1] + (size_t)first * nr, oc);
+        }
     }
 
-    // Rows staged: k0 .. klast (klast = k1, the theta neighbour of the last
-    // computed row, unless k1 is past the pole).
-    const int klast = min(k1, nth - 1);
+    // Rows staged: first + dir i for i = 0 .. nst-1, i.e. every computed row
+    // plus the one ahead of the last (its theta neighbour) unless that is past
+    // a pole.
+    const int ahead_last = first + dir * n;
+    const int nst = (ahead_last >= 0 && ahead_last < nth) ? n + 1 : n;
     double xa[4], xb[4];
     auto load_row = [&](int k) {
         const size_t row = (size_t)k * nr;
@@ -304,15 +314,16 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
             for (int p = 0; p < 4; ++p) s[buf][p][kWave + l] = xb[p];
         }
     };
-    load_row(k0);
+    load_row(first);
     store_row(0);
-    if (k0 + 1 <= klast) {
-        load_row(k0 + 1);
+    if (nst > 1) {
+        load_row(first + dir);
         store_row(1);
     }
 
-    for (int k = k0; k < k1; ++k) {
-        const int b = (k - k0) & 1;
+    for (int i = 0; i < n; ++i) {
+        const int k = first + dir * i;
+        const int b = i & 1;
         const size_t row = (size_t)k * nr;
         // polar factors of the row: uniform, read before the vector loads are
         // queued so that waiting for them never waits for the prefetch
@@ -321,8 +332,8 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
         const double cot = tt[kCot * nth + k];
         const double th = tt[kTh * nth + k];
         // next rows' traffic, consumed at the end of this iteration
-        const bool pre = k + 2 <= klast;
-        if (pre) load_row(k + 2);
+        const bool pre = i + 2 < nst;
+        if (pre) load_row(k + 2 * dir);
         double n0, n1, n2, n3;
         if (kMode == kStageLater) {
             n0 = ldb(unp[0] + row, oc);
@@ -338,13 +349,13 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
         const double gI = Weno<WP>::flux6(s[b][3][l + 5], s[b][3][l + 4], s[b][3][l + 3], s[b][3][l + 2], s[b][3][l + 1], A.eps);
         const double phR = s[b][0][l + 3], phI = s[b][1][l + 3];
         const double piR = s[b][2][l + 3], piI = s[b][3][l + 3];
-        double nxtR, nxtI;
-        if (k + 1 < nth) {
-            nxtR = s[b ^ 1][0][l + 3];
-            nxtI = s[b ^ 1][1][l + 3];
+        double ahR, ahI;   // Phi on the row ahead (k + dir)
+        if (i + 1 < nst) {
+            ahR = s[b ^ 1][0][l + 3];
+            ahI = s[b ^ 1][1][l + 3];
         } else {
-            nxtR = A.parity * phR;
-            nxtI = A.parity * phI;
+            ahR = A.parity * phR;
+            ahI = A.parity * phI;
         }
 
         const double fR1 = __shfl_down(fR, 1);
@@ -360,9 +371,12 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
 
             const PointCoef c = point_coef(rt, sn2, cs, cot, th, rsq64(sigma2(rt, sn2)));
 
-            const double d1R = (nxtR - prvR) * A.ih1, d1I = (nxtI - prvI) * A.ih1;
-            const double d2R = (nxtR - 2.0 * phR + prvR) * A.ih2;
-            const double d2I = (nxtI - 2.0 * phI + prvI) * A.ih2;
+            // rows k+1 and k-1
+            const double upR = dir > 0 ? ahR : bhR, upI = dir > 0 ? ahI : bhI;
+            const double dnR = dir > 0 ? bhR : ahR, dnI = dir > 0 ? bhI : ahI;
+            const double d1R = (upR - dnR) * A.ih1, d1I = (upI - dnI) * A.ih1;
+            const double d2R = (upR - 2.0 * phR + dnR) * A.ih2;
+            const double d2I = (upI - 2.0 * phI + dnI) * A.ih2;
 
             // d_t Phi = pi - b d_x Phi
             const double FphR = piR - c.b * dPhR;
@@ -390,21 +404,22 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
                 stb(outp[3] + row, oc, A.ca * n3 + A.cb * (piI + A.dt * FpiI));
             }
         }
-        prvR = phR;
-        prvI = phI;
+        bhR = phR;
+        bhI = phI;
         lds_sync();               // every lane is done reading s[b] (row k)
-        if (pre) store_row(b);    // row k+2 takes its place
+        if (pre) store_row(b);    // row k + 2 dir takes its place
     }
 }
 
-// Persistent, balanced launch: the grid is the number of workgroups the GPU
-// holds at once.  The work is the list of (strip, theta row) units in
-// strip-major order; workgroup `rank` takes the contiguous range
-// [total*rank/G, total*(rank+1)/G), so every workgroup does the same number of
-// rows (to within one) and none waits for a second round.  Ranks are dealt so
-// that each XCD (which receives every eighth workgroup id) owns a contiguous
-// block of ranges: its concurrently running rows are neighbours in theta and
-// share their boundary rows in that XCD's L2.
+// Launch layout: every radial strip is cut into the same number `segs` of theta
+// segments (an even number when there is more than one), workgroup
+// rank = strip * segs + i owns segment i of its strip, and even segments march
+// upward, odd ones downward.  Two segments that share a boundary row then read
+// it at the same moment (both start there, or both end there), and segment i
+// of neighbouring strips -- which share the radial halo -- march the same rows
+// in step, so the shared lines are read from HBM once and hit in L2 for the
+// second reader.  Ranks are dealt so that each XCD (which receives every
+// eighth workgroup id) owns a contiguous block of ranks, i.e. whole strips.
 template <int WP, int kMode>
 __global__ __launch_bounds__(kWave) void stage_kernel(StageArgs A)
 {
@@ -414,17 +429,11 @@ __global__ __launch_bounds__(kWave) void stage_kernel(StageArgs A)
     const int xcd = bid & 7, loc = bid >> 3;
     const int q8 = G >> 3, r8 = G & 7;
     const int rank = xcd * q8 + (xcd < r8 ? xcd : r8) + loc;
-    const long long total = (long long)A.nstrips * A.nth;
-    long long u = total * rank / G;
-    const long long u_end = total * (rank + 1) / G;
-    while (u < u_end) {
-        const int strip = (int)(u / A.nth);
-        const int k0 = (int)(u - (long long)strip * A.nth);
-        const long long left = u_end - u;
-        const int k1 = (int)min((long long)A.nth, (long long)k0 + left);
-        march_strip<WP, kMode>(A, s, strip, k0, k1);
-        u += k1 - k0;
-    }
+    const int strip = rank / A.segs;
+    const int seg = rank - strip * A.segs;
+    const int k0 = (int)((long long)A.nth * seg / A.segs);
+    const int k1 = (int)((long long)A.nth * (seg + 1) / A.segs);
+    if (k1 > k0) march_strip<WP, kMode>(A, s, strip, k0, k1, (seg & 1) ? -1 : 1);
 }
 
 // ---------------------------------------------------------------- stability bound
