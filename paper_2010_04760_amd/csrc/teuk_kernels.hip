@@ -65,12 +65,35 @@ __device__ __forceinline__ double rsq64(double x)
 // The f^- flux f^-_{j+1/2} is the same function of the mirrored stencil
 // (f_{j+3}, f_{j+2}, f_{j+1}, f_j, f_{j-1}).
 //
-// Weights: alpha_k = d_k / (eps + IS_k)^2, omega_k = alpha_k / sum alpha, taken
-// over the common denominator (one reciprocal instead of four divisions);
-// omega_2 = 1 - omega_0 - omega_1 in FP64, so the weights sum to one exactly
-// in the combination whatever precision they were computed in.
+// Arithmetic, rearranged by exact identities (only rounding differs from the
+// printed formulas):
+//  * with the second differences d_k and first differences e_k of IS_k,
+//    4 IS_k = (13/3) d_k^2 + e_k^2; eps is scaled by 4 as well, so every
+//    t_k = (eps + IS_k)^2 carries the same factor 16, which cancels in omega;
+//  * omega_k = alpha_k / sum alpha with alpha_k = d_k / t_k is taken over the
+//    common denominator, constants scaled by 10:
+//        omega_0 = t1 t2 / D,  omega_1 = 6 t0 t2 / D,  D = t1 t2 + 6 t0 t2 + 3 t0 t1,
+//    one reciprocal instead of four divisions;
+//  * omega_2 = 1 - omega_0 - omega_1, i.e. the flux is
+//        6 f = q2 + omega_0 (q0 - q2) + omega_1 (q1 - q2),
+//    so the weights sum to one exactly in the combination;
+//  * the candidates (times 6) reuse the differences:
+//        q2 = 3 (v2 + v3) - d2,  q1 - q2 = d2 - d1,  q0 = 2 d0 + 9 v2 - 3 v1.
 template <int WP>
 struct Weno;
+
+// Candidate part shared by every weight precision: 6 f from omega_0, omega_1.
+struct Candidates {
+    double q2, dq0, dq1;
+    __device__ __forceinline__ Candidates(double v0, double v1, double v2, double v3, double d0, double d1,
+                                          double d2)
+    {
+        (void)v0;
+        q2 = 3.0 * (v2 + v3) - d2;
+        dq1 = d2 - d1;
+        dq0 = (2.0 * d0 + (9.0 * v2 - 3.0 * v1)) - q2;
+    }
+};
 
 template <>
 struct Weno<TEUK_W_FP64> {
@@ -83,22 +106,18 @@ struct Weno<TEUK_W_FP64> {
         const double e0 = v0 - 4.0 * v1 + 3.0 * v2;
         const double e1 = v1 - v3;
         const double e2 = 3.0 * v2 - 4.0 * v3 + v4;
-        const double b0 = (13.0 / 12.0) * d0 * d0 + 0.25 * e0 * e0;
-        const double b1 = (13.0 / 12.0) * d1 * d1 + 0.25 * e1 * e1;
-        const double b2 = (13.0 / 12.0) * d2 * d2 + 0.25 * e2 * e2;
-        double t0 = eps + b0, t1 = eps + b1, t2 = eps + b2;
+        constexpr double c = 13.0 / 3.0;
+        const double eps4 = 4.0 * eps;
+        double t0 = eps4 + ((c * d0) * d0 + e0 * e0);
+        double t1 = eps4 + ((c * d1) * d1 + e1 * e1);
+        double t2 = eps4 + ((c * d2) * d2 + e2 * e2);
         t0 *= t0;
         t1 *= t1;
         t2 *= t2;
-        const double n0 = 0.1 * t1 * t2;
-        const double n1 = 0.6 * t0 * t2;
-        const double n2 = 0.3 * t0 * t1;
-        const double inv = rcp64(n0 + n1 + n2);
-        const double w0 = n0 * inv, w1 = n1 * inv;
-        const double q0 = 2.0 * v0 - 7.0 * v1 + 11.0 * v2;
-        const double q1 = -v1 + 5.0 * v2 + 2.0 * v3;
-        const double q2 = 2.0 * v2 + 5.0 * v3 - v4;
-        return q2 + w0 * (q0 - q2) + w1 * (q1 - q2);
+        const double p12 = t1 * t2, p02 = t0 * t2, p01 = t0 * t1;
+        const double inv = rcp64(p12 + (6.0 * p02 + 3.0 * p01));
+        const Candidates q(v0, v1, v2, v3, d0, d1, d2);
+        return q.q2 + inv * (p12 * q.dq0 + (6.0 * p02) * q.dq1);
     }
 };
 
@@ -203,10 +222,8 @@ struct WenoLow {
         const double e2 = 3.0 * v2 - 4.0 * v3 + v4;
         double w0, w1;
         low_weights<L, kScale>(d0, d1, d2, e0, e1, e2, eps, &w0, &w1);
-        const double q0 = 2.0 * v0 - 7.0 * v1 + 11.0 * v2;
-        const double q1 = -v1 + 5.0 * v2 + 2.0 * v3;
-        const double q2 = 2.0 * v2 + 5.0 * v3 - v4;
-        return q2 + w0 * (q0 - q2) + w1 * (q1 - q2);
+        const Candidates q(v0, v1, v2, v3, d0, d1, d2);
+        return q.q2 + (w0 * q.dq0 + w1 * q.dq1);
     }
 };
 
