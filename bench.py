@@ -1,18 +1,26 @@
 #!/usr/bin/env python3
 """Throughput of the WENO5 / SSP-RK3 Teukolsky hot path on one MI355X.
 
-Workload: the gravitational solve s = -2, m = 2, a/M = 0.999 on an 8192 (r_*)
-x 256 (theta) grid, x in [-200, 400], seeded Gaussian pulse times the
-spin-weighted harmonic, dt = 0.5 x the device stability bound, waveform sampled
-at r_* = 30 every 10 steps.  One benchmark step is one SSP-RK(3,3) time step
-(three fused stage kernels over the whole grid, plus the waveform sample when
-due).  Inputs are resident in HBM before the timed region.
+Default workload (C2): the gravitational solve s = -2, m = 2, a/M = 0.999 on an
+8192 (r_*) x 256 (theta) grid, x in [-200, 400], seeded Gaussian pulse times
+the spin-weighted harmonic, dt = 0.5 x the device stability bound, waveform
+sampled at r_* = 30 every 10 steps.  One benchmark step is one SSP-RK(3,3)
+time step (three fused stage kernels over the whole grid, plus the waveform
+sample when due).  Inputs are resident in HBM before the timed region.
 
 Reported: point-updates/s (one point-update = one RHS evaluation with its RK
 combination at one grid point, all four planes; three per point per step), the
 HBM roofline of the fused stage kernel (algorithmic bytes: 64 B per point in
-stage 1, 96 B in stages 2 and 3, i.e. 256 B per point-step), and the FP64 CPU
-oracle timed on a bounded sample of the same workload on the host cores.
+stage 1, 96 B in stages 2 and 3, i.e. 256 B per point-step), the same workload
+with FP32 / FP16 / BF16 WENO weights (speed and waveform error against FP64),
+and the FP64 CPU oracle timed on a bounded sample of the workload on the host
+cores.
+
+Other workloads (one JSON line each):
+  --workload C4   64 independent solves of uneven size advanced together
+                  through the group extension (FP32 weights, 2000 steps).
+  --workload C5   Poisson arrivals of such solves served by continuous
+                  batching (admission by HBM footprint); p50/p99 latency.
 """
 from __future__ import annotations
 
@@ -32,6 +40,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_POINT_STEP = 256.0   # 64 + 96 + 96 (fields only; coefficients rebuilt on chip)
 KERNEL_SRC = os.path.join(ROOT, "paper_2010_04760_amd", "csrc", "teuk_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_c2_traffic.json")
+METRIC = "WENO5 RHS point-updates/s, %HBM peak; mixed vs FP64 speedup at equal error"
 
 
 def kernel_sha() -> str:
@@ -49,6 +58,10 @@ def measured_traffic(weights: str):
     return float(rec["bytes_per_launch"][weights])
 
 
+def log(msg: str):
+    print("# " + msg, file=sys.stderr, flush=True)
+
+
 def cpu_baseline(wl, u0, target_s: float):
     """The FP64 oracle on the host cores, on the same grid and initial data."""
     from oracle import solver as S
@@ -57,28 +70,248 @@ def cpu_baseline(wl, u0, target_s: float):
     prob = S.Problem(wl.s, wl.m, wl.a, wl.nr, wl.nth, wl.x_min, wl.x_max)
     o = S.TeukOracle(prob)
     dt = o.dt_bound(0.5)
-    t0 = time.perf_counter()
-    u1, _ = o.evolve(u0, dt, 1)
-    t1 = time.perf_counter() - t0
-    n = max(1, int(target_s / max(t1, 1e-3)))
-    t0 = time.perf_counter()
-    o.evolve(u1, dt, n)
-    el = time.perf_counter() - t0
+    u, _ = o.evolve(u0, dt, 1)                 # first call: thread start-up, page faults
+    n, el, chunk = 0, 0.0, 1
+    while el < target_s:
+        t0 = time.perf_counter()
+        u, _ = o.evolve(u, dt, chunk)
+        dt_chunk = time.perf_counter() - t0
+        n, el = n + chunk, el + dt_chunk
+        chunk = max(1, min(64, int(0.25 * target_s / max(dt_chunk / chunk, 1e-4))))
     return {"value": 3.0 * wl.points * n / el, "unit": "point-updates/s", "cores": S.num_threads(),
             "kind": "oracle",
-            "sample": f"{wl.nr}x{wl.nth} grid of the same workload, {n} SSP-RK3 steps "
+            "sample": f"{wl.nr}x{wl.nth} grid ({wl.name.split(',')[0]}), {n} SSP-RK3 steps "
                       f"({3 * wl.points * n:.3g} point-updates, {el:.1f} s) on {S.num_threads()} OpenMP threads"}
+
+
+def roofline(points_per_launch: float, t_launch: float, traffic):
+    bytes_launch = BYTES_PER_POINT_STEP * points_per_launch / 3.0
+    achieved = bytes_launch / t_launch / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "stage_kernel (fused SSP-RK3 stage)",
+            "algorithmic_bytes_per_launch": bytes_launch, "avg_launch_us": t_launch * 1e6}
+
+
+def solver_config(T, wl, weights, total_steps, workgroups=0, every=None):
+    every = wl.every if every is None else every
+    return T.make_config(s=wl.s, m=wl.m, a=wl.a, nr=wl.nr, ntheta=wl.nth, x_min=wl.x_min, x_max=wl.x_max,
+                         M=wl.M, dt=0.0, cfl=0.5, weight_prec=weights, x_extract=wl.x_e, extract_every=every,
+                         max_samples=total_steps // every + 1 if every > 0 else 0, workgroups=workgroups)
+
+
+# ----------------------------------------------------------------------------- C2: one solve
+def bench_single(args, torch, T, W):
+    wl = W.C2
+    steps = 20000 if args.steps is None else args.steps
+    warmup = 100 if args.warmup is None else args.warmup
+    weights = args.weights or "fp64"
+    u0 = W.gaussian_pulse(wl)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {n * 8} bytes read and written per copy")
+        del src, dst
+
+    def run(wp):
+        """Warm up, then time `steps` steps with HIP events on the solver's
+        stream.  Returns (seconds, wall seconds, info, waveform samples)."""
+        sv = T.Solver(solver_config(T, wl, wp, warmup + steps, args.workgroups), stream=stream)
+        sv.set_initial(u0)
+        log(f"{wp}: warmup {warmup} steps")
+        sv.step(warmup)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        log(f"{wp}: timing {steps} steps")
+        w0 = time.perf_counter()
+        ev0.record(stream)
+        sv.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        sec = ev0.elapsed_time(ev1) / 1e3
+        sv.check_finite()
+        info = sv.info()
+        _, wave = sv.waveform()
+        sv.close()
+        return sec, wall, info, wave
+
+    gpu_s, wall, info, wave = run(weights)
+    pu = 3.0 * wl.points * steps
+    # 3 stage launches per step; the sample kernel (one per 10 steps) is
+    # included in the time and is < 0.5 % of it.
+    out = {
+        "metric": METRIC, "value": pu / gpu_s, "unit": "point-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": gpu_s / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if weights == "fp64" else f"f64 (weights {weights})",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "nr": wl.nr, "ntheta": wl.nth, "s": wl.s, "m": wl.m, "a": wl.a,
+                   "weights": weights, "dt": info.dt, "workgroups": info.workgroups,
+                   "extract_every": wl.every, "seed": wl.seed},
+        "roofline": roofline(wl.points, gpu_s / (3 * steps), measured_traffic(weights)),
+        "wall_s": wall,
+    }
+    if weights == "fp64" and not args.no_mixed:
+        # Mixed-precision weights on the same workload: speed and waveform
+        # error (relative L2 over all samples) against the FP64 run above.
+        mixed = {}
+        for wp in ("fp32", "fp16", "bf16"):
+            sec_w, _, _, wave_w = run(wp)
+            err = float(np.linalg.norm(wave_w - wave) / np.linalg.norm(wave))
+            mixed[wp] = {"value": pu / sec_w, "speedup_vs_fp64": gpu_s / sec_w, "waveform_rel_l2_vs_fp64": err}
+        out["mixed_precision"] = mixed
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(wl, u0, args.cpu_seconds)
+    return out
+
+
+# ----------------------------------------------------------------------------- C4: batched solves
+def bench_batched(args, torch, T, W):
+    mix = W.batch_workloads()
+    steps = 2000 if args.steps is None else args.steps
+    warmup = 20 if args.warmup is None else args.warmup
+    weights = args.weights or "fp32"
+    stream = torch.cuda.current_stream()
+    members = []
+    log(f"C4: creating {len(mix)} solves")
+    for w in mix:
+        sv = T.Solver(solver_config(T, w, weights, warmup + steps), stream=stream)
+        sv.set_initial(W.gaussian_pulse(w))
+        members.append(sv)
+    points = sum(w.points for w in mix)
+
+    # the same solves advanced one after another with teuk_step (context for
+    # the batching gain; a few steps each)
+    alone_steps = max(1, min(20, steps))
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    for sv in members:
+        sv.step(2)
+    ev0.record(stream)
+    for sv in members:
+        sv.step(alone_steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    alone_s = ev0.elapsed_time(ev1) / 1e3
+    for sv, w in zip(members, mix):     # restart from the initial data
+        sv.set_initial(W.gaussian_pulse(w))
+
+    g = T.Group(len(mix), workgroups=args.workgroups, rows_per_tile=args.rows_per_tile, stream=stream)
+    for sv in members:
+        g.add(sv)
+    ginfo = g.info()
+    log(f"C4: warmup {warmup} steps")
+    g.step(warmup)
+    torch.cuda.synchronize()
+    log(f"C4: timing {steps} steps")
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    g.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    for sv in members:
+        sv.check_finite()
+    g.close()
+    for sv in members:
+        sv.close()
+    pu = 3.0 * points * steps
+    # one stage = one launch per weight precision present (one here)
+    out = {
+        "metric": METRIC, "value": pu / gpu_s, "unit": "point-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": gpu_s / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": f"f64 (weights {weights})", "data": "synthetic",
+        "config": {"workload": f"C4: {len(mix)} solves, Nr~U{{2048..16384}}, Ntheta~U{{64..256}}, "
+                               f"{points} points, {steps} steps",
+                   "solves": len(mix), "points": points, "weights": weights, "seeds": "1000..1063",
+                   "workgroups_per_stage": int(ginfo.workgroups), "tiles_per_stage": int(ginfo.tiles),
+                   "rows_per_tile": args.rows_per_tile or 8},
+        "roofline": roofline(points, gpu_s / (3 * steps), None),
+        "alone_sequential": {"value": 3.0 * points * alone_steps / alone_s, "steps": alone_steps},
+        "batching_speedup": (pu / gpu_s) / (3.0 * points * alone_steps / alone_s),
+        "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        # the oracle on the member nearest the mean size
+        mean = points / len(mix)
+        w = min(mix, key=lambda x: abs(x.points - mean))
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(w, W.gaussian_pulse(w), args.cpu_seconds)
+    return out
+
+
+# ----------------------------------------------------------------------------- C5: serving
+def bench_serving(args, torch, T, W):
+    from paper_2010_04760_amd import serving
+    nreq = args.requests
+    load = args.load
+    reqs = serving.poisson_requests(nreq, seed=args.serve_seed)
+    work = sum(r.work for r in reqs)
+    cap_rate = args.capacity_rate
+    if cap_rate <= 0:
+        # calibrate the offered load against the batched throughput of the mix
+        log("C5: measuring batched throughput for the load calibration")
+        cap_rate = serving.measure_capacity(reqs[:16], steps=200)
+    rate = load * cap_rate / (work / nreq)          # requests per second
+    arrivals = serving.arrival_times(nreq, rate, seed=args.serve_seed)
+    budget = int(args.hbm_budget_gb * (1 << 30)) if args.hbm_budget_gb > 0 else None
+    log(f"C5: {nreq} requests, offered load {load:.2f} x {cap_rate:.3g} pu/s = {rate:.3g} req/s")
+    srv = serving.Server(max_members=nreq, hbm_budget=budget, chunk_steps=args.chunk_steps,
+                         workgroups=args.workgroups, rows_per_tile=args.rows_per_tile)
+    res = srv.run(reqs, arrivals, progress=log)
+    lat = np.array([r.latency for r in res.done])
+    queued = np.array([r.queued for r in res.done])
+    pu = 3.0 * sum(r.req.points * r.req.steps for r in res.done)
+    return {
+        "metric": METRIC, "value": pu / res.makespan, "unit": "point-updates/s", "n_gpus": 1,
+        "steps": int(sum(r.req.steps for r in res.done)), "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": f"f64 (weights {reqs[0].weights})", "data": "synthetic",
+        "config": {"workload": f"C5: {nreq} Poisson requests, steps~U{{5000..50000}}, offered load {load}",
+                   "requests": nreq, "offered_load": load, "capacity_rate": cap_rate, "arrival_rate": rate,
+                   "hbm_budget_bytes": res.budget, "chunk_steps": args.chunk_steps},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "max": float(lat.max()), "mean": float(lat.mean())},
+        "queue_s": {"p50": float(np.percentile(queued, 50)), "p99": float(np.percentile(queued, 99))},
+        "max_resident": res.max_resident, "makespan_s": res.makespan,
+    }
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000, help="timed SSP-RK3 steps (workload length: 20000)")
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--weights", default="fp64", choices=["fp64", "fp32", "fp16", "bf16"])
-    ap.add_argument("--workgroups", type=int, default=0, help="stage-kernel workgroups (0: all the GPU holds at once)")
+    ap.add_argument("--workload", default="C2", choices=["C2", "C4", "C5"])
+    ap.add_argument("--steps", type=int, default=None, help="timed SSP-RK3 steps (C2: 20000, C4: 2000)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (C2: 100, C4: 20)")
+    ap.add_argument("--weights", default=None, choices=["fp64", "fp32", "fp16", "bf16"],
+                    help="WENO weight precision (C2: fp64, C4/C5: fp32)")
+    ap.add_argument("--workgroups", type=int, default=0,
+                    help="stage-kernel workgroups (C2, 0: all the GPU holds at once; C4/C5, 0: one per tile)")
+    ap.add_argument("--rows-per-tile", type=int, default=0, help="C4/C5: theta rows per group tile (0: 8)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/FP16/BF16-weight runs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="before the solve, run a plain device copy of MIB MiB three times (a known-size "
+                         "kernel that calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--requests", type=int, default=32, help="C5: number of requests")
+    ap.add_argument("--load", type=float, default=0.9, help="C5: offered load / batched capacity")
+    ap.add_argument("--capacity-rate", type=float, default=0.0,
+                    help="C5: batched point-updates/s used for the load (0: measure)")
+    ap.add_argument("--chunk-steps", type=int, default=250, help="C5: steps between admission checks")
+    ap.add_argument("--hbm-budget-gb", type=float, default=0.0, help="C5: admission budget (0: free HBM)")
+    ap.add_argument("--serve-seed", type=int, default=5)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -90,74 +323,9 @@ def main():
     import paper_2010_04760_amd as T
     import workloads as W
 
-    wl = W.C2
-    u0 = W.gaussian_pulse(wl)
-    total = args.warmup + args.steps
-    cfg = T.make_config(s=wl.s, m=wl.m, a=wl.a, nr=wl.nr, ntheta=wl.nth, x_min=wl.x_min, x_max=wl.x_max,
-                        M=wl.M, dt=0.0, cfl=0.5, weight_prec=args.weights, x_extract=wl.x_e,
-                        extract_every=wl.every, max_samples=total // wl.every + 1, workgroups=args.workgroups)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream(dev)
-    sv = T.Solver(cfg, stream=stream)
-    sv.set_initial(u0)
-    print(f"# warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    sv.step(args.warmup)
-    torch.cuda.synchronize()
-
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    print(f"# timing {args.steps} steps", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record(stream)
-    sv.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    gpu_s = ev0.elapsed_time(ev1) / 1e3
-    sv.check_finite()
-    info = sv.info()
-    sv.close()
-
-    npts = wl.points
-    pu = 3.0 * npts * args.steps
-    value = pu / gpu_s
-    # Stage kernels: 3 launches per step; the sample kernel (one per 10 steps)
-    # is included in the time and is < 0.5 % of it.
-    launches = 3 * args.steps
-    t_launch = gpu_s / launches
-    bytes_launch = BYTES_PER_POINT_STEP * npts / 3.0
-    achieved = bytes_launch / t_launch / 1e9
-    traffic = measured_traffic(args.weights)
-
-    out = {
-        "metric": "WENO5 RHS point-updates/s, %HBM peak; mixed vs FP64 speedup at equal error",
-        "value": value,
-        "unit": "point-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": gpu_s / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.weights == "fp64" else f"f64 (weights {args.weights})",
-        "data": "synthetic",
-        "config": {"workload": wl.name, "nr": wl.nr, "ntheta": wl.nth, "s": wl.s, "m": wl.m, "a": wl.a,
-                   "weights": args.weights, "dt": info.dt, "workgroups": info.workgroups,
-                   "extract_every": wl.every, "seed": wl.seed},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "kernel": "stage_kernel (fused SSP-RK3 stage)",
-                     "algorithmic_bytes_per_launch": bytes_launch,
-                     "avg_launch_us": t_launch * 1e6},
-        "wall_s": wall,
-    }
-    if not args.no_cpu_baseline:
-        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, u0, args.cpu_seconds)
+    torch.cuda.set_device(0)
+    fn = {"C2": bench_single, "C4": bench_batched, "C5": bench_serving}[args.workload]
+    out = fn(args, torch, T, W)
     print(json.dumps(out), flush=True)
 
 

@@ -107,7 +107,8 @@ typedef struct {
     double x_min, x_max;     /* radial range of x = r_* (x_min < x_max)                */
     double dt;               /* > 0: time step used as given; <= 0: cfl * stability bound */
     double cfl;              /* used when dt <= 0 (e.g. 0.5)                           */
-    double weno_eps;         /* epsilon of the WENO weights (e.g. 1e-6), > 0           */
+    double weno_eps;         /* epsilon of the WENO weights (e.g. 1e-6), in [1e-30, 1e30]
+                                (normal in FP32, so reduced-precision weights stay finite) */
     double x_extract;        /* waveform radius; the nearest grid node is sampled       */
 } teuk_config;
 
@@ -198,6 +199,72 @@ const char* teuk_last_error(const teuk_solver* h);
  * GPU.  out holds capacity doubles (>= TEUK_NCOEF*ntheta*nr).
  * Errors: INVALID_ARG, CAPACITY. */
 teuk_status teuk_host_coefficients(const teuk_config* cfg, double* out, size_t capacity);
+
+/* ------------------------------------------------------------------------
+ * Group extension: many independent solves advanced together.
+ *
+ * Separating exp(i m phi~) (Sec. 3) leaves one 2+1D problem per (s, m) mode
+ * and per background; such solves share nothing, so a group advances all of
+ * its members in one stage-kernel launch per SSP-RK stage (one per weight
+ * precision present) instead of three launches per member per step.  Each
+ * member keeps its own grid, coefficients, dt, waveform ring and counters, and
+ * its results are bitwise those of teuk_step on the member alone: the tiles
+ * of a member run the single-solve stage arithmetic unchanged.
+ *
+ * Members are created with teuk_create as usual and must use the group's
+ * stream.  The group does not own its members; teuk_destroy of a member
+ * removes it from its group first.  A solver belongs to at most one group.
+ * Device memory: the group allocates one small descriptor block at creation
+ * (about 3 * max_members * 160 bytes) and nothing per step.
+ */
+typedef struct teuk_group teuk_group;   /* opaque; owned by the library */
+
+typedef struct {
+    int32_t members;         /* solvers in the group                                 */
+    int32_t classes;         /* weight precisions present (= launches per stage)     */
+    int64_t workgroups;      /* workgroups per stage, summed over the launches        */
+    int64_t tiles;           /* tiles (one strip x one theta segment) per stage        */
+    int64_t units;           /* strip-rows per stage (63 radial points x 1 theta row)  */
+    int64_t points;          /* grid points over all members                          */
+} teuk_group_info_t;
+
+/* Create an empty group on the current HIP device, enqueuing on ctx->stream
+ * (ctx may be NULL: null stream; ctx->workspace is not used).  max_members in
+ * [1, 65536].  Each member is cut into tiles of one 63-point radial strip by
+ * one theta segment of about rows_per_tile rows (0: 8); the tiles are
+ * numbered segment by segment with the strip index fastest, so that the
+ * workgroups in flight march neighbouring strips over the same rows.  Each
+ * stage launch runs one workgroup per tile (workgroups = 0) or `workgroups`
+ * workgroups that take the tiles round-robin.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE; teuk_group_last_error(NULL)
+ * says why. */
+teuk_status teuk_group_create(const teuk_device_ctx* ctx, int32_t max_members, int32_t workgroups,
+                              int32_t rows_per_tile, teuk_group** out);
+
+/* Add a solver (after teuk_set_initial) to the group.  Synchronises the group's
+ * stream and uploads the members' descriptors.  Errors: INVALID_ARG (NULL,
+ * other stream, already in a group), CAPACITY (group full), STATE (no initial
+ * data), DEVICE. */
+teuk_status teuk_group_add(teuk_group* g, teuk_solver* h);
+
+/* Remove a member (synchronises the group's stream).  The solver stays valid
+ * and can be stepped alone.  Errors: INVALID_ARG (NULL, not a member), DEVICE. */
+teuk_status teuk_group_remove(teuk_group* g, teuk_solver* h);
+
+/* Advance every member nsteps SSP-RK(3,3) steps with its own dt, sampling each
+ * member's waveform as teuk_step does.  Asynchronous on the group's stream.
+ * An empty group or nsteps = 0 is a no-op.  Errors: INVALID_ARG, DEVICE. */
+teuk_status teuk_group_step(teuk_group* g, int64_t nsteps);
+
+/* Group information (no synchronisation).  Errors: INVALID_ARG. */
+teuk_status teuk_group_info(const teuk_group* g, teuk_group_info_t* info);
+
+/* Release the group (members are detached, not destroyed).  NULL-safe. */
+void teuk_group_destroy(teuk_group* g);
+
+/* Last error message of g (or of the thread's last failed teuk_group_create
+ * when g is NULL).  Never NULL. */
+const char* teuk_group_last_error(const teuk_group* g);
 
 #ifdef __cplusplus
 }

@@ -5,5 +5,5 @@ package is its thin Python binding.  See ``Solver`` and the ``teuk_*``
 functions, which carry the C names.
 """
 from ._binding import *  # noqa: F401,F403
-from ._binding import (EXPORTED, LIB_PATH, Solver, TeukError, make_config, teuk_config,  # noqa: F401
-                       teuk_device_ctx, teuk_info_t)
+from ._binding import (EXPORTED, LIB_PATH, Group, Solver, TeukError, make_config, teuk_config,  # noqa: F401
+                       teuk_device_ctx, teuk_group_info_t, teuk_info_t)

@@ -87,9 +87,32 @@ _lib.teuk_last_error.restype = ctypes.c_char_p
 _lib.teuk_host_coefficients.argtypes = [_P(teuk_config), _dp, ctypes.c_size_t]
 _lib.teuk_host_coefficients.restype = ctypes.c_int
 
+
+class teuk_group_info_t(ctypes.Structure):
+    _fields_ = [("members", ctypes.c_int32), ("classes", ctypes.c_int32), ("workgroups", ctypes.c_int64),
+                ("tiles", ctypes.c_int64), ("units", ctypes.c_int64), ("points", ctypes.c_int64)]
+
+
+_lib.teuk_group_create.argtypes = [_P(teuk_device_ctx), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   _P(ctypes.c_void_p)]
+_lib.teuk_group_create.restype = ctypes.c_int
+_lib.teuk_group_add.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+_lib.teuk_group_add.restype = ctypes.c_int
+_lib.teuk_group_remove.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+_lib.teuk_group_remove.restype = ctypes.c_int
+_lib.teuk_group_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+_lib.teuk_group_step.restype = ctypes.c_int
+_lib.teuk_group_info.argtypes = [ctypes.c_void_p, _P(teuk_group_info_t)]
+_lib.teuk_group_info.restype = ctypes.c_int
+_lib.teuk_group_destroy.argtypes = [ctypes.c_void_p]
+_lib.teuk_group_destroy.restype = None
+_lib.teuk_group_last_error.argtypes = [ctypes.c_void_p]
+_lib.teuk_group_last_error.restype = ctypes.c_char_p
+
 EXPORTED = ["teuk_default_config", "teuk_footprint_bytes", "teuk_create", "teuk_set_initial", "teuk_step",
             "teuk_extract", "teuk_info", "teuk_check_finite", "teuk_destroy", "teuk_last_error",
-            "teuk_host_coefficients"]
+            "teuk_host_coefficients", "teuk_group_create", "teuk_group_add", "teuk_group_remove",
+            "teuk_group_step", "teuk_group_info", "teuk_group_destroy", "teuk_group_last_error"]
 
 
 class TeukError(RuntimeError):
@@ -101,6 +124,11 @@ class TeukError(RuntimeError):
 def _check(st: int, h=None):
     if st != TEUK_OK:
         raise TeukError(st, _lib.teuk_last_error(h).decode())
+
+
+def _gcheck(st: int, g=None):
+    if st != TEUK_OK:
+        raise TeukError(st, _lib.teuk_group_last_error(g).decode())
 
 
 # ----------------------------------------------------------------------------- same names as the C ABI
@@ -168,6 +196,40 @@ def teuk_host_coefficients(cfg: teuk_config) -> np.ndarray:
     out = np.empty(TEUK_NCOEF * n, dtype=np.float64)
     _check(_lib.teuk_host_coefficients(ctypes.byref(cfg), out.ctypes.data_as(_dp), out.size))
     return out.reshape(TEUK_NCOEF, cfg.ntheta, cfg.nr)
+
+
+def teuk_group_create(ctx: teuk_device_ctx | None, max_members: int, workgroups: int = 0,
+                      rows_per_tile: int = 0) -> int:
+    g = ctypes.c_void_p()
+    _gcheck(_lib.teuk_group_create(ctypes.byref(ctx) if ctx is not None else None, int(max_members),
+                                   int(workgroups), int(rows_per_tile), ctypes.byref(g)))
+    return g.value
+
+
+def teuk_group_add(g: int, h: int) -> None:
+    _gcheck(_lib.teuk_group_add(g, h), g)
+
+
+def teuk_group_remove(g: int, h: int) -> None:
+    _gcheck(_lib.teuk_group_remove(g, h), g)
+
+
+def teuk_group_step(g: int, nsteps: int) -> None:
+    _gcheck(_lib.teuk_group_step(g, int(nsteps)), g)
+
+
+def teuk_group_info(g: int) -> teuk_group_info_t:
+    info = teuk_group_info_t()
+    _gcheck(_lib.teuk_group_info(g, ctypes.byref(info)), g)
+    return info
+
+
+def teuk_group_destroy(g: int | None) -> None:
+    _lib.teuk_group_destroy(g)
+
+
+def teuk_group_last_error(g: int | None = None) -> str:
+    return _lib.teuk_group_last_error(g).decode()
 
 
 # ----------------------------------------------------------------------------- convenience (marshalling only)
@@ -250,6 +312,52 @@ class Solver:
             teuk_destroy(self.h)
             self.h = None
             self._ws = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Group:
+    """Independent solves advanced together (one launch per RK stage for all
+    members).  Members are ``Solver`` objects on the group's stream; the group
+    keeps a reference to each so that their memory outlives membership."""
+
+    def __init__(self, max_members: int, workgroups: int = 0, rows_per_tile: int = 0,
+                 stream: "torch.cuda.Stream | None" = None, device=None):
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        ctx = teuk_device_ctx(ctypes.c_void_p(self.stream.cuda_stream), None, 0)
+        self.g = teuk_group_create(ctx, max_members, workgroups, rows_per_tile)
+        self.members: list[Solver] = []
+
+    def add(self, sv: "Solver"):
+        teuk_group_add(self.g, sv.h)
+        self.members.append(sv)
+
+    def remove(self, sv: "Solver"):
+        teuk_group_remove(self.g, sv.h)
+        self.members.remove(sv)
+
+    def step(self, nsteps: int):
+        teuk_group_step(self.g, nsteps)
+
+    def info(self) -> teuk_group_info_t:
+        return teuk_group_info(self.g)
+
+    def close(self):
+        if self.g is not None:
+            teuk_group_destroy(self.g)
+            self.g = None
+            self.members = []
 
     def __enter__(self):
         return self

@@ -33,6 +33,25 @@ struct teuk_solver {
     long long plane = 0;
     long long steps = 0, samples = 0;
     bool have_init = false;
+    int device = 0;
+    teuk_group* group = nullptr;                    // group holding this solver, if any
+    std::string err;
+};
+
+struct teuk_group {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int cap = 0;                                    // max members
+    int workgroups = 0;                             // per stage launch; 0 = one per tile
+    int rows = 8;                                   // theta rows per tile (target)
+    std::vector<teuk_solver*> mem;                  // insertion order
+    StageArgs* d_args = nullptr;                    // [3][cap]: per stage, members by weight precision
+    long long* d_start = nullptr;                   // [4][cap + 1]: tile prefix sums per precision class
+    std::vector<StageArgs> h_args;
+    std::vector<long long> h_start;
+    int cls_first[4] = {0, 0, 0, 0}, cls_n[4] = {0, 0, 0, 0}, cls_grid[4] = {0, 0, 0, 0};
+    long long cls_tiles[4] = {0, 0, 0, 0}, cls_units[4] = {0, 0, 0, 0};
+    long long points = 0;
     std::string err;
 };
 
@@ -75,7 +94,7 @@ bool validate(const teuk_config* c, std::string& err)
     if (!(c->M > 0.0) || !std::isfinite(c->M)) { err = "M must be positive and finite"; return false; }
     if (!(c->a >= 0.0) || !(c->a <= c->M)) { err = "spin a must satisfy 0 <= a <= M"; return false; }
     if (!std::isfinite(c->x_min) || !std::isfinite(c->x_max) || !(c->x_min < c->x_max)) { err = "need finite x_min < x_max"; return false; }
-    if (!(c->weno_eps > 0.0) || !std::isfinite(c->weno_eps)) { err = "weno_eps must be positive and finite"; return false; }
+    if (!(c->weno_eps >= 1e-30) || !(c->weno_eps <= 1e30)) { err = "weno_eps must lie in [1e-30, 1e30]"; return false; }
     if (!std::isfinite(c->dt)) { err = "dt must be finite"; return false; }
     if (c->dt <= 0.0 && (!(c->cfl > 0.0) || !std::isfinite(c->cfl))) { err = "cfl must be positive when dt <= 0"; return false; }
     if (c->extract_every < 0 || c->max_samples < 0) { err = "extract_every and max_samples must be >= 0"; return false; }
@@ -181,6 +200,7 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     if (!h) return fail(nullptr, TEUK_ERR_OUT_OF_MEMORY, "host allocation failed");
     h->cfg = *cfg;
     h->stream = ctx ? (hipStream_t)ctx->stream : nullptr;
+    (void)hipGetDevice(&h->device);
     const Layout L = layout_of(*cfg);
     h->bytes = L.total;
     if (ctx && ctx->workspace) {
@@ -413,6 +433,7 @@ teuk_status teuk_check_finite(teuk_solver* h)
 void teuk_destroy(teuk_solver* h)
 {
     if (!h) return;
+    if (h->group) (void)teuk_group_remove(h->group, h);
     (void)hipStreamSynchronize(h->stream);
     free_solver(h);
 }
@@ -452,6 +473,208 @@ teuk_status teuk_host_coefficients(const teuk_config* cfg, double* out, size_t c
         }
     }
     return TEUK_OK;
+}
+
+// ---------------------------------------------------------------- groups
+
+static thread_local std::string g_group_err;
+
+static teuk_status gfail(teuk_group* g, teuk_status st, const std::string& msg)
+{
+    if (g) g->err = msg; else g_group_err = msg;
+    return st;
+}
+
+// Theta segments per strip when tiles should march about `rows` rows each (an
+// even number when more than one, so that segments pair up at their shared
+// boundary rows).
+static int group_segs(int nth, int rows)
+{
+    int segs = nth / rows;
+    if (segs > 1) segs &= ~1;
+    if (segs < 1) segs = 1;
+    return segs;
+}
+
+// Rebuild and upload the members' stage descriptors and tile prefix sums, and
+// size each precision class's launch.  The caller has synchronised the group's
+// stream.
+static teuk_status group_upload(teuk_group* g)
+{
+    const int cap = g->cap;
+    int idx = 0;
+    g->points = 0;
+    for (int c = 0; c < 4; ++c) {
+        g->cls_first[c] = idx;
+        g->cls_n[c] = 0;
+        long long* start = &g->h_start[(size_t)c * (cap + 1)];
+        long long tiles = 0, units = 0;
+        start[0] = 0;
+        for (teuk_solver* h : g->mem) {
+            if (h->cfg.weight_prec != c) continue;
+            StageArgs a = stage_args(h);
+            a.segs = group_segs(h->cfg.ntheta, g->rows);
+            a.grid = 0;                                  // set per launch
+            tiles += (long long)h->nstrips * a.segs;
+            units += (long long)h->nstrips * h->cfg.ntheta;
+            const int k = g->cls_n[c];
+            start[k + 1] = tiles;
+            // stage 1: u1 = u + dt F(u)
+            a.uk = a.un = h->u[0]; a.out = h->u[1]; a.ca = 0.0; a.cb = 1.0;
+            g->h_args[0 * (size_t)cap + idx] = a;
+            // stage 2: u2 = 3/4 u + 1/4 (u1 + dt F(u1))
+            a.uk = h->u[1]; a.un = h->u[0]; a.out = h->u[2]; a.ca = 0.75; a.cb = 0.25;
+            g->h_args[1 * (size_t)cap + idx] = a;
+            // stage 3: u = 1/3 u + 2/3 (u2 + dt F(u2)), in place
+            a.uk = h->u[2]; a.un = h->u[0]; a.out = h->u[0]; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0;
+            g->h_args[2 * (size_t)cap + idx] = a;
+            g->points += h->plane;
+            ++g->cls_n[c];
+            ++idx;
+        }
+        if (tiles > (1LL << 31) - 1)
+            return gfail(g, TEUK_ERR_CAPACITY, "group too large for one launch (2^31 - 1 tiles)");
+        g->cls_tiles[c] = tiles;
+        g->cls_units[c] = units;
+        g->cls_grid[c] = 0;
+        if (tiles > 0) g->cls_grid[c] = (int)(g->workgroups > 0 && g->workgroups < tiles ? g->workgroups : tiles);
+    }
+    int e = (int)hipMemcpyAsync(g->d_args, g->h_args.data(), g->h_args.size() * sizeof(StageArgs),
+                                hipMemcpyHostToDevice, g->stream);
+    if (!e) e = (int)hipMemcpyAsync(g->d_start, g->h_start.data(), g->h_start.size() * sizeof(long long),
+                                    hipMemcpyHostToDevice, g->stream);
+    if (!e) e = (int)hipStreamSynchronize(g->stream);
+    if (e) return gfail(g, TEUK_ERR_DEVICE, std::string("group upload: ") + hipGetErrorString((hipError_t)e));
+    return TEUK_OK;
+}
+
+teuk_status teuk_group_create(const teuk_device_ctx* ctx, int32_t max_members, int32_t workgroups,
+                              int32_t rows_per_tile, teuk_group** out)
+{
+    if (!out) return gfail(nullptr, TEUK_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (max_members < 1 || max_members > 65536) return gfail(nullptr, TEUK_ERR_INVALID_ARG, "max_members must be in [1, 65536]");
+    if (workgroups < 0) return gfail(nullptr, TEUK_ERR_INVALID_ARG, "workgroups must be >= 0");
+    if (rows_per_tile < 0) return gfail(nullptr, TEUK_ERR_INVALID_ARG, "rows_per_tile must be >= 0");
+    teuk_group* g = new (std::nothrow) teuk_group();
+    if (!g) return gfail(nullptr, TEUK_ERR_OUT_OF_MEMORY, "host allocation failed");
+    g->stream = ctx ? (hipStream_t)ctx->stream : nullptr;
+    (void)hipGetDevice(&g->device);
+    g->cap = max_members;
+    g->workgroups = workgroups;
+    g->rows = rows_per_tile > 0 ? rows_per_tile : 8;
+    g->h_args.assign(3 * (size_t)max_members, StageArgs{});
+    g->h_start.assign(4 * ((size_t)max_members + 1), 0);
+    int e = (int)hipMalloc(&g->d_args, g->h_args.size() * sizeof(StageArgs));
+    if (!e) e = (int)hipMalloc(&g->d_start, g->h_start.size() * sizeof(long long));
+    if (e) {
+        if (g->d_args) (void)hipFree(g->d_args);
+        (void)hipGetLastError();
+        delete g;
+        return gfail(nullptr, e == (int)hipErrorOutOfMemory ? TEUK_ERR_OUT_OF_MEMORY : TEUK_ERR_DEVICE,
+                     std::string("hipMalloc: ") + hipGetErrorString((hipError_t)e));
+    }
+    *out = g;
+    return TEUK_OK;
+}
+
+teuk_status teuk_group_add(teuk_group* g, teuk_solver* h)
+{
+    if (!g) return gfail(nullptr, TEUK_ERR_INVALID_ARG, "group is NULL");
+    if (!h) return gfail(g, TEUK_ERR_INVALID_ARG, "solver is NULL");
+    if (h->group) return gfail(g, TEUK_ERR_INVALID_ARG, "solver already belongs to a group");
+    if (h->stream != g->stream) return gfail(g, TEUK_ERR_INVALID_ARG, "solver and group use different streams");
+    if (h->device != g->device) return gfail(g, TEUK_ERR_INVALID_ARG, "solver and group are on different devices");
+    if (!h->have_init) return gfail(g, TEUK_ERR_STATE, "solver has no initial data");
+    if ((int)g->mem.size() >= g->cap) return gfail(g, TEUK_ERR_CAPACITY, "group is full");
+    int e = (int)hipStreamSynchronize(g->stream);
+    if (e) return gfail(g, TEUK_ERR_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString((hipError_t)e));
+    g->mem.push_back(h);
+    teuk_status st = group_upload(g);
+    if (st != TEUK_OK) {
+        g->mem.pop_back();
+        (void)group_upload(g);
+        return st;
+    }
+    h->group = g;
+    return TEUK_OK;
+}
+
+teuk_status teuk_group_remove(teuk_group* g, teuk_solver* h)
+{
+    if (!g) return gfail(nullptr, TEUK_ERR_INVALID_ARG, "group is NULL");
+    if (!h || h->group != g) return gfail(g, TEUK_ERR_INVALID_ARG, "solver is not a member of this group");
+    int e = (int)hipStreamSynchronize(g->stream);
+    if (e) return gfail(g, TEUK_ERR_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString((hipError_t)e));
+    for (size_t i = 0; i < g->mem.size(); ++i)
+        if (g->mem[i] == h) {
+            g->mem.erase(g->mem.begin() + (long)i);
+            break;
+        }
+    h->group = nullptr;
+    return group_upload(g);
+}
+
+teuk_status teuk_group_step(teuk_group* g, int64_t nsteps)
+{
+    if (!g) return gfail(nullptr, TEUK_ERR_INVALID_ARG, "group is NULL");
+    if (nsteps < 0) return gfail(g, TEUK_ERR_INVALID_ARG, "nsteps must be >= 0");
+    if (g->mem.empty()) return TEUK_OK;
+    const size_t cap = (size_t)g->cap;
+    for (int64_t n = 0; n < nsteps; ++n) {
+        for (int stage = 1; stage <= 3; ++stage) {
+            for (int c = 0; c < 4; ++c) {
+                if (g->cls_n[c] == 0) continue;
+                const int e = launch_group_stage(g->d_args + (stage - 1) * cap + g->cls_first[c],
+                                                 g->d_start + c * (cap + 1), g->cls_n[c], g->cls_tiles[c],
+                                                 g->cls_grid[c], stage, c, g->stream);
+                if (e) return gfail(g, TEUK_ERR_DEVICE, std::string("group stage launch: ") +
+                                                           hipGetErrorString((hipError_t)e));
+            }
+        }
+        for (teuk_solver* h : g->mem) {
+            ++h->steps;
+            if (h->cfg.extract_every > 0 && h->steps % h->cfg.extract_every == 0) {
+                teuk_status st = record_sample(h);
+                if (st != TEUK_OK) return gfail(g, st, h->err);
+            }
+        }
+    }
+    return TEUK_OK;
+}
+
+teuk_status teuk_group_info(const teuk_group* g, teuk_group_info_t* info)
+{
+    if (!g) return gfail(nullptr, TEUK_ERR_INVALID_ARG, "group is NULL");
+    if (!info) return TEUK_ERR_INVALID_ARG;
+    info->members = (int32_t)g->mem.size();
+    info->classes = 0;
+    info->workgroups = 0;
+    info->tiles = 0;
+    info->units = 0;
+    for (int c = 0; c < 4; ++c) {
+        info->classes += g->cls_n[c] > 0;
+        info->workgroups += g->cls_grid[c];
+        info->tiles += g->cls_tiles[c];
+        info->units += g->cls_units[c];
+    }
+    info->points = g->points;
+    return TEUK_OK;
+}
+
+void teuk_group_destroy(teuk_group* g)
+{
+    if (!g) return;
+    (void)hipStreamSynchronize(g->stream);
+    for (teuk_solver* h : g->mem) h->group = nullptr;
+    if (g->d_args) (void)hipFree(g->d_args);
+    if (g->d_start) (void)hipFree(g->d_start);
+    delete g;
+}
+
+const char* teuk_group_last_error(const teuk_group* g)
+{
+    return g ? g->err.c_str() : g_group_err.c_str();
 }
 
 }  // extern "C"

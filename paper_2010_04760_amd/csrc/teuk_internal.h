@@ -47,6 +47,12 @@ int stage_grid(int weight_prec, bool first);
 // Launchers (all asynchronous on `stream`; they return the hipError_t as int).
 // stage: 1 = first SSP stage, 2/3 = later stages, 0 = write F(u) only.
 int launch_stage(const StageArgs& a, int stage, int weight_prec, void* stream);
+// One stage (1, 2 or 3) of several solves in one launch of `grid` workgroups:
+// args[0..nmem) are the members' stage arguments (segs = theta segments per
+// strip), start[0..nmem] the prefix sums of their tile counts (nstrips * segs
+// each), tiles = start[nmem].
+int launch_group_stage(const StageArgs* args, const long long* start, int nmem, long long tiles, int grid,
+                       int stage, int weight_prec, void* stream);
 int launch_dt_bound(const double* rtab, const double* ttab, int nr, int nth, double dx, double dth,
                     unsigned long long* cell, void* stream);
 int launch_guard(const double* u, long long n, int* flag, void* stream);

@@ -135,17 +135,23 @@ struct Weno<TEUK_W_FP64> {
 // and keeps every intermediate in [0, 1] whatever the magnitude of the data.
 // rho_k = 1 where tau_k equals tau_min (also when both are zero).
 
-// Arithmetic in the low format: every result rounded to it.
+// Arithmetic in the low format: every result rounded to it.  ratio(a, b) is
+// a / b for 0 <= a < b.  In the 16-bit formats it is a true division: after
+// the power-of-two scaling eps can underflow to zero, so a flat stencil gives
+// tau_min = 0 next to a tau_k below 2^-16 whose reciprocal overflows, and
+// 0 * inf would poison the weights.  In FP32, tau_k >= eps keeps 1/tau_k finite.
 struct LowF32 {
     typedef float T;
     __device__ static T cvt(float x) { return x; }
     __device__ static T rcp(T x) { return __builtin_amdgcn_rcpf(x); }
+    __device__ static T ratio(T a, T b) { return a * __builtin_amdgcn_rcpf(b); }
     __device__ static float f(T x) { return x; }
 };
 struct LowF16 {
     typedef _Float16 T;
     __device__ static T cvt(float x) { return (_Float16)x; }
     __device__ static T rcp(T x) { return (_Float16)1.0 / x; }
+    __device__ static T ratio(T a, T b) { return a / b; }
     __device__ static float f(T x) { return (float)x; }
 };
 // BF16 arithmetic: compute in FP32 and round each result to BF16 (round to
@@ -166,6 +172,7 @@ struct LowBF16 {
     typedef Bf16Val T;
     __device__ static T cvt(float x) { return {bf16_round(x)}; }
     __device__ static T rcp(T x) { return {bf16_round(1.0f / x.v)}; }
+    __device__ static T ratio(T a, T b) { return {bf16_round(a.v / b.v)}; }
     __device__ static float f(T x) { return x.v; }
 };
 
@@ -198,9 +205,9 @@ __device__ __forceinline__ void low_weights(double d0, double d1, double d2, dou
     T tm = t0 < t1 ? t0 : t1;
     tm = t2 < tm ? t2 : tm;
     const T one = L::cvt(1.0f);
-    const T r0 = t0 == tm ? one : tm * L::rcp(t0);
-    const T r1 = t1 == tm ? one : tm * L::rcp(t1);
-    const T r2 = t2 == tm ? one : tm * L::rcp(t2);
+    const T r0 = t0 == tm ? one : L::ratio(tm, t0);
+    const T r1 = t1 == tm ? one : L::ratio(tm, t1);
+    const T r2 = t2 == tm ? one : L::ratio(tm, t2);
     const T a0 = L::cvt(0.1f) * (r0 * r0);
     const T a1 = L::cvt(0.6f) * (r1 * r1);
     const T a2 = L::cvt(0.3f) * (r2 * r2);
@@ -435,22 +442,68 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
 // it at the same moment (both start there, or both end there), and segment i
 // of neighbouring strips -- which share the radial halo -- march the same rows
 // in step, so the shared lines are read from HBM once and hit in L2 for the
-// second reader.  Ranks are dealt so that each XCD (which receives every
-// eighth workgroup id) owns a contiguous block of ranks, i.e. whole strips.
+// second reader.
 template <int WP, int kMode>
-__global__ __launch_bounds__(kWave) void stage_kernel(StageArgs A)
+__device__ __forceinline__ void run_tile(const StageArgs& A, double (*s)[4][kRow], int rank)
 {
-    __shared__ double s[2][4][kRow];
-    const int G = (int)gridDim.x;
-    const int bid = (int)blockIdx.x;
-    const int xcd = bid & 7, loc = bid >> 3;
-    const int q8 = G >> 3, r8 = G & 7;
-    const int rank = xcd * q8 + (xcd < r8 ? xcd : r8) + loc;
     const int strip = rank / A.segs;
     const int seg = rank - strip * A.segs;
     const int k0 = (int)((long long)A.nth * seg / A.segs);
     const int k1 = (int)((long long)A.nth * (seg + 1) / A.segs);
     if (k1 > k0) march_strip<WP, kMode>(A, s, strip, k0, k1, (seg & 1) ? -1 : 1);
+}
+
+// Ranks are dealt so that each XCD (which receives every eighth workgroup id)
+// owns a contiguous block of ranks, i.e. whole strips and their neighbours.
+__device__ __forceinline__ int xcd_rank(int bid, int G)
+{
+    const int xcd = bid & 7, loc = bid >> 3;
+    const int q8 = G >> 3, r8 = G & 7;
+    return xcd * q8 + (xcd < r8 ? xcd : r8) + loc;
+}
+
+template <int WP, int kMode>
+__global__ __launch_bounds__(kWave) void stage_kernel(StageArgs A)
+{
+    __shared__ double s[2][4][kRow];
+    run_tile<WP, kMode>(A, s, xcd_rank((int)blockIdx.x, (int)gridDim.x));
+}
+
+// One stage of several independent solves in one launch.  Member m is cut
+// into tiles of one radial strip by one theta segment (args[m].segs segments
+// per strip) and owns the tile numbers [start[m], start[m+1]), numbered
+// segment by segment with the strip index fastest; args[m] holds its buffers,
+// tables, grid and dt.  Workgroup `rank` takes the tiles rank, rank + G,
+// rank + 2G, ...: at any moment the workgroups in flight hold consecutive
+// tiles, i.e. neighbouring strips of the same theta segment, which march the
+// same rows together -- their reads of a row are one contiguous stretch of
+// each plane, and the radial halo they share is read once into L2.  Even
+// segments march upward and odd ones downward, so the two tiles that share a
+// boundary row meet there at the end of their march.  With G equal to the
+// tile count every workgroup runs one tile.  A tile runs exactly the
+// single-solve code.
+template <int WP, int kMode>
+__global__ __launch_bounds__(kWave) void group_stage_kernel(const StageArgs* __restrict__ args,
+                                                            const long long* __restrict__ start, int nmem,
+                                                            long long tiles)
+{
+    __shared__ double s[2][4][kRow];
+    const int G = (int)gridDim.x;
+    for (long long t = xcd_rank((int)blockIdx.x, G); t < tiles; t += G) {
+        int lo = 0, hi = nmem - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (start[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const StageArgs A = args[lo];
+        const int local = (int)(t - start[lo]);
+        const int seg = local / A.nstrips;
+        const int strip = local - seg * A.nstrips;
+        const int k0 = (int)((long long)A.nth * seg / A.segs);
+        const int k1 = (int)((long long)A.nth * (seg + 1) / A.segs);
+        if (k1 > k0) march_strip<WP, kMode>(A, s, strip, k0, k1, (seg & 1) ? -1 : 1);
+    }
 }
 
 // ---------------------------------------------------------------- stability bound
@@ -578,6 +631,32 @@ int launch_stage(const StageArgs& a, int stage, int weight_prec, void* stream)
         return (int)hipErrorInvalidValue;
     }
 #undef TEUK_LAUNCH
+    return (int)hipGetLastError();
+}
+
+int launch_group_stage(const StageArgs* args, const long long* start, int nmem, long long tiles, int grid,
+                       int stage, int weight_prec, void* stream)
+{
+    if (nmem < 1 || tiles < 1 || grid < 1 || stage < 1 || stage > 3) return (int)hipErrorInvalidValue;
+    const dim3 g((unsigned)grid), block(kWave);
+    hipStream_t st = (hipStream_t)stream;
+    (void)hipGetLastError();
+#define TEUK_GLAUNCH(W)                                                                                         \
+    case W:                                                                                                    \
+        if (stage == 1)                                                                                        \
+            hipLaunchKernelGGL((group_stage_kernel<W, kStageFirst>), g, block, 0, st, args, start, nmem, tiles); \
+        else                                                                                                   \
+            hipLaunchKernelGGL((group_stage_kernel<W, kStageLater>), g, block, 0, st, args, start, nmem, tiles); \
+        break;
+    switch (weight_prec) {
+        TEUK_GLAUNCH(TEUK_W_FP64)
+        TEUK_GLAUNCH(TEUK_W_FP32)
+        TEUK_GLAUNCH(TEUK_W_FP16)
+        TEUK_GLAUNCH(TEUK_W_BF16)
+    default:
+        return (int)hipErrorInvalidValue;
+    }
+#undef TEUK_GLAUNCH
     return (int)hipGetLastError();
 }
 

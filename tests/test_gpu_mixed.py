@@ -86,3 +86,23 @@ def test_c1_waveform_error_against_fp64_oracle(prec, c1_reference):
     err = np.linalg.norm(w - wref) / np.linalg.norm(wref)
     say("C1", prec, "waveform rel L2", err)
     assert err <= WAVE_BAR[prec], err
+
+
+@pytest.mark.parametrize("prec", LOW)
+def test_flat_stencil_next_to_a_jump_stays_finite(prec):
+    """A flat sub-stencil beside a large jump: after the power-of-two scaling of
+    the 16-bit paths eps underflows to zero, so tau_min = 0 while a
+    neighbouring tau_k is tiny but nonzero.  The weights must stay finite (the
+    ratio tau_min / tau_k is formed without the reciprocal of tau_k)."""
+    say("case flat stencil beside a jump", prec)
+    prob = S.Problem(0, 0, 0.5, 200, 8, -20.0, 40.0)
+    prof = np.zeros(prob.nr)
+    prof[100] = 2.0
+    prof[101:] = 1000.0
+    u = np.zeros((4, prob.nth, prob.nr))
+    for p in range(4):
+        u[p] = prof[None, :] * (1.0 + 0.1 * p)
+    F64 = rhs(prob, u, "fp64")
+    Flo = rhs(prob, u, prec)
+    assert np.all(np.isfinite(Flo))
+    assert np.max(np.abs(Flo - F64)) <= 0.1 * np.max(np.abs(F64))

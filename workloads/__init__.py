@@ -141,3 +141,20 @@ def batch_workloads(n: int = 64, seed0: int = 1000, steps: int = 2000) -> List[W
         out.append(Workload(f"batch[{i}]", s=s, m=m, a=a, nr=nr, nth=nth, x_min=-200.0, x_max=400.0,
                             steps=steps, seed=seed0 + i, angular="lowest", x_e=30.0, every=10))
     return out
+
+
+def serving_requests(n: int = 32, seed: int = 5, seed0: int = 2000) -> List[Workload]:
+    """Requests of the served workload: solves drawn as in `batch_workloads`
+    (per-request seeds seed0 + i), with a step count ~ U{5000..50000} per
+    request drawn from `seed`."""
+    rng = np.random.default_rng(seed)
+    steps = rng.integers(5000, 50001, size=n)
+    base = batch_workloads(n, seed0=seed0)
+    return [replace(w, name=f"request[{i}]", steps=int(steps[i])) for i, w in enumerate(base)]
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = 5) -> np.ndarray:
+    """Arrival times (seconds from the start) of a Poisson process of the given
+    rate: cumulative sums of exponential gaps drawn from `seed`."""
+    rng = np.random.default_rng(seed + 7919)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
