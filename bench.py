@@ -17,6 +17,9 @@ and the FP64 CPU oracle timed on a bounded sample of the workload on the host
 cores.
 
 Other workloads (one JSON line each):
+  --workload C3   s = 0, m = 0 extremal Kerr on 16384 x 128, 200000 steps, with
+                  FP64 / FP32 / FP16 / BF16 weights: speed, waveform error and
+                  late-time tail index against FP64.
   --workload C4   64 independent solves of uneven size advanced together
                   through the group extension (FP32 weights, 2000 steps).
   --workload C5   Poisson arrivals of such solves served by continuous
@@ -174,6 +177,72 @@ def bench_single(args, torch, T, W):
     return out
 
 
+# ----------------------------------------------------------------------------- C3: precision sweep
+def local_index(t, y):
+    """p(t) = t (dy/dt) / y by centred differences of a sampled series."""
+    return t[1:-1] * (y[2:] - y[:-2]) / (t[2:] - t[:-2]) / y[1:-1]
+
+
+def bench_sweep(args, torch, T, W):
+    wl = W.C3
+    steps = wl.steps if args.steps is None else args.steps
+    u0 = W.gaussian_pulse(wl)
+    stream = torch.cuda.current_stream()
+    k_star = wl.nth // 4                      # fixed polar node for the tail (theta ~ pi/4)
+    runs = {}
+    for wp in ("fp64", "fp32", "fp16", "bf16"):
+        sv = T.Solver(solver_config(T, wl, wp, steps), stream=stream)
+        sv.set_initial(u0)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        log(f"C3 {wp}: {steps} steps")
+        ev0.record(stream)
+        sv.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        sec = ev0.elapsed_time(ev1) / 1e3
+        sv.check_finite()
+        t, w = sv.waveform()
+        dt = sv.info().dt
+        sv.close()
+        runs[wp] = (sec, t, w, dt)
+        log(f"C3 {wp}: {sec:.2f} s")
+    pu = 3.0 * wl.points * steps
+    sec64, t, w64, dt = runs["fp64"]
+    lo, hi = 200.0, min(800.0, t[-1])
+    win = (t >= lo) & (t <= hi)
+    late = (t >= 0.75 * hi) & (t <= hi)
+
+    def tail(w):
+        y = w[:, k_star, 0]
+        p = local_index(t, y)
+        tm = t[1:-1]
+        sel = (tm >= 0.75 * hi) & (tm <= hi)
+        return float(np.mean(p[sel])), float(p[np.searchsorted(tm, hi) - 1])
+
+    p64 = tail(w64)
+    per = {}
+    for wp, (sec, _, w, _) in runs.items():
+        pm, pe = tail(w)
+        err = float(np.linalg.norm(w[win] - w64[win]) / np.linalg.norm(w64[win]))
+        err_late = float(np.linalg.norm(w[late] - w64[late]) / np.linalg.norm(w64[late]))
+        per[wp] = {"value": pu / sec, "seconds": sec, "speedup_vs_fp64": sec64 / sec,
+                   "waveform_rel_l2_vs_fp64": err, "late_rel_l2_vs_fp64": err_late,
+                   "tail_index_mean": pm, "tail_index_end": pe, "tail_index_diff_vs_fp64": pm - p64[0]}
+    return {
+        "metric": METRIC, "value": pu / sec64, "unit": "point-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": 0, "ms_per_step": sec64 / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl.name, "nr": wl.nr, "ntheta": wl.nth, "s": wl.s, "m": wl.m, "a": wl.a,
+                   "dt": dt, "x_extract": wl.x_e, "theta_star": float((k_star + 0.5) * np.pi / wl.nth),
+                   "window": [lo, hi], "reference": "FP64 GPU run (the oracle checks it at this size for "
+                                                    "a few steps; the full run is beyond the host)"},
+        "roofline": roofline(wl.points, sec64 / (3 * steps), None),
+        "per_dtype": per,
+    }
+
+
 # ----------------------------------------------------------------------------- C4: batched solves
 def bench_batched(args, torch, T, W):
     mix = W.batch_workloads()
@@ -291,8 +360,9 @@ def bench_serving(args, torch, T, W):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="C2", choices=["C2", "C4", "C5"])
-    ap.add_argument("--steps", type=int, default=None, help="timed SSP-RK3 steps (C2: 20000, C4: 2000)")
+    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "C5"])
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed SSP-RK3 steps (C2: 20000, C3: 200000, C4: 2000)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (C2: 100, C4: 20)")
     ap.add_argument("--weights", default=None, choices=["fp64", "fp32", "fp16", "bf16"],
                     help="WENO weight precision (C2: fp64, C4/C5: fp32)")
@@ -324,7 +394,7 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
-    fn = {"C2": bench_single, "C4": bench_batched, "C5": bench_serving}[args.workload]
+    fn = {"C2": bench_single, "C3": bench_sweep, "C4": bench_batched, "C5": bench_serving}[args.workload]
     out = fn(args, torch, T, W)
     print(json.dumps(out), flush=True)
 

@@ -135,6 +135,27 @@ def test_c2_grid_full_size(nsteps):
     say("C2 errors", errs)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c3_grid_full_size(prec):
+    """The extremal-Kerr sweep grid (16384 x 128, a = M) at full size, 3 steps:
+    FP64 weights against the oracle to the parity bar; FP32 weights against
+    the oracle to 1e-6 (the reduced-precision bar)."""
+    wl = W.C3
+    say("case C3 full grid", wl.name, prec)
+    prob = S.Problem(wl.s, wl.m, wl.a, wl.nr, wl.nth, wl.x_min, wl.x_max)
+    o = S.TeukOracle(prob)
+    dt = o.dt_bound(0.5)
+    u0 = W.gaussian_pulse(wl)
+    ref, _ = o.evolve(u0, dt, 3)
+    got = run_gpu(cfg_for(prob, dt, weight_prec=prec), u0, 3)
+    if prec == "fp64":
+        errs = assert_parity(got, ref, what="C3")
+    else:
+        errs = state_error(got, ref)
+        assert errs <= 1e-6, errs
+    say("C3 errors", errs)
+
+
 def test_launch_shape_invariance():
     say("case rows invariance")
     prob = S.Problem(-2, 2, 0.999, 300, 37, -50.0, 80.0)
