@@ -151,7 +151,12 @@ def ssprk3_step(u0, dt, rhs):
 # ----------------------------------------------------------------------------- Teukolsky
 @dataclass
 class Problem:
-    """A chart-T solve: background (M, a), field (s, m) and the grid."""
+    """One solve: background (M, a), field (s, m), chart and grid.
+
+    chart "T": x = r_* (tortoise); chart "H": x = rho, the compactified
+    hyperboloidal radius with parameter S (paper Sec. 2.2).  In both charts
+    the radial nodes are x_j = x_min + j (x_max - x_min)/(nr - 1).
+    """
     s: int
     m: int
     a: float
@@ -161,6 +166,8 @@ class Problem:
     x_max: float
     M: float = 1.0
     eps: float = 1e-6
+    chart: str = "T"
+    S: float = 20.0
 
     @property
     def dx(self):
@@ -188,21 +195,27 @@ class TeukOracle:
     def __init__(self, prob: Problem):
         self.prob = prob
         x = prob.x()
-        self.r, self.y, self.Delta = coeffs.r_of_tortoise(x, prob.M, prob.a)
         th = prob.theta()
-        R = self.r[None, :]
-        D = self.Delta[None, :]
-        T = th[:, None]
-        c = coeffs.first_order_coefficients(R, D, T, prob.M, prob.a, prob.s, prob.m)
-        shp = (prob.nth, prob.nr)
-        f = lambda v: np.ascontiguousarray(np.broadcast_to(v, shp), dtype=np.float64)
-        self.tab = {
-            "lam1": f(c["lam1"]), "lam2": f(c["lam2"]),
-            "m3r": f(c["m3"].real), "m3i": f(c["m3"].imag),
-            "btr": f(c["Bt"].real), "bti": f(c["Bt"].imag),
-            "cr": f(c["C"].real), "ci": f(c["C"].imag),
-            "ath": f(c["Ath"]), "bth": f(c["Bth"]),
-        }
+        if prob.chart == "H":
+            from . import hyperboloidal as hyp
+            self.r = x * prob.S / (prob.S - x)
+            tab = hyp.first_order_tables(x, th, prob.M, prob.a, prob.s, prob.m, prob.S)
+            self.tab = {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in tab.items()}
+        else:
+            self.r, self.y, self.Delta = coeffs.r_of_tortoise(x, prob.M, prob.a)
+            R = self.r[None, :]
+            D = self.Delta[None, :]
+            T = th[:, None]
+            c = coeffs.first_order_coefficients(R, D, T, prob.M, prob.a, prob.s, prob.m)
+            shp = (prob.nth, prob.nr)
+            f = lambda v: np.ascontiguousarray(np.broadcast_to(v, shp), dtype=np.float64)
+            self.tab = {
+                "lam1": f(c["lam1"]), "lam2": f(c["lam2"]),
+                "m3r": f(c["m3"].real), "m3i": f(c["m3"].imag),
+                "btr": f(c["Bt"].real), "bti": f(c["Bt"].imag),
+                "cr": f(c["C"].real), "ci": f(c["C"].imag),
+                "ath": f(c["Ath"]), "bth": f(c["Bth"]),
+            }
         self._s = _OracleTeuk(prob.nr, prob.nth, prob.dx, prob.dth, prob.eps, prob.parity(),
                               *[ptr(self.tab[n]) for n in ("lam1", "lam2", "m3r", "m3i", "btr",
                                                            "bti", "cr", "ci", "ath", "bth")])
@@ -230,6 +243,21 @@ class TeukOracle:
     def extract_index(self, x_e):
         p = self.prob
         return int(np.floor((x_e - p.x_min) / p.dx + 0.5))
+
+    def horizon(self, u):
+        """Phi and d_rho Phi on the horizon rho_H = S r+ / (r+ + S) (chart H),
+        per theta row, by 4-point Lagrange interpolation on the nodes around it.
+        Returns complex arrays (Phi_H[nth], dPhi_H[nth])."""
+        from . import hyperboloidal as hyp
+        p = self.prob
+        rp, _ = coeffs.horizons(p.M, p.a)
+        rho_h = p.S * rp / (rp + p.S)
+        j = int(np.floor((rho_h - p.x_min) / p.dx))
+        xi = (rho_h - (p.x_min + j * p.dx)) / p.dx
+        w, dw = hyp.horizon_weights(xi)
+        ph = u[0] + 1j * u[1]
+        win = ph[:, j - 1:j + 3]
+        return win @ w, (win @ dw) / p.dx
 
     def evolve(self, u0, dt, nsteps, x_e=None, every=0, max_samples=0):
         """Run nsteps SSP-RK3 steps.  Returns (u, wave[n][nth][2] or None)."""
