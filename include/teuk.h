@@ -64,8 +64,15 @@ typedef enum {
     TEUK_ERR_CAPACITY = -7        /* output array smaller than the data       */
 } teuk_status;
 
-/* Radial chart.  Only the tortoise chart (x = r_*) is offered in ABI v1. */
-enum { TEUK_CHART_TORTOISE = 0 };
+/* Radial chart.
+ *   TEUK_CHART_TORTOISE:     x = r_* (Sec. 2.2), Psi = exp(i m phi~) r^-(2s+1) Phi(t, x, theta).
+ *   TEUK_CHART_HYPERBOLOIDAL: x = rho = r/(1 + r/S), time tau = t~ - r^2/(r+S) + 4M ln(S/(r+S))
+ *                            with t~ the ingoing-Kerr time (Sec. 2.2), and
+ *                            Psi = exp(i m phi~) r^-1 Delta^-s Phi(tau, rho, theta) (for s = -2
+ *                            the Phi = (r/Delta^2) Psi of Sec. 4).  The grid reaches through
+ *                            the horizon towards null infinity (x_max < S).  Each row is
+ *                            upwinded by the sign of its own speed at the point. */
+enum { TEUK_CHART_TORTOISE = 0, TEUK_CHART_HYPERBOLOIDAL = 1 };
 
 /* Precision of the WENO smoothness indicators and nonlinear weights
  * (Sec. 3.1.3).  The six stencil differences, the candidate fluxes and
@@ -79,23 +86,28 @@ enum {
     TEUK_X_TIMES = 2,     /* [n] times of the waveform samples                        */
     TEUK_X_COEFFS = 3,    /* [TEUK_NCOEF][ntheta][nr] per-point coefficients as the
                              device evaluates them (diagnostic)                       */
-    TEUK_X_RHS = 4        /* [4][ntheta][nr] F(u^n) = -(M d_x u + L u + A u) of the
+    TEUK_X_RHS = 4,       /* [4][ntheta][nr] F(u^n) = -(M d_x u + L u + A u) of the
                              current state, by the stage kernel (diagnostic)           */
+    TEUK_X_HORIZON = 5    /* [n][ntheta][4] (Phi_R, Phi_I, d_rho Phi_R, d_rho Phi_I) on the
+                             horizon rho_H = S r+/(r+ + S), oldest first, sampled with
+                             the waveform (hyperboloidal chart only)                  */
 };
 
 /* Per-point coefficients returned by TEUK_X_COEFFS / teuk_host_coefficients,
- * plane order: b, Re m3, Im m3, Re B~t, Im B~t, Re C~, Im C~, A~thth, B~th, where
- *   d_t Phi = pi - b d_x Phi
- *   d_t pi  = b d_x pi - m3 d_x Phi + B~t pi + A~thth Phi_thth + B~th Phi_th + C~ Phi
- * (the paper's M, A, L entries: m31 = Re m3, m32 = -Im m3, a31 = -Re C~,
- *  a32 = Im C~, a33 = -Re B~t, a34 = Im B~t, l31 = -(A~thth d_thth + B~th d_th)). */
-#define TEUK_NCOEF 9
+ * plane order: lam1, Re m3, Im m3, Re B~t, Im B~t, Re C~, Im C~, A~thth, B~th, lam2,
+ * where (x the chart's radial coordinate, t its time)
+ *   d_t Phi = pi - lam1 d_x Phi
+ *   d_t pi  = -lam2 d_x pi - m3 d_x Phi + B~t pi + A~thth Phi_thth + B~th Phi_th + C~ Phi
+ * (the paper's M, A, L entries: M11 = lam1, M33 = lam2, m31 = Re m3, m32 = -Im m3,
+ *  a31 = -Re C~, a32 = Im C~, a33 = -Re B~t, a34 = Im B~t, l31 = -(A~thth d_thth + B~th d_th)).
+ * Chart T: lam1 = b = (r^2+a^2)/Sigma > 0 and lam2 = -b. */
+#define TEUK_NCOEF 10
 
 typedef struct {
     int32_t abi_version;     /* must equal TEUK_ABI_VERSION                          */
     int32_t s;               /* spin weight, |s| <= 2                                 */
     int32_t m;               /* azimuthal number, |m| <= 8                            */
-    int32_t chart;           /* TEUK_CHART_TORTOISE                                   */
+    int32_t chart;           /* TEUK_CHART_*                                          */
     int32_t nr;              /* radial points, 7 <= nr <= 2^24                         */
     int32_t ntheta;          /* polar points, 2 <= ntheta <= 65536                     */
     int32_t weight_prec;     /* TEUK_W_*                                              */
@@ -104,12 +116,15 @@ typedef struct {
     int32_t workgroups;      /* stage-kernel workgroups; 0 = all the GPU holds at once */
     double M;                /* black-hole mass (> 0)                                  */
     double a;                /* spin, 0 <= a <= M                                      */
-    double x_min, x_max;     /* radial range of x = r_* (x_min < x_max)                */
+    double x_min, x_max;     /* radial range of x (r_* or rho; x_min < x_max)          */
     double dt;               /* > 0: time step used as given; <= 0: cfl * stability bound */
     double cfl;              /* used when dt <= 0 (e.g. 0.5)                           */
     double weno_eps;         /* epsilon of the WENO weights (e.g. 1e-6), in [1e-30, 1e30]
                                 (normal in FP32, so reduced-precision weights stay finite) */
     double x_extract;        /* waveform radius; the nearest grid node is sampled       */
+    double S;                /* hyperboloidal chart parameter (Sec. 2.2; e.g. 20); the
+                                grid needs 0 < x_min < rho_H < x_max < S, no node on the
+                                horizon, and one node below / two above it */
 } teuk_config;
 
 typedef struct {
@@ -173,6 +188,8 @@ teuk_status teuk_step(teuk_solver* h, int64_t nsteps);
  *   TEUK_X_STATE     4*ntheta*nr doubles
  *   TEUK_X_WAVEFORM  min(samples, max_samples)*ntheta*2 doubles, oldest first
  *   TEUK_X_TIMES     min(samples, max_samples) doubles
+ *   TEUK_X_HORIZON   min(samples, max_samples)*ntheta*4 doubles, oldest first
+ *                    (hyperboloidal chart; UNSUPPORTED in the tortoise chart)
  *   TEUK_X_COEFFS    TEUK_NCOEF*ntheta*nr doubles
  *   TEUK_X_RHS       4*ntheta*nr doubles (uses the stage scratch buffer; the
  *                    state is unchanged)

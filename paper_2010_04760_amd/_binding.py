@@ -31,10 +31,11 @@ TEUK_ERR_STATE = -4
 TEUK_ERR_NONFINITE = -5
 TEUK_ERR_UNSUPPORTED = -6
 TEUK_ERR_CAPACITY = -7
-TEUK_CHART_TORTOISE = 0
+TEUK_CHART_TORTOISE, TEUK_CHART_HYPERBOLOIDAL = 0, 1
 TEUK_W_FP64, TEUK_W_FP32, TEUK_W_FP16, TEUK_W_BF16 = 0, 1, 2, 3
-TEUK_X_STATE, TEUK_X_WAVEFORM, TEUK_X_TIMES, TEUK_X_COEFFS, TEUK_X_RHS = 0, 1, 2, 3, 4
-TEUK_NCOEF = 9
+TEUK_X_STATE, TEUK_X_WAVEFORM, TEUK_X_TIMES, TEUK_X_COEFFS, TEUK_X_RHS, TEUK_X_HORIZON = 0, 1, 2, 3, 4, 5
+TEUK_NCOEF = 10
+CHART = {"T": TEUK_CHART_TORTOISE, "H": TEUK_CHART_HYPERBOLOIDAL}
 WEIGHT_PREC = {"fp64": TEUK_W_FP64, "fp32": TEUK_W_FP32, "fp16": TEUK_W_FP16, "bf16": TEUK_W_BF16}
 
 _STATUS_NAMES = {0: "TEUK_OK", -1: "TEUK_ERR_INVALID_ARG", -2: "TEUK_ERR_OUT_OF_MEMORY", -3: "TEUK_ERR_DEVICE",
@@ -49,7 +50,7 @@ class teuk_config(ctypes.Structure):
                 ("max_samples", ctypes.c_int32), ("workgroups", ctypes.c_int32),
                 ("M", ctypes.c_double), ("a", ctypes.c_double), ("x_min", ctypes.c_double),
                 ("x_max", ctypes.c_double), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
-                ("weno_eps", ctypes.c_double), ("x_extract", ctypes.c_double)]
+                ("weno_eps", ctypes.c_double), ("x_extract", ctypes.c_double), ("S", ctypes.c_double)]
 
 
 class teuk_device_ctx(ctypes.Structure):
@@ -236,7 +237,7 @@ def teuk_group_last_error(g: int | None = None) -> str:
 def make_config(*, s: int, m: int, a: float, nr: int, ntheta: int, x_min: float, x_max: float,
                 M: float = 1.0, dt: float = 0.0, cfl: float = 0.5, weno_eps: float = 1e-6,
                 weight_prec="fp64", x_extract: float | None = None, extract_every: int = 0,
-                max_samples: int = 0, workgroups: int = 0) -> teuk_config:
+                max_samples: int = 0, workgroups: int = 0, chart="T", S: float = 20.0) -> teuk_config:
     c = teuk_default_config()
     c.s, c.m, c.a, c.M = int(s), int(m), float(a), float(M)
     c.nr, c.ntheta = int(nr), int(ntheta)
@@ -246,6 +247,8 @@ def make_config(*, s: int, m: int, a: float, nr: int, ntheta: int, x_min: float,
     c.extract_every, c.max_samples = int(extract_every), int(max_samples)
     c.x_extract = float(x_min if x_extract is None else x_extract)
     c.workgroups = int(workgroups)
+    c.chart = CHART[chart] if isinstance(chart, str) else int(chart)
+    c.S = float(S)
     return c
 
 
@@ -294,6 +297,15 @@ class Solver:
         w = teuk_extract(self.h, TEUK_X_WAVEFORM, ns * self.cfg.ntheta * 2).reshape(ns, self.cfg.ntheta, 2)
         t = teuk_extract(self.h, TEUK_X_TIMES, ns)
         return t, w
+
+    def horizon(self):
+        """Horizon samples (hyperboloidal chart): times and complex arrays
+        Phi_H[n][ntheta], dPhi_H[n][ntheta] (d_rho Phi) on rho_H."""
+        inf = self.info()
+        ns = min(inf.samples, self.cfg.max_samples) if self.cfg.extract_every > 0 else 0
+        h = teuk_extract(self.h, TEUK_X_HORIZON, ns * self.cfg.ntheta * 4).reshape(ns, self.cfg.ntheta, 4)
+        t = teuk_extract(self.h, TEUK_X_TIMES, ns)
+        return t, h[..., 0] + 1j * h[..., 1], h[..., 2] + 1j * h[..., 3]
 
     def rhs(self) -> np.ndarray:
         """F(u^n) as the stage kernel evaluates it (the state is unchanged)."""

@@ -23,7 +23,11 @@ struct teuk_solver {
     double* u[3] = {nullptr, nullptr, nullptr};   // u^n, u^(1), u^(2)
     double* rtab = nullptr;
     double* ttab = nullptr;
+    double* ctab = nullptr;                         // chart H per-point table
     double* wave = nullptr;
+    double* hwave = nullptr;                        // chart H horizon ring [samples][nth][4]
+    int j_h = 0;                                    // chart H: horizon between nodes j_h and j_h + 1
+    double hw[4] = {0, 0, 0, 0}, hdw[4] = {0, 0, 0, 0};   // horizon value / derivative weights
     unsigned long long* cell = nullptr;             // dt-bound reduction cell
     int* flag = nullptr;                            // non-finite flag
     double dx = 0, dth = 0, dt = 0, dt_bound = 0;
@@ -38,6 +42,8 @@ struct teuk_solver {
     std::string err;
 };
 
+constexpr int kClasses = 8;   // (weight precision, chart) pairs
+
 struct teuk_group {
     hipStream_t stream = nullptr;
     int device = 0;
@@ -46,11 +52,12 @@ struct teuk_group {
     int rows = 8;                                   // theta rows per tile (target)
     std::vector<teuk_solver*> mem;                  // insertion order
     StageArgs* d_args = nullptr;                    // [3][cap]: per stage, members by weight precision
-    long long* d_start = nullptr;                   // [4][cap + 1]: tile prefix sums per precision class
+    long long* d_start = nullptr;                   // [8][cap + 1]: tile prefix sums per (precision, chart) class
     std::vector<StageArgs> h_args;
     std::vector<long long> h_start;
-    int cls_first[4] = {0, 0, 0, 0}, cls_n[4] = {0, 0, 0, 0}, cls_grid[4] = {0, 0, 0, 0};
-    long long cls_tiles[4] = {0, 0, 0, 0}, cls_units[4] = {0, 0, 0, 0};
+    // launch classes: c = weight_prec + 4 * chart
+    int cls_first[kClasses] = {}, cls_n[kClasses] = {}, cls_grid[kClasses] = {};
+    long long cls_tiles[kClasses] = {}, cls_units[kClasses] = {};
     long long points = 0;
     std::string err;
 };
@@ -63,7 +70,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t u, rtab, ttab, wave, cells, total;
+    size_t u, rtab, ttab, ctab, wave, hwave, cells, total;
 };
 
 Layout layout_of(const teuk_config& c)
@@ -71,20 +78,55 @@ Layout layout_of(const teuk_config& c)
     Layout L;
     const size_t plane = (size_t)c.nr * (size_t)c.ntheta;
     L.u = align_up(4 * plane * sizeof(double));
-    L.rtab = align_up((size_t)kNRT * c.nr * sizeof(double));
-    L.ttab = align_up((size_t)kNTT * c.ntheta * sizeof(double));
+    const bool H = c.chart == TEUK_CHART_HYPERBOLOIDAL;
+    L.rtab = H ? 0 : align_up((size_t)kNRT * c.nr * sizeof(double));
+    L.ttab = H ? 0 : align_up((size_t)kNTT * c.ntheta * sizeof(double));
+    L.ctab = H ? align_up((size_t)kNCH * plane * sizeof(double)) : 0;
     const size_t ns = c.extract_every > 0 ? (size_t)c.max_samples : 0;
     L.wave = align_up(ns * (size_t)c.ntheta * 2 * sizeof(double));
+    L.hwave = H ? align_up(ns * (size_t)c.ntheta * 4 * sizeof(double)) : 0;
     L.cells = kAlign;
-    L.total = 3 * L.u + L.rtab + L.ttab + L.wave + L.cells;
+    L.total = 3 * L.u + L.rtab + L.ttab + L.ctab + L.wave + L.hwave + L.cells;
     return L;
+}
+
+// Horizon of the hyperboloidal chart between nodes j and j+1: 4-point Lagrange
+// weights on the nodes j-1 .. j+2 for the value (w) and the rho-derivative (dw,
+// divided by dx) at rho_H = S r+ / (r+ + S).  False if the stencil leaves the grid.
+bool horizon_stencil(const teuk_config& c, int* j, double* w, double* dw)
+{
+    const double d2 = c.M * c.M - c.a * c.a;
+    const double rp = c.M + (d2 > 0.0 ? std::sqrt(d2) : 0.0);
+    const double rho_h = c.S * rp / (rp + c.S);
+    const double dx = (c.x_max - c.x_min) / (c.nr - 1);
+    const double f = (rho_h - c.x_min) / dx;
+    if (!(f >= 1.0) || !(f < (double)(c.nr - 3))) return false;
+    const int jj = (int)std::floor(f);
+    const double xi = (rho_h - (c.x_min + dx * jj)) / dx;     // in [0, 1)
+    const double z[4] = {-1.0, 0.0, 1.0, 2.0};
+    for (int i = 0; i < 4; ++i) {
+        double num = 1.0, den = 1.0, dsum = 0.0;
+        for (int k = 0; k < 4; ++k) {
+            if (k == i) continue;
+            num *= xi - z[k];
+            den *= z[i] - z[k];
+            double prod = 1.0;                                 // d/dxi of the product, term k left out
+            for (int q = 0; q < 4; ++q)
+                if (q != i && q != k) prod *= xi - z[q];
+            dsum += prod;
+        }
+        w[i] = num / den;
+        dw[i] = dsum / den / dx;
+    }
+    *j = jj;
+    return true;
 }
 
 bool validate(const teuk_config* c, std::string& err)
 {
     if (!c) { err = "cfg is NULL"; return false; }
     if (c->abi_version != TEUK_ABI_VERSION) { err = "abi_version must be " + std::to_string(TEUK_ABI_VERSION); return false; }
-    if (c->chart != TEUK_CHART_TORTOISE) { err = "only the tortoise chart (TEUK_CHART_TORTOISE) is offered"; return false; }
+    if (c->chart != TEUK_CHART_TORTOISE && c->chart != TEUK_CHART_HYPERBOLOIDAL) { err = "chart must be a TEUK_CHART_* value"; return false; }
     if (c->s < -2 || c->s > 2) { err = "spin weight s must satisfy |s| <= 2"; return false; }
     if (c->m < -8 || c->m > 8) { err = "azimuthal number m must satisfy |m| <= 8"; return false; }
     if (c->nr < 7 || c->nr > (1 << 24)) { err = "nr must be in [7, 2^24]"; return false; }
@@ -103,6 +145,17 @@ bool validate(const teuk_config* c, std::string& err)
         if (!(c->x_extract >= c->x_min && c->x_extract <= c->x_max)) { err = "x_extract must lie in [x_min, x_max]"; return false; }
     }
     if (c->workgroups < 0) { err = "workgroups must be >= 0"; return false; }
+    if (c->chart == TEUK_CHART_HYPERBOLOIDAL) {
+        if (!(c->S > 0.0) || !std::isfinite(c->S)) { err = "S must be positive and finite"; return false; }
+        if (!(c->x_min > 0.0) || !(c->x_max < c->S)) { err = "hyperboloidal chart needs 0 < x_min and x_max < S"; return false; }
+        int jh;
+        double w[4], dw[4];
+        if (!horizon_stencil(*c, &jh, w, dw)) {
+            err = "hyperboloidal chart needs the horizon rho_H = S r+/(r+ + S) inside the grid with one node "
+                  "below and two above it";
+            return false;
+        }
+    }
     return true;
 }
 
@@ -111,7 +164,7 @@ bool validate(const teuk_config* c, std::string& err)
 // one so that neighbouring segments pair up, and at most one per theta row.
 int pick_segs(const teuk_config& c, int nstrips, int weight_prec, bool first)
 {
-    long long cap = c.workgroups > 0 ? c.workgroups : stage_grid(weight_prec, first);
+    long long cap = c.workgroups > 0 ? c.workgroups : stage_grid(weight_prec, first, c.chart);
     if (cap <= 0) return 0;
     long long segs = cap / nstrips;
     if (segs > c.ntheta) segs = c.ntheta;
@@ -159,6 +212,9 @@ teuk_status record_sample(teuk_solver* h)
     const long long slot = h->samples % h->cfg.max_samples;
     double* dst = h->wave + (size_t)slot * h->cfg.ntheta * 2;
     int e = launch_extract(h->u[0], h->plane, h->cfg.nr, h->cfg.ntheta, h->j_e, dst, h->stream);
+    if (!e && h->hwave)
+        e = launch_horizon(h->u[0], h->plane, h->cfg.nr, h->cfg.ntheta, h->j_h, h->hw, h->hdw,
+                           h->hwave + (size_t)slot * h->cfg.ntheta * 4, h->stream);
     if (e) return hip_fail(h, e, "extract launch");
     ++h->samples;
     return TEUK_OK;
@@ -178,6 +234,7 @@ void teuk_default_config(teuk_config* c)
     c->M = 1.0;
     c->cfl = 0.5;
     c->weno_eps = 1e-6;
+    c->S = 20.0;
 }
 
 size_t teuk_footprint_bytes(const teuk_config* cfg)
@@ -193,8 +250,10 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     *out = nullptr;
     std::string err;
     if (!validate(cfg, err)) return fail(nullptr, TEUK_ERR_INVALID_ARG, err);
-    std::vector<double> rtab, ttab;
-    if (!build_tables(*cfg, rtab, ttab, err)) return fail(nullptr, TEUK_ERR_INVALID_ARG, err);
+    const bool chartH = cfg->chart == TEUK_CHART_HYPERBOLOIDAL;
+    std::vector<double> rtab, ttab, ctab;
+    if (chartH ? !build_tables_H(*cfg, ctab, err) : !build_tables(*cfg, rtab, ttab, err))
+        return fail(nullptr, TEUK_ERR_INVALID_ARG, err);
 
     teuk_solver* h = new (std::nothrow) teuk_solver();
     if (!h) return fail(nullptr, TEUK_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -229,9 +288,12 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     }
     char* p = (char*)h->base;
     for (int i = 0; i < 3; ++i) { h->u[i] = (double*)p; p += L.u; }
-    h->rtab = (double*)p; p += L.rtab;
-    h->ttab = (double*)p; p += L.ttab;
+    h->rtab = L.rtab ? (double*)p : nullptr; p += L.rtab;
+    h->ttab = L.ttab ? (double*)p : nullptr; p += L.ttab;
+    h->ctab = L.ctab ? (double*)p : nullptr; p += L.ctab;
     h->wave = (double*)p; p += L.wave;
+    h->hwave = L.hwave ? (double*)p : nullptr; p += L.hwave;
+    if (chartH) (void)horizon_stencil(*cfg, &h->j_h, h->hw, h->hdw);
     h->cell = (unsigned long long*)p;
     h->flag = (int*)(p + 64);
 
@@ -249,10 +311,15 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     h->j_e = cfg->extract_every > 0 ? (int)std::floor((cfg->x_extract - cfg->x_min) / h->dx + 0.5) : 0;
     if (h->j_e > cfg->nr - 1) h->j_e = cfg->nr - 1;
 
-    int e = (int)hipMemcpyAsync(h->rtab, rtab.data(), rtab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
-    if (!e) e = (int)hipMemcpyAsync(h->ttab, ttab.data(), ttab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    int e = 0;
+    if (chartH) {
+        e = (int)hipMemcpyAsync(h->ctab, ctab.data(), ctab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    } else {
+        e = (int)hipMemcpyAsync(h->rtab, rtab.data(), rtab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
+        if (!e) e = (int)hipMemcpyAsync(h->ttab, ttab.data(), ttab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    }
     if (!e) e = (int)hipMemsetAsync(h->cell, 0, sizeof(unsigned long long), h->stream);
-    if (!e) e = launch_dt_bound(h->rtab, h->ttab, cfg->nr, cfg->ntheta, h->dx, h->dth, h->cell, h->stream);
+    if (!e) e = launch_dt_bound(h->rtab, h->ttab, h->ctab, cfg->nr, cfg->ntheta, h->dx, h->dth, h->cell, h->stream);
     unsigned long long bits = 0;
     if (!e) e = (int)hipMemcpyAsync(&bits, h->cell, sizeof(bits), hipMemcpyDeviceToHost, h->stream);
     if (!e) e = (int)hipStreamSynchronize(h->stream);
@@ -304,6 +371,7 @@ static StageArgs stage_args(const teuk_solver* h)
     StageArgs a;
     a.rtab = h->rtab;
     a.ttab = h->ttab;
+    a.ctab = h->ctab;
     a.plane = h->plane;
     a.nr = c.nr;
     a.nth = c.ntheta;
@@ -333,13 +401,13 @@ teuk_status teuk_step(teuk_solver* h, int64_t nsteps)
     for (int64_t n = 0; n < nsteps; ++n) {
         // u1 = u + dt F(u)
         a.uk = h->u[0]; a.un = h->u[0]; a.out = h->u[1]; a.ca = 0.0; a.cb = 1.0; a.segs = h->segs[0]; a.grid = h->nstrips * h->segs[0];
-        int e = launch_stage(a, 1, c.weight_prec, h->stream);
+        int e = launch_stage(a, 1, c.weight_prec, c.chart, h->stream);
         // u2 = 3/4 u + 1/4 (u1 + dt F(u1))
         if (!e) { a.uk = h->u[1]; a.un = h->u[0]; a.out = h->u[2]; a.ca = 0.75; a.cb = 0.25; a.segs = h->segs[1]; a.grid = h->nstrips * h->segs[1];
-                  e = launch_stage(a, 2, c.weight_prec, h->stream); }
+                  e = launch_stage(a, 2, c.weight_prec, c.chart, h->stream); }
         // u = 1/3 u + 2/3 (u2 + dt F(u2)), in place (u^n is read only at the own point)
         if (!e) { a.uk = h->u[2]; a.un = h->u[0]; a.out = h->u[0]; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0; a.segs = h->segs[1]; a.grid = h->nstrips * h->segs[1];
-                  e = launch_stage(a, 3, c.weight_prec, h->stream); }
+                  e = launch_stage(a, 3, c.weight_prec, c.chart, h->stream); }
         if (e) return hip_fail(h, e, "stage launch");
         ++h->steps;
         if (c.extract_every > 0 && h->steps % c.extract_every == 0) {
@@ -364,11 +432,16 @@ teuk_status teuk_extract(teuk_solver* h, int32_t what, double* out, size_t capac
     case TEUK_X_TIMES: need = (size_t)nsamp; break;
     case TEUK_X_COEFFS: need = (size_t)TEUK_NCOEF * h->plane; break;
     case TEUK_X_RHS: need = 4 * (size_t)h->plane; break;
+    case TEUK_X_HORIZON:
+        if (!h->hwave) return fail(h, TEUK_ERR_UNSUPPORTED, "horizon samples need the hyperboloidal chart and a waveform cadence");
+        need = (size_t)nsamp * c.ntheta * 4;
+        break;
     default: return fail(h, TEUK_ERR_INVALID_ARG, "unknown extract kind");
     }
     if (capacity < need) return fail(h, TEUK_ERR_CAPACITY, "output holds " + std::to_string(capacity) +
                                                               " doubles, need " + std::to_string(need));
-    if ((what == TEUK_X_STATE || what == TEUK_X_WAVEFORM || what == TEUK_X_RHS) && !h->have_init)
+    if ((what == TEUK_X_STATE || what == TEUK_X_WAVEFORM || what == TEUK_X_RHS || what == TEUK_X_HORIZON) &&
+        !h->have_init)
         return fail(h, TEUK_ERR_STATE, "no state: call teuk_set_initial first");
     int e = 0;
     teuk_status guard = TEUK_OK;
@@ -384,11 +457,19 @@ teuk_status teuk_extract(teuk_solver* h, int32_t what, double* out, size_t capac
             e = (int)hipMemcpyAsync(out + i * per, h->wave + slot * per, per * sizeof(double),
                                     hipMemcpyDeviceToHost, h->stream);
         }
+    } else if (what == TEUK_X_HORIZON) {
+        const long long first = h->samples - nsamp;
+        const size_t per = (size_t)c.ntheta * 4;
+        for (long long i = 0; i < nsamp && !e; ++i) {
+            const long long slot = (first + i) % c.max_samples;
+            e = (int)hipMemcpyAsync(out + i * per, h->hwave + slot * per, per * sizeof(double),
+                                    hipMemcpyDeviceToHost, h->stream);
+        }
     } else if (what == TEUK_X_RHS) {
         // F(u^n) by the stage kernel itself, written into the u^(1) buffer
         // (scratch between steps), then copied out
         StageArgs a = stage_args(h);
-        e = launch_stage(a, 0, h->cfg.weight_prec, h->stream);
+        e = launch_stage(a, 0, h->cfg.weight_prec, h->cfg.chart, h->stream);
         if (!e) e = (int)hipMemcpyAsync(out, h->u[1], need * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     } else if (what == TEUK_X_TIMES) {
         const long long first = h->samples - nsamp;
@@ -396,7 +477,7 @@ teuk_status teuk_extract(teuk_solver* h, int32_t what, double* out, size_t capac
     } else {
         double* tmp = nullptr;
         e = (int)hipMalloc(&tmp, need * sizeof(double));
-        if (!e) e = launch_coef_dump(h->rtab, h->ttab, c.nr, c.ntheta, tmp, h->stream);
+        if (!e) e = launch_coef_dump(h->rtab, h->ttab, h->ctab, c.nr, c.ntheta, tmp, h->stream);
         if (!e) e = (int)hipMemcpyAsync(out, tmp, need * sizeof(double), hipMemcpyDeviceToHost, h->stream);
         if (!e) e = (int)hipStreamSynchronize(h->stream);
         if (tmp) (void)hipFree(tmp);
@@ -450,6 +531,14 @@ teuk_status teuk_host_coefficients(const teuk_config* cfg, double* out, size_t c
     if (!out) return fail(nullptr, TEUK_ERR_INVALID_ARG, "out is NULL");
     const size_t n = (size_t)cfg->nr * cfg->ntheta;
     if (capacity < TEUK_NCOEF * n) return fail(nullptr, TEUK_ERR_CAPACITY, "out too small");
+    if (cfg->chart == TEUK_CHART_HYPERBOLOIDAL) {
+        std::vector<double> ctab;
+        if (!build_tables_H(*cfg, ctab, err)) return fail(nullptr, TEUK_ERR_INVALID_ARG, err);
+        const int order[TEUK_NCOEF] = {kHLam1, kHM3r, kHM3i, kHBtr, kHBti, kHCr, kHCi, kHAth, kHBth, kHLam2};
+        for (int q = 0; q < TEUK_NCOEF; ++q)
+            std::memcpy(out + (size_t)q * n, ctab.data() + (size_t)order[q] * n, n * sizeof(double));
+        return TEUK_OK;
+    }
     std::vector<double> rtab, ttab;
     if (!build_tables(*cfg, rtab, ttab, err)) return fail(nullptr, TEUK_ERR_INVALID_ARG, err);
     const int nr = cfg->nr, nth = cfg->ntheta;
@@ -470,6 +559,7 @@ teuk_status teuk_host_coefficients(const teuk_config* cfg, double* out, size_t c
             out[6 * n + i] = c.ci;
             out[7 * n + i] = c.ath;
             out[8 * n + i] = c.bth;
+            out[9 * n + i] = -c.b;
         }
     }
     return TEUK_OK;
@@ -504,14 +594,14 @@ static teuk_status group_upload(teuk_group* g)
     const int cap = g->cap;
     int idx = 0;
     g->points = 0;
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < kClasses; ++c) {
         g->cls_first[c] = idx;
         g->cls_n[c] = 0;
         long long* start = &g->h_start[(size_t)c * (cap + 1)];
         long long tiles = 0, units = 0;
         start[0] = 0;
         for (teuk_solver* h : g->mem) {
-            if (h->cfg.weight_prec != c) continue;
+            if (h->cfg.weight_prec + 4 * h->cfg.chart != c) continue;
             StageArgs a = stage_args(h);
             a.segs = group_segs(h->cfg.ntheta, g->rows);
             a.grid = 0;                                  // set per launch
@@ -564,7 +654,7 @@ teuk_status teuk_group_create(const teuk_device_ctx* ctx, int32_t max_members, i
     g->workgroups = workgroups;
     g->rows = rows_per_tile > 0 ? rows_per_tile : 8;
     g->h_args.assign(3 * (size_t)max_members, StageArgs{});
-    g->h_start.assign(4 * ((size_t)max_members + 1), 0);
+    g->h_start.assign(kClasses * ((size_t)max_members + 1), 0);
     int e = (int)hipMalloc(&g->d_args, g->h_args.size() * sizeof(StageArgs));
     if (!e) e = (int)hipMalloc(&g->d_start, g->h_start.size() * sizeof(long long));
     if (e) {
@@ -623,11 +713,11 @@ teuk_status teuk_group_step(teuk_group* g, int64_t nsteps)
     const size_t cap = (size_t)g->cap;
     for (int64_t n = 0; n < nsteps; ++n) {
         for (int stage = 1; stage <= 3; ++stage) {
-            for (int c = 0; c < 4; ++c) {
+            for (int c = 0; c < kClasses; ++c) {
                 if (g->cls_n[c] == 0) continue;
                 const int e = launch_group_stage(g->d_args + (stage - 1) * cap + g->cls_first[c],
                                                  g->d_start + c * (cap + 1), g->cls_n[c], g->cls_tiles[c],
-                                                 g->cls_grid[c], stage, c, g->stream);
+                                                 g->cls_grid[c], stage, c % 4, c / 4, g->stream);
                 if (e) return gfail(g, TEUK_ERR_DEVICE, std::string("group stage launch: ") +
                                                            hipGetErrorString((hipError_t)e));
             }
@@ -652,7 +742,7 @@ teuk_status teuk_group_info(const teuk_group* g, teuk_group_info_t* info)
     info->workgroups = 0;
     info->tiles = 0;
     info->units = 0;
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < kClasses; ++c) {
         info->classes += g->cls_n[c] > 0;
         info->workgroups += g->cls_grid[c];
         info->tiles += g->cls_tiles[c];

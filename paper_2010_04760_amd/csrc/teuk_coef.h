@@ -55,6 +55,18 @@ enum PolarRow : int {
     kNTT
 };
 
+// Chart-H per-point coefficient table, [kNCH][ntheta][nr] (streamed by the
+// stage kernel: the hyperboloidal coefficients have no cheap on-chip form).
+enum ChartHPlane : int {
+    kHLam1 = 0,  // lam1 = b, speed of the Phi rows
+    kHLam2,      // lam2, speed of the pi rows
+    kHM3r, kHM3i,
+    kHBtr, kHBti,
+    kHCr, kHCi,
+    kHAth, kHBth,
+    kNCH
+};
+
 struct PointCoef {
     double b, m3r, m3i, btr, bti, cr, ci, ath, bth;
 };

@@ -17,6 +17,10 @@ namespace teuk {
 bool build_tables(const teuk_config& c, std::vector<double>& rtab, std::vector<double>& ttab,
                   std::string& err);
 
+// Build the chart-H per-point table [kNCH][ntheta][nr] of teuk_coef.h for a
+// validated TEUK_CHART_HYPERBOLOIDAL configuration.
+bool build_tables_H(const teuk_config& c, std::vector<double>& ctab, std::string& err);
+
 // Points per radial strip of one stage workgroup (one wave of 64 lanes computes
 // 64 interface fluxes and 63 point updates).
 constexpr int kStripPoints = 63;
@@ -28,6 +32,7 @@ struct StageArgs {
     double* out;           // u^(k+1); may alias un (stage 3 writes in place)
     const double* rtab;    // radial table [kNRT][nr]
     const double* ttab;    // polar table [kNTT][nth]
+    const double* ctab;    // chart H: per-point table [kNCH][nth][nr] (null in chart T)
     long long plane;       // nth * nr
     int nr, nth;
     int nstrips;           // radial strips of kStripPoints
@@ -42,23 +47,27 @@ struct StageArgs {
 // Resident workgroup count of a stage-kernel instantiation on the current
 // device (0 if the weight precision is not built).  The launch uses
 // nstrips * segs workgroups with segs chosen from it.
-int stage_grid(int weight_prec, bool first);
+int stage_grid(int weight_prec, bool first, int chart);
 
 // Launchers (all asynchronous on `stream`; they return the hipError_t as int).
 // stage: 1 = first SSP stage, 2/3 = later stages, 0 = write F(u) only.
-int launch_stage(const StageArgs& a, int stage, int weight_prec, void* stream);
+int launch_stage(const StageArgs& a, int stage, int weight_prec, int chart, void* stream);
 // One stage (1, 2 or 3) of several solves in one launch of `grid` workgroups:
 // args[0..nmem) are the members' stage arguments (segs = theta segments per
 // strip), start[0..nmem] the prefix sums of their tile counts (nstrips * segs
 // each), tiles = start[nmem].
 int launch_group_stage(const StageArgs* args, const long long* start, int nmem, long long tiles, int grid,
-                       int stage, int weight_prec, void* stream);
-int launch_dt_bound(const double* rtab, const double* ttab, int nr, int nth, double dx, double dth,
-                    unsigned long long* cell, void* stream);
+                       int stage, int weight_prec, int chart, void* stream);
+int launch_dt_bound(const double* rtab, const double* ttab, const double* ctab, int nr, int nth, double dx,
+                    double dth, unsigned long long* cell, void* stream);
 int launch_guard(const double* u, long long n, int* flag, void* stream);
 int launch_extract(const double* u, long long plane, int nr, int nth, int j_e, double* wave_slot,
                    void* stream);
-int launch_coef_dump(const double* rtab, const double* ttab, int nr, int nth, double* out,
+int launch_coef_dump(const double* rtab, const double* ttab, const double* ctab, int nr, int nth, double* out,
                      void* stream);
+// Horizon sample: Phi and d_rho Phi from the nodes j_h-1 .. j_h+2 with value
+// weights w[4] and derivative weights dw[4] (divided by dx); slot is [nth][4].
+int launch_horizon(const double* u, long long plane, int nr, int nth, int j_h, const double* w, const double* dw,
+                   double* slot, void* stream);
 
 }  // namespace teuk

@@ -40,6 +40,10 @@ constexpr int kStageFirst = 0;    // out = u + dt F(u)
 constexpr int kStageLater = 1;    // out = ca u^n + cb (u^(k) + dt F(u^(k)))
 constexpr int kRhsOnly = 2;       // out = F(u)
 
+// Radial chart (TEUK_CHART_*).
+constexpr int kChartT = TEUK_CHART_TORTOISE;
+constexpr int kChartH = TEUK_CHART_HYPERBOLOIDAL;
+
 // 1/x to full FP64 precision: hardware estimate refined by two Newton steps.
 __device__ __forceinline__ double rcp64(double x)
 {
@@ -271,7 +275,14 @@ __device__ __forceinline__ void stb(double* base, unsigned off, double v)
 // k + 2 dir and of u^n at row k are already in flight and are consumed at the
 // end of the iteration, so each wave always has its next rows' memory traffic
 // overlapping its arithmetic.
-template <int WP, int kMode>
+//
+// Chart T: the Phi rows move with speed +b (f^+ fluxes), the pi rows with -b
+// (f^- fluxes), and the coefficients are rebuilt from the radial and polar
+// tables.  Chart H: the ten coefficients of the point are read from the
+// per-point table, and each row takes the flux side of the sign of its own
+// speed at the point (speed >= 0: f^+, speed < 0: f^-); a wave whose lanes
+// disagree computes both sides and each lane differences its own.
+template <int WP, int kMode, int kChart>
 __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][kRow], int strip, int k0, int k1,
                                             int dir)
 {
@@ -292,8 +303,10 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
     double* outp[4] = {A.out, A.out + P, A.out + 2 * P, A.out + 3 * P};
 
     double rt[kNRT];
+    if constexpr (kChart == kChartT) {
 #pragma unroll
-    for (int i = 0; i < kNRT; ++i) rt[i] = ldb(A.rtab + (size_t)i * nr, oc);
+        for (int i = 0; i < kNRT; ++i) rt[i] = ldb(A.rtab + (size_t)i * nr, oc);
+    }
     // The polar table is read-only for the whole launch: reading it through the
     // constant address space makes its (uniform) loads scalar.
     const __attribute__((address_space(4))) double* tt =
@@ -349,12 +362,15 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
         const int k = first + dir * i;
         const int b = i & 1;
         const size_t row = (size_t)k * nr;
-        // polar factors of the row: uniform, read before the vector loads are
-        // queued so that waiting for them never waits for the prefetch
-        const double sn2 = tt[kSn2 * nth + k];
-        const double cs = tt[kCs * nth + k];
-        const double cot = tt[kCot * nth + k];
-        const double th = tt[kTh * nth + k];
+        double sn2 = 0.0, cs = 0.0, cot = 0.0, th = 0.0;
+        if constexpr (kChart == kChartT) {
+            // polar factors of the row: uniform, read before the vector loads are
+            // queued so that waiting for them never waits for the prefetch
+            sn2 = tt[kSn2 * nth + k];
+            cs = tt[kCs * nth + k];
+            cot = tt[kCot * nth + k];
+            th = tt[kTh * nth + k];
+        }
         // next rows' traffic, consumed at the end of this iteration
         const bool pre = i + 2 < nst;
         if (pre) load_row(k + 2 * dir);
@@ -365,12 +381,47 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
             n2 = ldb(unp[2] + row, oc);
             n3 = ldb(unp[3] + row, oc);
         }
+        double hc[kNCH];
+        if constexpr (kChart == kChartH) {
+#pragma unroll
+            for (int q = 0; q < kNCH; ++q) hc[q] = ldb(A.ctab + (size_t)q * P + row, oc);
+        }
         lds_sync();
 
-        const double fR = Weno<WP>::flux6(s[b][0][l], s[b][0][l + 1], s[b][0][l + 2], s[b][0][l + 3], s[b][0][l + 4], A.eps);
-        const double fI = Weno<WP>::flux6(s[b][1][l], s[b][1][l + 1], s[b][1][l + 2], s[b][1][l + 3], s[b][1][l + 4], A.eps);
-        const double gR = Weno<WP>::flux6(s[b][2][l + 5], s[b][2][l + 4], s[b][2][l + 3], s[b][2][l + 2], s[b][2][l + 1], A.eps);
-        const double gI = Weno<WP>::flux6(s[b][3][l + 5], s[b][3][l + 4], s[b][3][l + 3], s[b][3][l + 2], s[b][3][l + 1], A.eps);
+        double dPhR, dPhI, dPiR, dPiI;
+        if constexpr (kChart == kChartT) {
+            const double fR = Weno<WP>::flux6(s[b][0][l], s[b][0][l + 1], s[b][0][l + 2], s[b][0][l + 3], s[b][0][l + 4], A.eps);
+            const double fI = Weno<WP>::flux6(s[b][1][l], s[b][1][l + 1], s[b][1][l + 2], s[b][1][l + 3], s[b][1][l + 4], A.eps);
+            const double gR = Weno<WP>::flux6(s[b][2][l + 5], s[b][2][l + 4], s[b][2][l + 3], s[b][2][l + 2], s[b][2][l + 1], A.eps);
+            const double gI = Weno<WP>::flux6(s[b][3][l + 5], s[b][3][l + 4], s[b][3][l + 3], s[b][3][l + 2], s[b][3][l + 1], A.eps);
+            dPhR = (__shfl_down(fR, 1) - fR) * A.inv6dx;
+            dPhI = (__shfl_down(fI, 1) - fI) * A.inv6dx;
+            dPiR = (__shfl_down(gR, 1) - gR) * A.inv6dx;
+            dPiI = (__shfl_down(gI, 1) - gI) * A.inv6dx;
+        } else {
+            // upwind side per lane and row: speed >= 0 -> f^+, speed < 0 -> f^-
+            const bool up1 = hc[kHLam1] >= 0.0, up2 = hc[kHLam2] >= 0.0;
+            auto deriv = [&](int p, bool up, bool any_up, bool any_dn) {
+                double fp = 0.0, fm = 0.0, d = 0.0;
+                if (any_up) {
+                    fp = Weno<WP>::flux6(s[b][p][l], s[b][p][l + 1], s[b][p][l + 2], s[b][p][l + 3], s[b][p][l + 4], A.eps);
+                    const double dp = __shfl_down(fp, 1) - fp;
+                    if (up) d = dp;
+                }
+                if (any_dn) {
+                    fm = Weno<WP>::flux6(s[b][p][l + 5], s[b][p][l + 4], s[b][p][l + 3], s[b][p][l + 2], s[b][p][l + 1], A.eps);
+                    const double dm = __shfl_down(fm, 1) - fm;
+                    if (!up) d = dm;
+                }
+                return d * A.inv6dx;
+            };
+            const bool up1_any = __any(active && up1), dn1_any = __any(active && !up1);
+            const bool up2_any = __any(active && up2), dn2_any = __any(active && !up2);
+            dPhR = deriv(0, up1, up1_any, dn1_any);
+            dPhI = deriv(1, up1, up1_any, dn1_any);
+            dPiR = deriv(2, up2, up2_any, dn2_any);
+            dPiI = deriv(3, up2, up2_any, dn2_any);
+        }
         const double phR = s[b][0][l + 3], phI = s[b][1][l + 3];
         const double piR = s[b][2][l + 3], piI = s[b][3][l + 3];
         double ahR, ahI;   // Phi on the row ahead (k + dir)
@@ -382,18 +433,16 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
             ahI = A.parity * phI;
         }
 
-        const double fR1 = __shfl_down(fR, 1);
-        const double fI1 = __shfl_down(fI, 1);
-        const double gR1 = __shfl_down(gR, 1);
-        const double gI1 = __shfl_down(gI, 1);
-
         if (active) {
-            const double dPhR = (fR1 - fR) * A.inv6dx;
-            const double dPhI = (fI1 - fI) * A.inv6dx;
-            const double dPiR = (gR1 - gR) * A.inv6dx;
-            const double dPiI = (gI1 - gI) * A.inv6dx;
-
-            const PointCoef c = point_coef(rt, sn2, cs, cot, th, rsq64(sigma2(rt, sn2)));
+            double lam1, lam2n, m3r, m3i, btr, bti, cr, ci, ath, bth;   // lam2n = -lam2
+            if constexpr (kChart == kChartT) {
+                const PointCoef c = point_coef(rt, sn2, cs, cot, th, rsq64(sigma2(rt, sn2)));
+                lam1 = c.b; lam2n = c.b; m3r = c.m3r; m3i = c.m3i; btr = c.btr; bti = c.bti;
+                cr = c.cr; ci = c.ci; ath = c.ath; bth = c.bth;
+            } else {
+                lam1 = hc[kHLam1]; lam2n = -hc[kHLam2]; m3r = hc[kHM3r]; m3i = hc[kHM3i];
+                btr = hc[kHBtr]; bti = hc[kHBti]; cr = hc[kHCr]; ci = hc[kHCi]; ath = hc[kHAth]; bth = hc[kHBth];
+            }
 
             // rows k+1 and k-1
             const double upR = dir > 0 ? ahR : bhR, upI = dir > 0 ? ahI : bhI;
@@ -402,14 +451,14 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
             const double d2R = (upR - 2.0 * phR + dnR) * A.ih2;
             const double d2I = (upI - 2.0 * phI + dnI) * A.ih2;
 
-            // d_t Phi = pi - b d_x Phi
-            const double FphR = piR - c.b * dPhR;
-            const double FphI = piI - c.b * dPhI;
-            // d_t pi = b d_x pi - m3 d_x Phi + B~t pi + A~thth Phi_thth + B~th Phi_th + C~ Phi
-            const double FpiR = c.b * dPiR - (c.m3r * dPhR - c.m3i * dPhI) + (c.btr * piR - c.bti * piI) +
-                                c.ath * d2R + c.bth * d1R + (c.cr * phR - c.ci * phI);
-            const double FpiI = c.b * dPiI - (c.m3r * dPhI + c.m3i * dPhR) + (c.btr * piI + c.bti * piR) +
-                                c.ath * d2I + c.bth * d1I + (c.cr * phI + c.ci * phR);
+            // d_t Phi = pi - lam1 d_x Phi
+            const double FphR = piR - lam1 * dPhR;
+            const double FphI = piI - lam1 * dPhI;
+            // d_t pi = -lam2 d_x pi - m3 d_x Phi + B~t pi + A~thth Phi_thth + B~th Phi_th + C~ Phi
+            const double FpiR = lam2n * dPiR - (m3r * dPhR - m3i * dPhI) + (btr * piR - bti * piI) +
+                                ath * d2R + bth * d1R + (cr * phR - ci * phI);
+            const double FpiI = lam2n * dPiI - (m3r * dPhI + m3i * dPhR) + (btr * piI + bti * piR) +
+                                ath * d2I + bth * d1I + (cr * phI + ci * phR);
 
             if (kMode == kRhsOnly) {
                 stb(outp[0] + row, oc, FphR);
@@ -443,14 +492,14 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
 // of neighbouring strips -- which share the radial halo -- march the same rows
 // in step, so the shared lines are read from HBM once and hit in L2 for the
 // second reader.
-template <int WP, int kMode>
+template <int WP, int kMode, int kChart>
 __device__ __forceinline__ void run_tile(const StageArgs& A, double (*s)[4][kRow], int rank)
 {
     const int strip = rank / A.segs;
     const int seg = rank - strip * A.segs;
     const int k0 = (int)((long long)A.nth * seg / A.segs);
     const int k1 = (int)((long long)A.nth * (seg + 1) / A.segs);
-    if (k1 > k0) march_strip<WP, kMode>(A, s, strip, k0, k1, (seg & 1) ? -1 : 1);
+    if (k1 > k0) march_strip<WP, kMode, kChart>(A, s, strip, k0, k1, (seg & 1) ? -1 : 1);
 }
 
 // Ranks are dealt so that each XCD (which receives every eighth workgroup id)
@@ -462,11 +511,11 @@ __device__ __forceinline__ int xcd_rank(int bid, int G)
     return xcd * q8 + (xcd < r8 ? xcd : r8) + loc;
 }
 
-template <int WP, int kMode>
+template <int WP, int kMode, int kChart>
 __global__ __launch_bounds__(kWave) void stage_kernel(StageArgs A)
 {
     __shared__ double s[2][4][kRow];
-    run_tile<WP, kMode>(A, s, xcd_rank((int)blockIdx.x, (int)gridDim.x));
+    run_tile<WP, kMode, kChart>(A, s, xcd_rank((int)blockIdx.x, (int)gridDim.x));
 }
 
 // One stage of several independent solves in one launch.  Member m is cut
@@ -479,10 +528,11 @@ __global__ __launch_bounds__(kWave) void stage_kernel(StageArgs A)
 // same rows together -- their reads of a row are one contiguous stretch of
 // each plane, and the radial halo they share is read once into L2.  Even
 // segments march upward and odd ones downward, so the two tiles that share a
-// boundary row meet there at the end of their march.  With G equal to the
-// tile count every workgroup runs one tile.  A tile runs exactly the
-// single-solve code.
-template <int WP, int kMode>
+// boundary row meet there at the end of their march.  By default G equals the
+// tile count (one tile per workgroup, dispatched in tile order by the
+// hardware as slots free up), which measured faster than fewer workgroups
+// looping over tiles.  A tile runs exactly the single-solve code.
+template <int WP, int kMode, int kChart>
 __global__ __launch_bounds__(kWave) void group_stage_kernel(const StageArgs* __restrict__ args,
                                                             const long long* __restrict__ start, int nmem,
                                                             long long tiles)
@@ -502,28 +552,46 @@ __global__ __launch_bounds__(kWave) void group_stage_kernel(const StageArgs* __r
         const int strip = local - seg * A.nstrips;
         const int k0 = (int)((long long)A.nth * seg / A.segs);
         const int k1 = (int)((long long)A.nth * (seg + 1) / A.segs);
-        if (k1 > k0) march_strip<WP, kMode>(A, s, strip, k0, k1, (seg & 1) ? -1 : 1);
+        if (k1 > k0) march_strip<WP, kMode, kChart>(A, s, strip, k0, k1, (seg & 1) ? -1 : 1);
     }
 }
 
 // ---------------------------------------------------------------- stability bound
-// max over points of b/dx + sqrt(4 A~thth/dtheta^2 + |B~th|/dtheta + |C~|); the
-// values are >= 0, so their bit patterns order like unsigned integers and the
-// reduction ends in one 64-bit atomic max per workgroup.
+// max over points of max(|lam1|, |lam2|)/dx + sqrt(4 A~thth/dtheta^2 + |B~th|/dtheta + |C~|);
+// the values are >= 0, so their bit patterns order like unsigned integers and
+// the reduction ends in one 64-bit atomic max per workgroup.  Chart T takes the
+// coefficients from the radial / polar tables (|lam1| = |lam2| = b), chart H
+// from the per-point table (ctab != nullptr).
 __global__ __launch_bounds__(256) void dt_bound_kernel(const double* __restrict__ rtab,
-                                                       const double* __restrict__ ttab, int nr, int nth,
+                                                       const double* __restrict__ ttab,
+                                                       const double* __restrict__ ctab, int nr, int nth,
                                                        double idx, double idth, unsigned long long* cell)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)nr * nth;
     double val = 0.0;
-    if (i < (long long)nr * nth) {
-        const int k = (int)(i / nr), j = (int)(i - (long long)k * nr);
-        double rt[kNRT];
-        for (int t = 0; t < kNRT; ++t) rt[t] = rtab[(size_t)t * nr + j];
-        const double sn2 = ttab[kSn2 * nth + k];
-        const PointCoef c = point_coef(rt, sn2, ttab[kCs * nth + k], ttab[kCot * nth + k], ttab[kTh * nth + k],
-                                       rsq64(sigma2(rt, sn2)));
-        val = c.b * idx + sqrt(4.0 * c.ath * idth * idth + fabs(c.bth) * idth + hypot(c.cr, c.ci));
+    if (i < n) {
+        double lam, ath, bth, cr, ci;
+        if (ctab) {
+            lam = fmax(fabs(ctab[kHLam1 * n + i]), fabs(ctab[kHLam2 * n + i]));
+            ath = ctab[kHAth * n + i];
+            bth = ctab[kHBth * n + i];
+            cr = ctab[kHCr * n + i];
+            ci = ctab[kHCi * n + i];
+        } else {
+            const int k = (int)(i / nr), j = (int)(i - (long long)k * nr);
+            double rt[kNRT];
+            for (int t = 0; t < kNRT; ++t) rt[t] = rtab[(size_t)t * nr + j];
+            const double sn2 = ttab[kSn2 * nth + k];
+            const PointCoef c = point_coef(rt, sn2, ttab[kCs * nth + k], ttab[kCot * nth + k], ttab[kTh * nth + k],
+                                           rsq64(sigma2(rt, sn2)));
+            lam = c.b;
+            ath = c.ath;
+            bth = c.bth;
+            cr = c.cr;
+            ci = c.ci;
+        }
+        val = lam * idx + sqrt(4.0 * ath * idth * idth + fabs(bth) * idth + hypot(cr, ci));
     }
     for (int off = 32; off > 0; off >>= 1) val = fmax(val, __shfl_xor(val, off));
     __shared__ double sm[4];
@@ -556,14 +624,49 @@ __global__ __launch_bounds__(256) void extract_kernel(const double* __restrict__
     }
 }
 
+// ---------------------------------------------------------------- horizon sample
+// Phi and d_rho Phi on the horizon from the four nodes j_h - 1 .. j_h + 2 with
+// interpolation weights w (value) and dw (derivative, already divided by dx).
+struct HorizonWeights {
+    double w[4], dw[4];
+};
+__global__ __launch_bounds__(256) void horizon_kernel(const double* __restrict__ u, long long plane, int nr,
+                                                      int nth, int j_h, HorizonWeights W,
+                                                      double* __restrict__ slot)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nth) {
+        const double* pr = u + (size_t)k * nr + (j_h - 1);
+        const double* pi = pr + plane;
+        double vr = 0.0, vi = 0.0, dr = 0.0, di = 0.0;
+        for (int q = 0; q < 4; ++q) {
+            vr += W.w[q] * pr[q];
+            vi += W.w[q] * pi[q];
+            dr += W.dw[q] * pr[q];
+            di += W.dw[q] * pi[q];
+        }
+        slot[4 * k] = vr;
+        slot[4 * k + 1] = vi;
+        slot[4 * k + 2] = dr;
+        slot[4 * k + 3] = di;
+    }
+}
+
 // ---------------------------------------------------------------- coefficient dump
+// TEUK_X_COEFFS order: lam1, Re m3, Im m3, Re B~t, Im B~t, Re C~, Im C~, A~thth, B~th, lam2.
 __global__ __launch_bounds__(256) void coef_dump_kernel(const double* __restrict__ rtab,
-                                                        const double* __restrict__ ttab, int nr, int nth,
+                                                        const double* __restrict__ ttab,
+                                                        const double* __restrict__ ctab, int nr, int nth,
                                                         double* __restrict__ out)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long n = (long long)nr * nth;
     if (i >= n) return;
+    if (ctab) {
+        const int order[TEUK_NCOEF] = {kHLam1, kHM3r, kHM3i, kHBtr, kHBti, kHCr, kHCi, kHAth, kHBth, kHLam2};
+        for (int q = 0; q < TEUK_NCOEF; ++q) out[q * n + i] = ctab[order[q] * n + i];
+        return;
+    }
     const int k = (int)(i / nr), j = (int)(i - (long long)k * nr);
     double rt[kNRT];
     for (int t = 0; t < kNRT; ++t) rt[t] = rtab[(size_t)t * nr + j];
@@ -579,94 +682,100 @@ __global__ __launch_bounds__(256) void coef_dump_kernel(const double* __restrict
     out[6 * n + i] = c.ci;
     out[7 * n + i] = c.ath;
     out[8 * n + i] = c.bth;
+    out[9 * n + i] = -c.b;
 }
 
 }  // namespace
 
-int stage_grid(int weight_prec, bool first)
+int stage_grid(int weight_prec, bool first, int chart)
 {
     // resident workgroups of one stage-kernel instantiation on the current device
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     hipError_t e = hipErrorInvalidValue;
-#define TEUK_OCC(W)                                                                                   \
-    case W:                                                                                          \
-        e = first ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<W, kStageFirst>, kWave, 0) \
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<W, kStageLater>, kWave, 0); \
-        break;
-    switch (weight_prec) {
-        TEUK_OCC(TEUK_W_FP64)
-        TEUK_OCC(TEUK_W_FP32)
-        TEUK_OCC(TEUK_W_FP16)
-        TEUK_OCC(TEUK_W_BF16)
-    default:
-        break;
-    }
+#define TEUK_OCC(W, C)                                                                                            \
+    if (weight_prec == W && chart == C)                                                                          \
+        e = first ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<W, kStageFirst, C>, kWave, 0) \
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_kernel<W, kStageLater, C>, kWave, 0);
+    TEUK_OCC(TEUK_W_FP64, kChartT)
+    TEUK_OCC(TEUK_W_FP32, kChartT)
+    TEUK_OCC(TEUK_W_FP16, kChartT)
+    TEUK_OCC(TEUK_W_BF16, kChartT)
+    TEUK_OCC(TEUK_W_FP64, kChartH)
+    TEUK_OCC(TEUK_W_FP32, kChartH)
+    TEUK_OCC(TEUK_W_FP16, kChartH)
+    TEUK_OCC(TEUK_W_BF16, kChartH)
 #undef TEUK_OCC
     if (e != hipSuccess || per_cu < 1) return 0;
     return cus * per_cu;
 }
 
-int launch_stage(const StageArgs& a, int stage, int weight_prec, void* stream)
+int launch_stage(const StageArgs& a, int stage, int weight_prec, int chart, void* stream)
 {
     const dim3 grid((unsigned)a.grid), block(kWave);
     hipStream_t st = (hipStream_t)stream;
     (void)hipGetLastError();   // report only what this launch does
-#define TEUK_LAUNCH(W)                                                                  \
-    case W:                                                                            \
-        if (stage == 1)                                                                \
-            hipLaunchKernelGGL((stage_kernel<W, kStageFirst>), grid, block, 0, st, a); \
-        else if (stage == 0)                                                           \
-            hipLaunchKernelGGL((stage_kernel<W, kRhsOnly>), grid, block, 0, st, a);    \
-        else                                                                           \
-            hipLaunchKernelGGL((stage_kernel<W, kStageLater>), grid, block, 0, st, a); \
-        break;
-    switch (weight_prec) {
-        TEUK_LAUNCH(TEUK_W_FP64)
-        TEUK_LAUNCH(TEUK_W_FP32)
-        TEUK_LAUNCH(TEUK_W_FP16)
-        TEUK_LAUNCH(TEUK_W_BF16)
-    default:
-        return (int)hipErrorInvalidValue;
+    bool done = false;
+#define TEUK_LAUNCH(W, C)                                                                      \
+    if (weight_prec == W && chart == C) {                                                     \
+        if (stage == 1)                                                                       \
+            hipLaunchKernelGGL((stage_kernel<W, kStageFirst, C>), grid, block, 0, st, a);     \
+        else if (stage == 0)                                                                  \
+            hipLaunchKernelGGL((stage_kernel<W, kRhsOnly, C>), grid, block, 0, st, a);        \
+        else                                                                                  \
+            hipLaunchKernelGGL((stage_kernel<W, kStageLater, C>), grid, block, 0, st, a);     \
+        done = true;                                                                          \
     }
+    TEUK_LAUNCH(TEUK_W_FP64, kChartT)
+    TEUK_LAUNCH(TEUK_W_FP32, kChartT)
+    TEUK_LAUNCH(TEUK_W_FP16, kChartT)
+    TEUK_LAUNCH(TEUK_W_BF16, kChartT)
+    TEUK_LAUNCH(TEUK_W_FP64, kChartH)
+    TEUK_LAUNCH(TEUK_W_FP32, kChartH)
+    TEUK_LAUNCH(TEUK_W_FP16, kChartH)
+    TEUK_LAUNCH(TEUK_W_BF16, kChartH)
 #undef TEUK_LAUNCH
+    if (!done) return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();
 }
 
 int launch_group_stage(const StageArgs* args, const long long* start, int nmem, long long tiles, int grid,
-                       int stage, int weight_prec, void* stream)
+                       int stage, int weight_prec, int chart, void* stream)
 {
     if (nmem < 1 || tiles < 1 || grid < 1 || stage < 1 || stage > 3) return (int)hipErrorInvalidValue;
     const dim3 g((unsigned)grid), block(kWave);
     hipStream_t st = (hipStream_t)stream;
     (void)hipGetLastError();
-#define TEUK_GLAUNCH(W)                                                                                         \
-    case W:                                                                                                    \
+    bool done = false;
+#define TEUK_GLAUNCH(W, C)                                                                                      \
+    if (weight_prec == W && chart == C) {                                                                      \
         if (stage == 1)                                                                                        \
-            hipLaunchKernelGGL((group_stage_kernel<W, kStageFirst>), g, block, 0, st, args, start, nmem, tiles); \
+            hipLaunchKernelGGL((group_stage_kernel<W, kStageFirst, C>), g, block, 0, st, args, start, nmem, tiles); \
         else                                                                                                   \
-            hipLaunchKernelGGL((group_stage_kernel<W, kStageLater>), g, block, 0, st, args, start, nmem, tiles); \
-        break;
-    switch (weight_prec) {
-        TEUK_GLAUNCH(TEUK_W_FP64)
-        TEUK_GLAUNCH(TEUK_W_FP32)
-        TEUK_GLAUNCH(TEUK_W_FP16)
-        TEUK_GLAUNCH(TEUK_W_BF16)
-    default:
-        return (int)hipErrorInvalidValue;
+            hipLaunchKernelGGL((group_stage_kernel<W, kStageLater, C>), g, block, 0, st, args, start, nmem, tiles); \
+        done = true;                                                                                           \
     }
+    TEUK_GLAUNCH(TEUK_W_FP64, kChartT)
+    TEUK_GLAUNCH(TEUK_W_FP32, kChartT)
+    TEUK_GLAUNCH(TEUK_W_FP16, kChartT)
+    TEUK_GLAUNCH(TEUK_W_BF16, kChartT)
+    TEUK_GLAUNCH(TEUK_W_FP64, kChartH)
+    TEUK_GLAUNCH(TEUK_W_FP32, kChartH)
+    TEUK_GLAUNCH(TEUK_W_FP16, kChartH)
+    TEUK_GLAUNCH(TEUK_W_BF16, kChartH)
 #undef TEUK_GLAUNCH
+    if (!done) return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();
 }
 
-int launch_dt_bound(const double* rtab, const double* ttab, int nr, int nth, double dx, double dth,
-                    unsigned long long* cell, void* stream)
+int launch_dt_bound(const double* rtab, const double* ttab, const double* ctab, int nr, int nth, double dx,
+                    double dth, unsigned long long* cell, void* stream)
 {
     (void)hipGetLastError();
     const long long n = (long long)nr * nth;
     const unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(dt_bound_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, rtab, ttab, nr, nth,
+    hipLaunchKernelGGL(dt_bound_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, rtab, ttab, ctab, nr, nth,
                        1.0 / dx, 1.0 / dth, cell);
     return (int)hipGetLastError();
 }
@@ -689,12 +798,28 @@ int launch_extract(const double* u, long long plane, int nr, int nth, int j_e, d
     return (int)hipGetLastError();
 }
 
-int launch_coef_dump(const double* rtab, const double* ttab, int nr, int nth, double* out, void* stream)
+int launch_horizon(const double* u, long long plane, int nr, int nth, int j_h, const double* w, const double* dw,
+                   double* slot, void* stream)
+{
+    if (j_h < 1 || j_h + 2 > nr - 1) return (int)hipErrorInvalidValue;
+    HorizonWeights W;
+    for (int q = 0; q < 4; ++q) {
+        W.w[q] = w[q];
+        W.dw[q] = dw[q];
+    }
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(horizon_kernel, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, (hipStream_t)stream, u,
+                       plane, nr, nth, j_h, W, slot);
+    return (int)hipGetLastError();
+}
+
+int launch_coef_dump(const double* rtab, const double* ttab, const double* ctab, int nr, int nth, double* out,
+                     void* stream)
 {
     (void)hipGetLastError();
     const long long n = (long long)nr * nth;
     hipLaunchKernelGGL(coef_dump_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
-                       rtab, ttab, nr, nth, out);
+                       rtab, ttab, ctab, nr, nth, out);
     return (int)hipGetLastError();
 }
 

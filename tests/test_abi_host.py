@@ -43,7 +43,7 @@ int main(void) {
   printf("teuk_config %zu\\n", sizeof(teuk_config));
   printf("teuk_device_ctx %zu\\n", sizeof(teuk_device_ctx));
   printf("teuk_info_t %zu\\n", sizeof(teuk_info_t));
-  F(teuk_config, M) F(teuk_config, a) F(teuk_config, x_extract) F(teuk_config, workgroups)
+  F(teuk_config, M) F(teuk_config, a) F(teuk_config, x_extract) F(teuk_config, workgroups) F(teuk_config, S)
   F(teuk_info_t, samples) F(teuk_info_t, dt_bound) F(teuk_device_ctx, workspace_bytes)
   return 0; }
 """)
@@ -62,7 +62,7 @@ int main(void) {
 
 CASES = [(0, 0, 0.5, -64.0, 64.0), (-2, 2, 0.999, -200.0, 400.0), (0, 0, 1.0, -400.0, 800.0),
          (-2, 4, 1.0, -100.0, 300.0), (1, -3, 0.3, -50.0, 60.0), (-2, 1, 0.0, -300.0, 300.0)]
-NAMES = ["lam1", "m3r", "m3i", "btr", "bti", "cr", "ci", "ath", "bth"]
+NAMES = ["lam1", "m3r", "m3i", "btr", "bti", "cr", "ci", "ath", "bth", "lam2"]
 
 
 @pytest.mark.parametrize("s,m,a,x0,x1", CASES)
@@ -77,6 +77,63 @@ def test_host_coefficients_match_oracle(s, m, a, x0, x1):
         err = np.max(np.abs(hc[i] - ref))
         assert err <= 1e-13 * np.max(np.abs(ref)) + 1e-15 * scale, (n, err, np.max(np.abs(ref)))
     np.testing.assert_allclose(o.tab["lam2"], -hc[0], rtol=1e-14)
+
+
+def chart_h_grid(a, nr, S=20.0, lo=0.55, hi_gap=0.3):
+    """x_min, x_max of a chart-H grid from lo * rho_H to S - hi_gap, nudged so
+    that no node falls on the horizon."""
+    rp, _ = S_oracle_horizons(a)
+    rho_h = S * rp / (rp + S)
+    x0, x1 = lo * rho_h, S - hi_gap
+    dx = (x1 - x0) / (nr - 1)
+    f = (rho_h - x0) / dx
+    if abs(f - round(f)) < 0.05:
+        x0 -= 0.3 * dx
+        x1 -= 0.3 * dx
+    return x0, x1
+
+
+def S_oracle_horizons(a):
+    from oracle import coefficients as C
+    return C.horizons(1.0, a)
+
+
+CASES_H = [(-2, 0, 1.0), (-2, 2, 0.999), (0, 1, 0.5), (0, 0, 0.0), (1, -3, 0.8)]
+
+
+@pytest.mark.parametrize("s,m,a", CASES_H)
+def test_host_coefficients_match_oracle_chart_H(s, m, a):
+    nr, nth = 157, 8
+    x0, x1 = chart_h_grid(a, nr)
+    cfg = T.make_config(s=s, m=m, a=a, nr=nr, ntheta=nth, x_min=x0, x_max=x1, chart="H", S=20.0)
+    hc = T.teuk_host_coefficients(cfg)
+    o = S.TeukOracle(S.Problem(s, m, a, nr, nth, x0, x1, chart="H", S=20.0))
+    scale = max(np.max(np.abs(o.tab[n])) for n in NAMES)
+    for i, n in enumerate(NAMES):
+        ref = o.tab[n]
+        err = np.max(np.abs(hc[i] - ref))
+        assert err <= 1e-13 * np.max(np.abs(ref)) + 1e-15 * scale, (n, err, np.max(np.abs(ref)))
+
+
+def test_chart_H_validation():
+    a = 1.0
+    x0, x1 = chart_h_grid(a, 101)
+    ok = T.make_config(s=-2, m=0, a=a, nr=101, ntheta=8, x_min=x0, x_max=x1, chart="H", S=20.0)
+    assert T.teuk_footprint_bytes(ok) > 0
+    rp, _ = S_oracle_horizons(a)
+    rho_h = 20.0 * rp / (rp + 20.0)
+    bad = [
+        dict(x_min=x0, x_max=20.0),                 # reaches S
+        dict(x_min=0.0, x_max=x1),                  # r = 0
+        dict(x_min=rho_h + 0.1, x_max=x1),          # horizon below the grid
+        dict(x_min=x0, x_max=x1, S=-1.0),
+        dict(x_min=rho_h - 0.2 * (x1 - rho_h) / 100, x_max=x1),   # no node below the horizon
+    ]
+    for kw in bad:
+        args = dict(s=-2, m=0, a=a, nr=101, ntheta=8, chart="H", S=20.0)
+        args.update(kw)
+        c = T.make_config(**args)
+        assert T.teuk_footprint_bytes(c) == 0, kw
 
 
 def test_footprint_and_validation():

@@ -1,0 +1,207 @@
+"""GPU parity in the hyperboloidal chart (paper Sec. 2.2), through the C ABI.
+
+The chart-H stage kernel streams the per-point coefficient table and upwinds
+each row by the sign of its own speed at the point, so cases include grids
+that reach between the two horizons of a sub-extremal hole, where the pi-row
+speed changes sign inside a strip and a wave computes both flux sides.  Bar:
+as for the tortoise chart (whole state <= 1e-12, each plane <= 5e-12, max-norm
+relative).  Also: horizon samples (Phi and d_rho Phi by 4-point Lagrange
+interpolation) against the oracle's, the device stability bound and
+coefficients, the paper's horizon setup, and sampled radial windows of the
+full 16384 x 64 grid."""
+import numpy as np
+import pytest
+
+import paper_2010_04760_amd as T
+import workloads as W
+from oracle import coefficients as C
+from oracle import solver as S
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+TOL_PLANE = 5e-12
+SS = 20.0
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def grid(a, nr, lo=0.55, hi_gap=0.3):
+    rp, _ = C.horizons(1.0, a)
+    rho_h = SS * rp / (rp + SS)
+    x0, x1 = lo * rho_h, SS - hi_gap
+    dx = (x1 - x0) / (nr - 1)
+    f = (rho_h - x0) / dx
+    if abs(f - round(f)) < 0.05:
+        x0 -= 0.3 * dx
+        x1 -= 0.3 * dx
+    return x0, x1
+
+
+def problem(s, m, a, nr, nth, lo=0.55):
+    x0, x1 = grid(a, nr, lo)
+    return S.Problem(s, m, a, nr, nth, x0, x1, chart="H", S=SS)
+
+
+def cfg_for(prob, dt, **kw):
+    return T.make_config(s=prob.s, m=prob.m, a=prob.a, nr=prob.nr, ntheta=prob.nth, x_min=prob.x_min,
+                         x_max=prob.x_max, M=prob.M, dt=dt, weno_eps=prob.eps, chart="H", S=prob.S, **kw)
+
+
+def assert_parity(g, o, what=""):
+    big = float(np.max(np.abs(o)))
+    se = float(np.max(np.abs(g - o))) / big
+    errs = []
+    for p in range(4):
+        ref = float(np.max(np.abs(o[p])))
+        errs.append(float(np.max(np.abs(g[p] - o[p]))) / (ref if ref > 0 else big))
+    assert se <= TOL, (what, se, errs)
+    assert max(errs) <= TOL_PLANE, (what, se, errs)
+    return se, errs
+
+
+CASES = [(150, 9, -2, 0, 1.0), (64, 4, -2, 2, 0.5), (63, 16, 0, 1, 0.7), (200, 5, 0, 0, 0.0),
+         (127, 8, -2, 3, 0.999), (90, 6, 1, -1, 0.3)]
+
+
+@pytest.mark.parametrize("nr,nth,s,m,a", CASES)
+def test_chart_h_random_state(nr, nth, s, m, a):
+    say("case chart H random", nr, nth, s, m, a)
+    prob = problem(s, m, a, nr, nth)
+    o = S.TeukOracle(prob)
+    dt = 0.3 * o.dt_bound(1.0)
+    u0 = W.random_state(nr, nth, seed=nr * 7 + nth, smooth=True)
+    with T.Solver(cfg_for(prob, dt)) as sv:
+        sv.set_initial(u0)
+        F = sv.rhs()
+        assert_parity(F, o.rhs(u0), what=("rhs", nr, nth))
+        sv.step(3)
+        got = sv.state()
+    ref, _ = o.evolve(u0, dt, 3)
+    se, errs = assert_parity(got, ref, what=("3 steps", nr, nth))
+    say("  errors", se, errs)
+
+
+def test_chart_h_mixed_sides_inside_the_horizon():
+    """a = 0.5: the grid starts between r- and r+, where the pi rows move
+    inward (lam2 < 0); strips straddling r+ hold lanes of both signs."""
+    prob = problem(-2, 2, 0.5, 200, 6, lo=0.3)
+    o = S.TeukOracle(prob)
+    assert np.any(o.tab["lam2"] < 0) and np.any(o.tab["lam2"] > 0)
+    dt = 0.3 * o.dt_bound(1.0)
+    u0 = W.random_state(prob.nr, prob.nth, seed=5, smooth=True)
+    with T.Solver(cfg_for(prob, dt)) as sv:
+        sv.set_initial(u0)
+        assert_parity(sv.rhs(), o.rhs(u0), what="mixed rhs")
+
+
+def test_chart_h_dt_bound_and_coefficients():
+    prob = problem(-2, 2, 0.9, 140, 10)
+    o = S.TeukOracle(prob)
+    with T.Solver(cfg_for(prob, 0.0, cfl=0.5)) as sv:
+        inf = sv.info()
+        assert abs(inf.dt_bound * 0.5 - o.dt_bound(0.5)) <= 1e-13 * o.dt_bound(0.5)
+        cf = sv.coefficients()
+    names = ["lam1", "m3r", "m3i", "btr", "bti", "cr", "ci", "ath", "bth", "lam2"]
+    scale = max(np.max(np.abs(o.tab[n])) for n in names)
+    for i, n in enumerate(names):
+        assert np.max(np.abs(cf[i] - o.tab[n])) <= 1e-13 * np.max(np.abs(o.tab[n])) + 1e-15 * scale, n
+
+
+def test_chart_h_horizon_samples():
+    """The paper's horizon setup at small size: s = -2, (l, m) = (2, 0), a = M,
+    Gaussian at rho = 1 of width 0.22; 60 steps, sampled every 6."""
+    wl = W.C3H.with_(nr=512, nth=16)
+    prob = S.Problem(wl.s, wl.m, wl.a, wl.nr, wl.nth, wl.x_min, wl.x_max, chart="H", S=wl.S)
+    o = S.TeukOracle(prob)
+    dt = o.dt_bound(0.5)
+    u0 = W.gaussian_pulse(wl)
+    cfg = cfg_for(prob, dt, x_extract=wl.x_e, extract_every=6, max_samples=20)
+    with T.Solver(cfg) as sv:
+        sv.set_initial(u0)
+        ph0 = sv.horizon()
+        sv.step(60)
+        t, phH, dphH = sv.horizon()
+        got = sv.state()
+    ref, _ = o.evolve(u0, dt, 60)
+    assert_parity(got, ref, what="horizon setup")
+    assert phH.shape == (11, prob.nth)
+    np.testing.assert_allclose(t, np.arange(11) * 6 * dt, rtol=1e-15)
+    # the first sample is the initial data; the last is the final state
+    h0, d0 = o.horizon(u0)
+    h1, d1 = o.horizon(ref)
+    for got_, ref_ in ((ph0[1][0], h0), (ph0[2][0], d0), (phH[-1], h1), (dphH[-1], d1)):
+        assert np.max(np.abs(got_ - ref_)) <= 1e-12 * max(np.max(np.abs(ref_)), 1e-300)
+
+
+def test_chart_h_full_grid_windows():
+    """The 16384 x 64 horizon grid at full size: F(u) of a smooth random state by
+    the stage kernel, compared on three radial windows (at the horizon, mid-grid
+    and near null infinity) with the oracle evaluated on those windows."""
+    wl = W.C3H
+    say("case chart H full grid windows", wl.name)
+    nr, nth = wl.nr, wl.nth
+    dx = (wl.x_max - wl.x_min) / (nr - 1)
+    u0 = W.random_state(nr, nth, seed=17, smooth=True)
+    cfg = T.make_config(s=wl.s, m=wl.m, a=wl.a, nr=nr, ntheta=nth, x_min=wl.x_min, x_max=wl.x_max, chart="H",
+                        S=wl.S, dt=1e-4)
+    with T.Solver(cfg) as sv:
+        sv.set_initial(u0)
+        F = sv.rhs()
+    rp, _ = C.horizons(1.0, wl.a)
+    j_h = int((wl.S * rp / (rp + wl.S) - wl.x_min) / dx)
+    for j0 in (j_h - 20, nr // 2, nr - 70):
+        j0 = max(j0, 0)
+        j1 = min(j0 + 64, nr)
+        a0, a1 = max(j0 - 3, 0), min(j1 + 3, nr)
+        prob = S.Problem(wl.s, wl.m, wl.a, a1 - a0, nth, wl.x_min + a0 * dx, wl.x_min + (a1 - 1) * dx,
+                         chart="H", S=wl.S)
+        o = S.TeukOracle(prob)
+        Fo = o.rhs(u0[:, :, a0:a1])
+        # interior of the window: points whose stencil lies inside it (or at a true boundary)
+        lo = j0 - a0
+        hi = j1 - a0
+        inner_lo = lo if a0 == 0 else max(lo, 3)
+        inner_hi = hi if a1 == nr else min(hi, (a1 - a0) - 3)
+        g = F[:, :, a0 + inner_lo:a0 + inner_hi]
+        r = Fo[:, :, inner_lo:inner_hi]
+        big = float(np.max(np.abs(r)))
+        err = float(np.max(np.abs(g - r))) / big
+        say("  window", j0, j1, "err", err)
+        assert err <= TOL, (j0, err)
+
+
+def test_chart_h_in_a_group_equals_alone():
+    """Chart-H and chart-T solves advanced together (one launch per (weight
+    precision, chart) class) equal the same solves alone, bitwise."""
+    specs = [problem(-2, 0, 1.0, 150, 9), problem(0, 1, 0.6, 100, 5)]
+    cfgs = [cfg_for(p, 0.0, weight_prec=wp, x_extract=5.0, extract_every=2, max_samples=8)
+            for p, wp in zip(specs, ("fp64", "fp32"))]
+    cfgs.append(T.make_config(s=-2, m=2, a=0.9, nr=130, ntheta=7, x_min=-30.0, x_max=50.0, x_extract=10.0,
+                              extract_every=2, max_samples=8))
+    u0s = [W.random_state(c.nr, c.ntheta, seed=40 + i, smooth=True) for i, c in enumerate(cfgs)]
+    alone = []
+    for c, u0 in zip(cfgs, u0s):
+        with T.Solver(c) as sv:
+            sv.set_initial(u0)
+            sv.step(6)
+            alone.append((sv.state(), sv.waveform()[1], sv.horizon()[1] if c.chart == 1 else None))
+    members = []
+    for c, u0 in zip(cfgs, u0s):
+        sv = T.Solver(c)
+        sv.set_initial(u0)
+        members.append(sv)
+    with T.Group(4) as g:
+        for sv in members:
+            g.add(sv)
+        assert g.info().classes == 3
+        g.step(6)
+        for sv, (st, wv, hz) in zip(members, alone):
+            assert np.array_equal(sv.state(), st)
+            assert np.array_equal(sv.waveform()[1], wv)
+            if hz is not None:
+                assert np.array_equal(sv.horizon()[1], hz)
+    for sv in members:
+        sv.close()
