@@ -20,6 +20,10 @@ Other workloads (one JSON line each):
   --workload C3   s = 0, m = 0 extremal Kerr on 16384 x 128, 200000 steps, with
                   FP64 / FP32 / FP16 / BF16 weights: speed, waveform error and
                   late-time tail index against FP64.
+  --workload C3H  the horizon experiment of Sec. 4 in the hyperboloidal chart
+                  (s = -2, l = 2, a = M, 16384 x 64) per weight precision, with the
+                  charge proxy d_rho Phi on the horizon against FP64, and a coarser
+                  FP64 run to tau = 2000 for the horizon power laws.
   --workload C4   64 independent solves of uneven size advanced together
                   through the group extension (FP32 weights, 2000 steps).
   --workload C5   Poisson arrivals of such solves served by continuous
@@ -243,6 +247,112 @@ def bench_sweep(args, torch, T, W):
     }
 
 
+# ----------------------------------------------------------------------------- C3-H: horizon chart
+def horizon_series(T, torch, wl, weights, steps, every, stream):
+    """Run the hyperboloidal-chart workload; returns (seconds, dt, tau, Phi_H, dPhi_H, theta)."""
+    cfg = T.make_config(s=wl.s, m=wl.m, a=wl.a, nr=wl.nr, ntheta=wl.nth, x_min=wl.x_min, x_max=wl.x_max,
+                        M=wl.M, dt=0.0, cfl=0.5, weight_prec=weights, x_extract=wl.x_e, extract_every=every,
+                        max_samples=steps // every + 1, chart="H", S=wl.S)
+    import workloads as W
+    sv = T.Solver(cfg, stream=stream)
+    sv.set_initial(W.gaussian_pulse(wl))
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    done = 0
+    while done < steps:                     # in chunks, so that progress is visible
+        k = min(steps - done, 50000)
+        sv.step(k)
+        done += k
+        torch.cuda.synchronize()
+        log(f"  {weights}: {done}/{steps} steps")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    sec = ev0.elapsed_time(ev1) / 1e3
+    sv.check_finite()
+    tau, ph, dph = sv.horizon()
+    dt = sv.info().dt
+    sv.close()
+    theta = (np.arange(wl.nth) + 0.5) * np.pi / wl.nth
+    return sec, dt, tau, ph, dph, theta
+
+
+def charge(dph, theta):
+    """Aretakis-charge proxy: the sin(theta)-weighted theta integral of d_rho Phi on the horizon."""
+    w = np.sin(theta) * (np.pi / len(theta))
+    return dph @ w
+
+
+def bench_horizon(args, torch, T, W):
+    wl = W.C3H
+    steps = wl.steps if args.steps is None else args.steps
+    stream = torch.cuda.current_stream()
+    k_star = wl.nth // 4
+    runs = {}
+    for wp in ("fp64", "fp32", "fp16", "bf16"):
+        log(f"C3-H {wp}: {steps} steps")
+        runs[wp] = horizon_series(T, torch, wl, wp, steps, wl.every, stream)
+    sec64, dt, tau, ph64, dph64, theta = runs["fp64"]
+    q64 = charge(dph64, theta)
+    pu = 3.0 * wl.points * steps
+    late = tau >= 0.5 * tau[-1]
+    per = {}
+    for wp, (sec, _, _, ph, dph, _) in runs.items():
+        q = charge(dph, theta)
+        per[wp] = {"value": pu / sec, "seconds": sec, "speedup_vs_fp64": sec64 / sec,
+                   "phi_h_rel_l2_vs_fp64": float(np.linalg.norm(ph - ph64) / np.linalg.norm(ph64)),
+                   "charge_rel_drift_vs_fp64": float(np.max(np.abs(q[late] - q64[late])) / np.max(np.abs(q64[late]))),
+                   "charge_change_late": float(abs(q[-1] / q[late][0] - 1.0))}
+    out = {
+        "metric": METRIC, "value": pu / sec64, "unit": "point-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": 0, "ms_per_step": sec64 / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl.name, "nr": wl.nr, "ntheta": wl.nth, "s": wl.s, "m": wl.m, "a": wl.a,
+                   "S": wl.S, "dt": dt, "tau_end": float(tau[-1]), "theta_star": float(theta[k_star])},
+        # the chart-H kernel streams ten coefficients per point: 80 B more per point-stage
+        "roofline": {"bound": "hbm", "algorithmic_bytes_per_point_stage": 85.33 + 80.0,
+                     "achieved": (85.33 + 80.0) * wl.points / (sec64 / (3 * steps)) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (85.33 + 80.0) * wl.points / (sec64 / (3 * steps)) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None},
+        "per_dtype": per,
+    }
+    if not args.no_physics:
+        # The horizon laws of Sec. 4 (Phi_H ~ 1/tau, d_rho Phi_H -> constant) on two
+        # coarser grids run to tau = 2000 in FP64.  The inner edge on the horizon
+        # closes with end-value ghosts, which leaves a floor in Phi_H of first
+        # order in the radial step; the two-grid Richardson value 2 Phi_H(fine) -
+        # Phi_H(coarse) removes it.
+        series = {}
+        for nrp in (args.physics_nr, 2 * args.physics_nr):
+            pw = wl.with_(nr=nrp, nth=32)
+            cfg = T.make_config(s=pw.s, m=pw.m, a=pw.a, nr=pw.nr, ntheta=pw.nth, x_min=pw.x_min,
+                                x_max=pw.x_max, chart="H", S=pw.S)
+            probe = T.Solver(cfg, stream=stream)
+            dtp = probe.info().dt
+            probe.close()
+            nsteps = int(np.ceil(args.tau_end / dtp))
+            every = max(1, nsteps // 4000)
+            log(f"C3-H horizon laws: {pw.nr}x{pw.nth}, {nsteps} steps to tau = {args.tau_end}")
+            secp, _, taup, php, dphp, thp = horizon_series(T, torch, pw, "fp64", nsteps, every, stream)
+            series[nrp] = (taup, php[:, pw.nth // 4].real, dphp[:, pw.nth // 4].real, secp, nsteps)
+        (tc, yc, dc, _, _), (tf, yf, df, secf, nf) = series[args.physics_nr], series[2 * args.physics_nr]
+        probe_t = np.linspace(25.0, args.tau_end, 400)
+        re = 2 * np.interp(probe_t, tf, yf) - np.interp(probe_t, tc, yc)
+        pre = local_index(probe_t, re)
+        early = (probe_t[1:-1] >= 50.0) & (probe_t[1:-1] <= 150.0)
+        late = tf[1:-1] >= 0.5 * tf[-1]
+        out["horizon_laws"] = {
+            "grids": [f"{args.physics_nr}x32", f"{2 * args.physics_nr}x32"], "tau_end": float(tf[-1]),
+            "phi_h_local_index_richardson_tau_50_150": float(np.mean(pre[early])), "expected_phi_h": -1.0,
+            "dphi_h_local_index_fine_late": float(np.mean(local_index(tf, df)[late])), "expected_dphi_h": 0.0,
+            "phi_h_floor_coarse": float(yc[-1]), "phi_h_floor_fine": float(yf[-1]),
+            "dphi_h_end_fine": float(df[-1]), "seconds_fine": secf, "steps_fine": nf,
+        }
+    return out
+
+
 # ----------------------------------------------------------------------------- C4: batched solves
 def bench_batched(args, torch, T, W):
     mix = W.batch_workloads()
@@ -360,7 +470,7 @@ def bench_serving(args, torch, T, W):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "C5"])
+    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C3H", "C4", "C5"])
     ap.add_argument("--steps", type=int, default=None,
                     help="timed SSP-RK3 steps (C2: 20000, C3: 200000, C4: 2000)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (C2: 100, C4: 20)")
@@ -382,6 +492,10 @@ def main():
     ap.add_argument("--chunk-steps", type=int, default=250, help="C5: steps between admission checks")
     ap.add_argument("--hbm-budget-gb", type=float, default=0.0, help="C5: admission budget (0: free HBM)")
     ap.add_argument("--serve-seed", type=int, default=5)
+    ap.add_argument("--no-physics", action="store_true", help="C3H: skip the coarse run to tau = 2000")
+    ap.add_argument("--physics-nr", type=int, default=4096,
+                    help="C3H: radial points of the coarser horizon-law run (the finer has twice as many)")
+    ap.add_argument("--tau-end", type=float, default=2000.0, help="C3H: end time of the coarse run")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -394,7 +508,8 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
-    fn = {"C2": bench_single, "C3": bench_sweep, "C4": bench_batched, "C5": bench_serving}[args.workload]
+    fn = {"C2": bench_single, "C3": bench_sweep, "C3H": bench_horizon, "C4": bench_batched,
+          "C5": bench_serving}[args.workload]
     out = fn(args, torch, T, W)
     print(json.dumps(out), flush=True)
 

@@ -123,8 +123,10 @@ typedef struct {
                                 (normal in FP32, so reduced-precision weights stay finite) */
     double x_extract;        /* waveform radius; the nearest grid node is sampled       */
     double S;                /* hyperboloidal chart parameter (Sec. 2.2; e.g. 20); the
-                                grid needs 0 < x_min < rho_H < x_max < S, no node on the
-                                horizon, and one node below / two above it */
+                                grid needs 0 < x_min, x_max < S and the horizon
+                                rho_H = S r+/(r+ + S) on it (at most half a step
+                                outside); for a = M start it on the horizon, where
+                                the pi-row speed vanishes (no incoming data) */
 } teuk_config;
 
 typedef struct {

@@ -37,9 +37,10 @@ What is computed:
   m3 = (A~trho + b) d_rho b + b B~tau - B~rho.  Each row is then upwinded by the
   sign of its own speed at the point (Sec. 3.1.2).
 
-Everything per point is done in 50-digit mpmath and rounded once to FP64.  The
-grid must not put a node exactly on the horizon (Delta = 0), where the divided
-coefficients are 0/0 as written; they are regular there, and the library's
+Everything per point is done in mpmath (50 digits, more for nodes a hair from
+the horizon, where the chain rule's 1/Delta^2 terms cancel) and rounded once to
+FP64.  A node exactly on the horizon (Delta = 0) is refused: the divided
+coefficients are 0/0 there as written; they are regular, and the library's
 closed forms are, but the oracle keeps the printed construction.
 """
 from __future__ import annotations
@@ -122,19 +123,27 @@ def radial_values(rho, M, a, s, m, S):
     50-digit arithmetic: r = rho S / (S - rho), Delta = (r - r+)(r - r-)."""
     fns = _radial_fns()
     out = []
-    with mp.workdps(DPS):
-        Sm = mp.mpf(S)
-        rp, rm = horizons_mp(M, a)
-        for x in np.asarray(rho, dtype=np.float64):
+    for x in np.asarray(rho, dtype=np.float64):
+        with mp.workdps(DPS):
+            rp, rm = horizons_mp(M, a)
+            xr = mp.mpf(float(x))
+            D0 = (xr * mp.mpf(S) / (mp.mpf(S) - xr) - rp) * (xr * mp.mpf(S) / (mp.mpf(S) - xr) - rm)
+        if D0 == 0:
+            raise ValueError("a radial node lies exactly on the horizon (0/0 in the printed construction)")
+        # the chain rule leaves terms up to 1/Delta^2 that cancel: carry enough
+        # digits for nodes a hair from the horizon
+        extra = int(max(0.0, -2.0 * float(mp.log10(abs(D0))))) + 5
+        with mp.workdps(DPS + extra):
+            Sm = mp.mpf(S)
+            rp, rm = horizons_mp(M, a)
             xr = mp.mpf(float(x))
             rr = xr * Sm / (Sm - xr)
             D = (rr - rp) * (rr - rm)
-            if D == 0:
-                raise ValueError("a radial node lies on the horizon")
             vals = {k: f(rr, D, mp.mpf(M), mp.mpf(a), int(s), int(m), Sm) for k, f in fns.items()}
             vals["r"], vals["Delta"] = rr, D
             vals["rho_p"] = Sm**2 / (rr + Sm) ** 2
-            out.append(vals)
+            vals = {k: +v for k, v in vals.items()}
+        out.append(vals)
     return out
 
 
@@ -214,17 +223,29 @@ def rho_of_r(r_, S):
     return r_ / (1.0 + r_ / S)
 
 
-def horizon_weights(xi):
-    """4-point Lagrange weights on the nodes at offsets -1, 0, 1, 2 (in units of
-    the grid step) for the value and the first derivative at offset xi in [0, 1)."""
-    nodes = (-1.0, 0.0, 1.0, 2.0)
+def horizon_stencil(f, nr):
+    """Nodes and weights for the horizon at fractional node position f (the
+    horizon sits at x_min + f dx): the four nodes j0 .. j0+3 with
+    j0 = floor(f) - 1, shifted to stay inside the grid (one-sided next to its
+    ends), and the 4-point Lagrange weights for the value and for the
+    derivative (per unit step) at f."""
+    j0 = int(np.floor(f)) - 1
+    j0 = min(max(j0, 0), nr - 4)
+    nodes = [float(j0 + i) for i in range(4)]
     w, dw = [], []
-    for i, xi_i in enumerate(nodes):
-        others = [x for k, x in enumerate(nodes) if k != i]
-        den = np.prod([xi_i - x for x in others])
-        w.append(np.prod([xi - x for x in others]) / den)
+    for i, zi in enumerate(nodes):
+        others = [z for k, z in enumerate(nodes) if k != i]
+        den = np.prod([zi - z for z in others])
+        w.append(np.prod([f - z for z in others]) / den)
         d = 0.0
         for k in range(3):
-            d += np.prod([xi - x for kk, x in enumerate(others) if kk != k])
+            d += np.prod([f - z for kk, z in enumerate(others) if kk != k])
         dw.append(d / den)
-    return np.array(w), np.array(dw)
+    return j0, np.array(w), np.array(dw)
+
+
+def horizon_weights(xi):
+    """Weights on the nodes at offsets -1, 0, 1, 2 for the value and the
+    derivative at offset xi in [0, 1) (an interior horizon)."""
+    j0, w, dw = horizon_stencil(1.0 + xi, 10**6)
+    return w, dw

@@ -246,17 +246,17 @@ class TeukOracle:
 
     def horizon(self, u):
         """Phi and d_rho Phi on the horizon rho_H = S r+ / (r+ + S) (chart H),
-        per theta row, by 4-point Lagrange interpolation on the nodes around it.
-        Returns complex arrays (Phi_H[nth], dPhi_H[nth])."""
+        per theta row, by 4-point Lagrange interpolation on the nodes around it
+        (one-sided at the grid's inner end).  Returns complex arrays
+        (Phi_H[nth], dPhi_H[nth])."""
         from . import hyperboloidal as hyp
         p = self.prob
         rp, _ = coeffs.horizons(p.M, p.a)
         rho_h = p.S * rp / (rp + p.S)
-        j = int(np.floor((rho_h - p.x_min) / p.dx))
-        xi = (rho_h - (p.x_min + j * p.dx)) / p.dx
-        w, dw = hyp.horizon_weights(xi)
+        f = (rho_h - p.x_min) / p.dx
+        j0, w, dw = hyp.horizon_stencil(f, p.nr)
         ph = u[0] + 1j * u[1]
-        win = ph[:, j - 1:j + 3]
+        win = ph[:, j0:j0 + 4]
         return win @ w, (win @ dw) / p.dx
 
     def evolve(self, u0, dt, nsteps, x_e=None, every=0, max_samples=0):

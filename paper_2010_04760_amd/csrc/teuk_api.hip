@@ -26,7 +26,7 @@ struct teuk_solver {
     double* ctab = nullptr;                         // chart H per-point table
     double* wave = nullptr;
     double* hwave = nullptr;                        // chart H horizon ring [samples][nth][4]
-    int j_h = 0;                                    // chart H: horizon between nodes j_h and j_h + 1
+    int j_h = 0;                                    // chart H: first of the four horizon-stencil nodes
     double hw[4] = {0, 0, 0, 0}, hdw[4] = {0, 0, 0, 0};   // horizon value / derivative weights
     unsigned long long* cell = nullptr;             // dt-bound reduction cell
     int* flag = nullptr;                            // non-finite flag
@@ -90,35 +90,40 @@ Layout layout_of(const teuk_config& c)
     return L;
 }
 
-// Horizon of the hyperboloidal chart between nodes j and j+1: 4-point Lagrange
-// weights on the nodes j-1 .. j+2 for the value (w) and the rho-derivative (dw,
-// divided by dx) at rho_H = S r+ / (r+ + S).  False if the stencil leaves the grid.
-bool horizon_stencil(const teuk_config& c, int* j, double* w, double* dw)
+// Horizon of the hyperboloidal chart, rho_H = S r+ / (r+ + S), at fractional
+// node position f = (rho_H - x_min)/dx: the four nodes j0 .. j0+3 around it
+// (j0 = floor(f) - 1, shifted to stay inside the grid, i.e. one-sided when the
+// grid starts on the horizon) and the 4-point Lagrange weights for the value
+// (w) and the rho-derivative (dw, divided by dx).  False unless
+// -1/2 <= f <= nr - 3/2 (at most half a step of extrapolation at either end).
+bool horizon_stencil(const teuk_config& c, int* j0, double* w, double* dw)
 {
     const double d2 = c.M * c.M - c.a * c.a;
     const double rp = c.M + (d2 > 0.0 ? std::sqrt(d2) : 0.0);
     const double rho_h = c.S * rp / (rp + c.S);
     const double dx = (c.x_max - c.x_min) / (c.nr - 1);
     const double f = (rho_h - c.x_min) / dx;
-    if (!(f >= 1.0) || !(f < (double)(c.nr - 3))) return false;
-    const int jj = (int)std::floor(f);
-    const double xi = (rho_h - (c.x_min + dx * jj)) / dx;     // in [0, 1)
-    const double z[4] = {-1.0, 0.0, 1.0, 2.0};
+    if (!(f >= -0.5) || !(f <= c.nr - 1.5) || c.nr < 4) return false;
+    int jj = (int)std::floor(f) - 1;
+    if (jj < 0) jj = 0;
+    if (jj > c.nr - 4) jj = c.nr - 4;
     for (int i = 0; i < 4; ++i) {
+        const double zi = jj + i;
         double num = 1.0, den = 1.0, dsum = 0.0;
         for (int k = 0; k < 4; ++k) {
             if (k == i) continue;
-            num *= xi - z[k];
-            den *= z[i] - z[k];
-            double prod = 1.0;                                 // d/dxi of the product, term k left out
+            const double zk = jj + k;
+            num *= f - zk;
+            den *= zi - zk;
+            double prod = 1.0;                                 // d/df of the product, factor k left out
             for (int q = 0; q < 4; ++q)
-                if (q != i && q != k) prod *= xi - z[q];
+                if (q != i && q != k) prod *= f - (jj + q);
             dsum += prod;
         }
         w[i] = num / den;
         dw[i] = dsum / den / dx;
     }
-    *j = jj;
+    *j0 = jj;
     return true;
 }
 
@@ -151,8 +156,8 @@ bool validate(const teuk_config* c, std::string& err)
         int jh;
         double w[4], dw[4];
         if (!horizon_stencil(*c, &jh, w, dw)) {
-            err = "hyperboloidal chart needs the horizon rho_H = S r+/(r+ + S) inside the grid with one node "
-                  "below and two above it";
+            err = "hyperboloidal chart needs the horizon rho_H = S r+/(r+ + S) on the grid (at most half a "
+                  "step outside it) and nr >= 4";
             return false;
         }
     }

@@ -169,6 +169,7 @@ bool build_tables(const teuk_config& c, std::vector<double>& rtab, std::vector<d
 // with d_rho b = (d_r b)/rho'.  Evaluated in long double and rounded once.
 bool build_tables_H(const teuk_config& c, std::vector<double>& ctab, std::string& err)
 {
+    (void)err;   // every node is admissible: the forms are regular through the horizon
     typedef long double L;
     const int nr = c.nr, nth = c.ntheta;
     const L M = c.M, a = c.a, S = c.S, s = c.s, m = c.m;
@@ -185,10 +186,6 @@ bool build_tables_H(const teuk_config& c, std::vector<double>& ctab, std::string
         const L r = x * S / (S - x);
         const L y = S * S * (x - rho_h) / ((S - x) * (S - rho_h));   // r - r+
         const L D = y * (y + (rp - rm));
-        if (y == 0.0L) {
-            err = "a radial node lies on the horizon rho_H; shift x_min";
-            return false;
-        }
         const L Dp = 2 * (r - M);
         const L u = r + S;
         const L r1 = S * S / (u * u), r2 = -2 * S * S / (u * u * u);

@@ -65,9 +65,9 @@ int launch_extract(const double* u, long long plane, int nr, int nth, int j_e, d
                    void* stream);
 int launch_coef_dump(const double* rtab, const double* ttab, const double* ctab, int nr, int nth, double* out,
                      void* stream);
-// Horizon sample: Phi and d_rho Phi from the nodes j_h-1 .. j_h+2 with value
+// Horizon sample: Phi and d_rho Phi from the nodes j0 .. j0+3 with value
 // weights w[4] and derivative weights dw[4] (divided by dx); slot is [nth][4].
-int launch_horizon(const double* u, long long plane, int nr, int nth, int j_h, const double* w, const double* dw,
+int launch_horizon(const double* u, long long plane, int nr, int nth, int j0, const double* w, const double* dw,
                    double* slot, void* stream);
 
 }  // namespace teuk

@@ -625,18 +625,18 @@ __global__ __launch_bounds__(256) void extract_kernel(const double* __restrict__
 }
 
 // ---------------------------------------------------------------- horizon sample
-// Phi and d_rho Phi on the horizon from the four nodes j_h - 1 .. j_h + 2 with
+// Phi and d_rho Phi on the horizon from the four nodes j0 .. j0 + 3 with
 // interpolation weights w (value) and dw (derivative, already divided by dx).
 struct HorizonWeights {
     double w[4], dw[4];
 };
 __global__ __launch_bounds__(256) void horizon_kernel(const double* __restrict__ u, long long plane, int nr,
-                                                      int nth, int j_h, HorizonWeights W,
+                                                      int nth, int j0, HorizonWeights W,
                                                       double* __restrict__ slot)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < nth) {
-        const double* pr = u + (size_t)k * nr + (j_h - 1);
+        const double* pr = u + (size_t)k * nr + j0;
         const double* pi = pr + plane;
         double vr = 0.0, vi = 0.0, dr = 0.0, di = 0.0;
         for (int q = 0; q < 4; ++q) {
@@ -798,10 +798,10 @@ int launch_extract(const double* u, long long plane, int nr, int nth, int j_e, d
     return (int)hipGetLastError();
 }
 
-int launch_horizon(const double* u, long long plane, int nr, int nth, int j_h, const double* w, const double* dw,
+int launch_horizon(const double* u, long long plane, int nr, int nth, int j0, const double* w, const double* dw,
                    double* slot, void* stream)
 {
-    if (j_h < 1 || j_h + 2 > nr - 1) return (int)hipErrorInvalidValue;
+    if (j0 < 0 || j0 + 3 > nr - 1) return (int)hipErrorInvalidValue;
     HorizonWeights W;
     for (int q = 0; q < 4; ++q) {
         W.w[q] = w[q];
@@ -809,7 +809,7 @@ int launch_horizon(const double* u, long long plane, int nr, int nth, int j_h, c
     }
     (void)hipGetLastError();
     hipLaunchKernelGGL(horizon_kernel, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, (hipStream_t)stream, u,
-                       plane, nr, nth, j_h, W, slot);
+                       plane, nr, nth, j0, W, slot);
     return (int)hipGetLastError();
 }
 

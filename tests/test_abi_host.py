@@ -120,14 +120,16 @@ def test_chart_H_validation():
     x0, x1 = chart_h_grid(a, 101)
     ok = T.make_config(s=-2, m=0, a=a, nr=101, ntheta=8, x_min=x0, x_max=x1, chart="H", S=20.0)
     assert T.teuk_footprint_bytes(ok) > 0
+    # a grid that starts on the horizon is admissible (one-sided horizon stencil)
+    on = T.make_config(s=-2, m=0, a=a, nr=101, ntheta=8, x_min=20.0 / 21.0, x_max=x1, chart="H", S=20.0)
+    assert T.teuk_footprint_bytes(on) > 0
     rp, _ = S_oracle_horizons(a)
     rho_h = 20.0 * rp / (rp + 20.0)
     bad = [
         dict(x_min=x0, x_max=20.0),                 # reaches S
         dict(x_min=0.0, x_max=x1),                  # r = 0
-        dict(x_min=rho_h + 0.1, x_max=x1),          # horizon below the grid
+        dict(x_min=rho_h + 0.5, x_max=x1),          # horizon more than half a step below the grid
         dict(x_min=x0, x_max=x1, S=-1.0),
-        dict(x_min=rho_h - 0.2 * (x1 - rho_h) / 100, x_max=x1),   # no node below the horizon
     ]
     for kw in bad:
         args = dict(s=-2, m=0, a=a, nr=101, ntheta=8, chart="H", S=20.0)

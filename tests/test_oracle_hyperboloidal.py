@@ -217,6 +217,31 @@ def test_speeds_chart_H(a):
     assert np.all(np.sign(o.tab["lam2"]) == np.sign(Delta)[None, :])
 
 
+def test_horizon_stencil_one_sided_exact_on_cubics():
+    rng = np.random.default_rng(2)
+    for f, nr in ((0.0, 50), (0.3, 50), (-0.4, 50), (48.2, 50), (7.6, 50)):
+        j0, w, dw = H.horizon_stencil(f, nr)
+        assert 0 <= j0 <= nr - 4
+        c = rng.standard_normal(4)
+        p = lambda z: c[0] + c[1] * z + c[2] * z * z + c[3] * z**3
+        dp = lambda z: c[1] + 2 * c[2] * z + 3 * c[3] * z * z
+        vals = np.array([p(float(j0 + i)) for i in range(4)])
+        assert abs(vals @ w - p(f)) < 1e-9 * max(1.0, abs(p(f)))
+        assert abs(vals @ dw - dp(f)) < 1e-9 * max(1.0, abs(dp(f)))
+
+
+def test_coefficients_a_hair_from_the_horizon():
+    """A node within rounding of the extremal horizon (the grid that starts on
+    it): the extra working precision keeps the tables equal to their limit,
+    i.e. continuous with the neighbouring nodes."""
+    rho_h = 20.0 / 21.0
+    rho = np.array([rho_h, rho_h + 1e-9, rho_h + 1e-6])
+    tab = H.first_order_tables(rho, np.array([0.6]), 1.0, 1.0, -2, 0, SS)
+    for k, v in tab.items():
+        assert np.all(np.isfinite(v)), k
+        assert abs(v[0, 0] - v[0, 1]) <= 1e-7 * max(1.0, abs(v[0, 2])), (k, v)
+
+
 def test_horizon_weights_exact_on_cubics():
     rng = np.random.default_rng(1)
     for xi in (0.0, 0.25, 0.5, 0.9):

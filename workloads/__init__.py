@@ -65,11 +65,12 @@ C3 = Workload("C3: s=0 m=0 a=1 16384x128, 200000 steps", s=0, m=0, a=1.0, nr=163
 
 # The horizon experiment of Sec. 4 in the hyperboloidal chart: s = -2, the
 # (l, m) = (2, 0) profile, extremal Kerr, a Gaussian packet centred at rho = 1.0
-# of width 0.22, S = 20, 16384 (rho) x 64 (theta).  The grid starts inside the
-# horizon (r = 0.9, rho = 0.8612) and stops short of null infinity (rho = S);
-# the waveform is read at rho = 19.5 (r = 780).
+# of width 0.22, S = 20, 16384 (rho) x 64 (theta).  The grid starts on the
+# horizon rho_H = 20/21 (r = M), where the pi-row speed vanishes, so that its
+# inner edge takes no incoming data, and stops short of null infinity
+# (rho = S); the waveform is read at rho = 19.5 (r = 780).
 C3H = Workload("C3-H: s=-2 m=0 a=1 hyperboloidal 16384x64", s=-2, m=0, a=1.0, nr=16384, nth=64,
-               x_min=0.8612, x_max=19.99, steps=200000, seed=3, angular="P2", x_e=19.5, every=100,
+               x_min=20.0 / 21.0, x_max=19.99, steps=200000, seed=3, angular="P2", x_e=19.5, every=100,
                amp_range=(1.0, 1.0), xc_range=(1.0, 1.0), w_range=(0.22, 0.22), chart="H", S=20.0)
 
 
