@@ -341,11 +341,11 @@ def bench_horizon(args, torch, T, W):
         probe_t = np.linspace(25.0, args.tau_end, 400)
         re = 2 * np.interp(probe_t, tf, yf) - np.interp(probe_t, tc, yc)
         pre = local_index(probe_t, re)
-        early = (probe_t[1:-1] >= 50.0) & (probe_t[1:-1] <= 150.0)
+        early = (probe_t[1:-1] >= 50.0) & (probe_t[1:-1] <= 110.0)
         late = tf[1:-1] >= 0.5 * tf[-1]
         out["horizon_laws"] = {
             "grids": [f"{args.physics_nr}x32", f"{2 * args.physics_nr}x32"], "tau_end": float(tf[-1]),
-            "phi_h_local_index_richardson_tau_50_150": float(np.mean(pre[early])), "expected_phi_h": -1.0,
+            "phi_h_local_index_richardson_tau_50_110": float(np.mean(pre[early])), "expected_phi_h": -1.0,
             "dphi_h_local_index_fine_late": float(np.mean(local_index(tf, df)[late])), "expected_dphi_h": 0.0,
             "phi_h_floor_coarse": float(yc[-1]), "phi_h_floor_fine": float(yf[-1]),
             "dphi_h_end_fine": float(df[-1]), "seconds_fine": secf, "steps_fine": nf,

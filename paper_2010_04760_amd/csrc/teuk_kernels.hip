@@ -388,16 +388,14 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
         }
         lds_sync();
 
-        double dPhR, dPhI, dPiR, dPiI;
+        double dPhR = 0.0, dPhI = 0.0, dPiR = 0.0, dPiI = 0.0;
+        double fR = 0.0, fI = 0.0, gR = 0.0, gI = 0.0, fR1 = 0.0, fI1 = 0.0, gR1 = 0.0, gI1 = 0.0;
         if constexpr (kChart == kChartT) {
-            const double fR = Weno<WP>::flux6(s[b][0][l], s[b][0][l + 1], s[b][0][l + 2], s[b][0][l + 3], s[b][0][l + 4], A.eps);
-            const double fI = Weno<WP>::flux6(s[b][1][l], s[b][1][l + 1], s[b][1][l + 2], s[b][1][l + 3], s[b][1][l + 4], A.eps);
-            const double gR = Weno<WP>::flux6(s[b][2][l + 5], s[b][2][l + 4], s[b][2][l + 3], s[b][2][l + 2], s[b][2][l + 1], A.eps);
-            const double gI = Weno<WP>::flux6(s[b][3][l + 5], s[b][3][l + 4], s[b][3][l + 3], s[b][3][l + 2], s[b][3][l + 1], A.eps);
-            dPhR = (__shfl_down(fR, 1) - fR) * A.inv6dx;
-            dPhI = (__shfl_down(fI, 1) - fI) * A.inv6dx;
-            dPiR = (__shfl_down(gR, 1) - gR) * A.inv6dx;
-            dPiI = (__shfl_down(gI, 1) - gI) * A.inv6dx;
+            // differenced below, inside the active-lane branch
+            fR = Weno<WP>::flux6(s[b][0][l], s[b][0][l + 1], s[b][0][l + 2], s[b][0][l + 3], s[b][0][l + 4], A.eps);
+            fI = Weno<WP>::flux6(s[b][1][l], s[b][1][l + 1], s[b][1][l + 2], s[b][1][l + 3], s[b][1][l + 4], A.eps);
+            gR = Weno<WP>::flux6(s[b][2][l + 5], s[b][2][l + 4], s[b][2][l + 3], s[b][2][l + 2], s[b][2][l + 1], A.eps);
+            gI = Weno<WP>::flux6(s[b][3][l + 5], s[b][3][l + 4], s[b][3][l + 3], s[b][3][l + 2], s[b][3][l + 1], A.eps);
         } else {
             // upwind side per lane and row: speed >= 0 -> f^+, speed < 0 -> f^-
             const bool up1 = hc[kHLam1] >= 0.0, up2 = hc[kHLam2] >= 0.0;
@@ -432,10 +430,20 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
             ahR = A.parity * phR;
             ahI = A.parity * phI;
         }
+        if constexpr (kChart == kChartT) {
+            fR1 = __shfl_down(fR, 1);
+            fI1 = __shfl_down(fI, 1);
+            gR1 = __shfl_down(gR, 1);
+            gI1 = __shfl_down(gI, 1);
+        }
 
         if (active) {
             double lam1, lam2n, m3r, m3i, btr, bti, cr, ci, ath, bth;   // lam2n = -lam2
             if constexpr (kChart == kChartT) {
+                dPhR = (fR1 - fR) * A.inv6dx;
+                dPhI = (fI1 - fI) * A.inv6dx;
+                dPiR = (gR1 - gR) * A.inv6dx;
+                dPiI = (gI1 - gI) * A.inv6dx;
                 const PointCoef c = point_coef(rt, sn2, cs, cot, th, rsq64(sigma2(rt, sn2)));
                 lam1 = c.b; lam2n = c.b; m3r = c.m3r; m3i = c.m3i; btr = c.btr; bti = c.bti;
                 cr = c.cr; ci = c.ci; ath = c.ath; bth = c.bth;
