@@ -269,6 +269,47 @@ __device__ __forceinline__ void stb(double* base, unsigned off, double v)
     *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + off) = v;
 }
 
+// ---------------------------------------------------------------- chart-T row pipeline
+// The tortoise-chart stage streams each theta row of the four planes straight
+// from HBM into a four-row LDS ring with LDS-DMA loads (global_load_lds: every
+// lane moves one dword, no VGPRs involved), three rows ahead of the row being
+// computed.  The compiler does not model these loads, so they and the u^n
+// loads are issued from inline assembly and waited for with explicit vmcnt
+// counts.  Each count covers only the loads issued here; any other memory
+// operation the compiler places in between can only make a wait stricter.
+constexpr int kRowP = 72;                                   // LDS row stride (doubles)
+constexpr int kRing = 4;                                    // rows in the LDS ring
+constexpr unsigned kPlaneBytes = kRowP * 8;                 // 576
+constexpr unsigned kSlotBytes = 4 * kPlaneBytes;            // 2304
+
+// One LDS-DMA dword per lane: LDS[m0 + 4 lane] = global[sbase + voff].
+__device__ __forceinline__ void dma_dword(unsigned voff, const double* sbase, unsigned lds)
+{
+    asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dword %0, %1" : : "v"(voff), "s"(sbase), "s"(lds) : "memory");
+}
+
+// A double from global memory whose arrival is waited for explicitly.
+__device__ __forceinline__ double ld_async(unsigned voff, const double* sbase)
+{
+    double v;
+    asm volatile("global_load_dwordx2 %0, %1, %2" : "=v"(v) : "v"(voff), "s"(sbase) : "memory");
+    return v;
+}
+
+// Wait until at most N vector-memory operations are outstanding.
+template <int N>
+__device__ __forceinline__ void vm_wait()
+{
+    asm volatile("s_waitcnt vmcnt(%0)" : : "n"(N) : "memory");
+}
+// The same, also making four values depend on the wait (so that no use of
+// them can be scheduled before it).
+template <int N>
+__device__ __forceinline__ void vm_wait(double& a, double& b, double& c, double& d)
+{
+    asm volatile("s_waitcnt vmcnt(%4)" : "+v"(a), "+v"(b), "+v"(c), "+v"(d) : "n"(N) : "memory");
+}
+
 // One radial strip [j0, j0 + 63) marched over the theta rows [k0, k1), upward
 // (dir = +1, from k0) or downward (dir = -1, from k1 - 1).  Rows are staged in
 // a two-row LDS ring: while row k is computed from LDS, the loads of row
@@ -492,6 +533,163 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
     }
 }
 
+// Chart-T march of one strip over rows [k0, k1) with the LDS-DMA row pipeline.
+// Row i of the march (k = first + dir i) lives in ring slot i mod 4; the
+// rows first, first + dir, first + 2 dir are issued before the loop and row
+// i + 3 at the top of iteration i.  Where the march has no such row, one
+// cache line is loaded into the free slot instead, so that every iteration
+// issues the same operations and the wait counts are constants:
+//     per iteration: [u^n of row i: 4 loads (later stages)] [row i + 3: 12 DMA];
+//     before reading rows i and i + 1: everything up to row i + 1 has landed,
+//         i.e. vmcnt <= (12 + it) at i = 0 and vmcnt <= 2 it for i >= 1,
+//         it = loads per iteration (16 later stages, 12 otherwise);
+//     before the stores: u^n of row i has landed, vmcnt <= 12.
+template <int WP, int kMode>
+__device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, int strip, int k0, int k1, int dir)
+{
+    const int l = threadIdx.x;
+    const int nr = A.nr, nth = A.nth;
+    const long long P = A.plane;
+    const int j0 = strip * kStripPoints;
+    const int j = j0 + l;
+    const bool active = (l < kStripPoints) && (j < nr);
+    const int jc = min(j, nr - 1);
+    const unsigned oc = (unsigned)jc * 8u;                                 // own point
+    // staged dword d = 64 c + l of a row holds half (d & 1) of position j0 - 3 + d/2
+    unsigned od[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int d = 64 * c + l;
+        od[c] = (unsigned)clampi(j0 - 3 + (d >> 1), 0, nr - 1) * 8u + (unsigned)(d & 1) * 4u;
+    }
+    const unsigned lds0 = (unsigned)(size_t)ring;          // LDS byte address of the ring
+    const double* ukp[4] = {A.uk, A.uk + P, A.uk + 2 * P, A.uk + 3 * P};
+    const double* unp[4] = {A.un, A.un + P, A.un + 2 * P, A.un + 3 * P};
+    double* outp[4] = {A.out, A.out + P, A.out + 2 * P, A.out + 3 * P};
+
+    double rt[kNRT];
+#pragma unroll
+    for (int i = 0; i < kNRT; ++i) rt[i] = ldb(A.rtab + (size_t)i * nr, oc);
+    const __attribute__((address_space(4))) double* tt =
+        (const __attribute__((address_space(4))) double*)A.ttab;
+
+    const int n = k1 - k0;
+    const int first = dir > 0 ? k0 : k1 - 1;
+    double bhR, bhI;
+    {
+        const int kb = first - dir;
+        if (kb >= 0 && kb < nth) {
+            bhR = ldb(ukp[0] + (size_t)kb * nr, oc);
+            bhI = ldb(ukp[1] + (size_t)kb * nr, oc);
+        } else {
+            bhR = A.parity * ldb(ukp[0] + (size_t)first * nr, oc);
+            bhI = A.parity * ldb(ukp[1] + (size_t)first * nr, oc);
+        }
+    }
+    const int ahead_last = first + dir * n;
+    const int nst = (ahead_last >= 0 && ahead_last < nth) ? n + 1 : n;
+
+    // 12 DMA operations: march row i into its slot, or, where the march has no
+    // row i, the first dword of each plane (one cache line, read by every lane)
+    // into the free slot
+    auto issue_row = [&](int i) {
+        const bool real = i < nst;
+        const size_t row = real ? (size_t)(first + dir * i) * nr : 0;
+        const unsigned slot = lds0 + (unsigned)(i & (kRing - 1)) * kSlotBytes;
+        const unsigned o0 = real ? od[0] : 0u, o1 = real ? od[1] : 0u, o2 = real ? od[2] : 0u;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const double* base = ukp[p] + row;
+            dma_dword(o0, base, slot + p * kPlaneBytes);
+            dma_dword(o1, base, slot + p * kPlaneBytes + 256u);
+            if (l < 10) dma_dword(o2, base, slot + p * kPlaneBytes + 512u);
+        }
+    };
+    issue_row(0);
+    issue_row(1);
+    issue_row(2);
+
+    const double (*sr)[4][kRowP] = reinterpret_cast<const double (*)[4][kRowP]>(ring);
+    for (int i = 0; i < n; ++i) {
+        const int k = first + dir * i;
+        const size_t row = (size_t)k * nr;
+        const double sn2 = tt[kSn2 * nth + k];
+        const double cs = tt[kCs * nth + k];
+        const double cot = tt[kCot * nth + k];
+        const double th = tt[kTh * nth + k];
+        double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
+        if (kMode == kStageLater) {
+            n0 = ld_async(oc, unp[0] + row);
+            n1 = ld_async(oc, unp[1] + row);
+            n2 = ld_async(oc, unp[2] + row);
+            n3 = ld_async(oc, unp[3] + row);
+        }
+        issue_row(i + 3);
+        constexpr int it = kMode == kStageLater ? 16 : 12;
+        if (i == 0) vm_wait<12 + it>();
+        else vm_wait<2 * it>();
+        const int b = i & (kRing - 1), bn = (i + 1) & (kRing - 1);
+
+        const double fR = Weno<WP>::flux6(sr[b][0][l], sr[b][0][l + 1], sr[b][0][l + 2], sr[b][0][l + 3], sr[b][0][l + 4], A.eps);
+        const double fI = Weno<WP>::flux6(sr[b][1][l], sr[b][1][l + 1], sr[b][1][l + 2], sr[b][1][l + 3], sr[b][1][l + 4], A.eps);
+        const double gR = Weno<WP>::flux6(sr[b][2][l + 5], sr[b][2][l + 4], sr[b][2][l + 3], sr[b][2][l + 2], sr[b][2][l + 1], A.eps);
+        const double gI = Weno<WP>::flux6(sr[b][3][l + 5], sr[b][3][l + 4], sr[b][3][l + 3], sr[b][3][l + 2], sr[b][3][l + 1], A.eps);
+        const double phR = sr[b][0][l + 3], phI = sr[b][1][l + 3];
+        const double piR = sr[b][2][l + 3], piI = sr[b][3][l + 3];
+        double ahR, ahI;   // Phi on the row ahead (k + dir)
+        if (i + 1 < nst) {
+            ahR = sr[bn][0][l + 3];
+            ahI = sr[bn][1][l + 3];
+        } else {
+            ahR = A.parity * phR;
+            ahI = A.parity * phI;
+        }
+        const double fR1 = __shfl_down(fR, 1);
+        const double fI1 = __shfl_down(fI, 1);
+        const double gR1 = __shfl_down(gR, 1);
+        const double gI1 = __shfl_down(gI, 1);
+
+        if (kMode == kStageLater) vm_wait<12>(n0, n1, n2, n3);
+        if (active) {
+            const double dPhR = (fR1 - fR) * A.inv6dx;
+            const double dPhI = (fI1 - fI) * A.inv6dx;
+            const double dPiR = (gR1 - gR) * A.inv6dx;
+            const double dPiI = (gI1 - gI) * A.inv6dx;
+            const PointCoef c = point_coef(rt, sn2, cs, cot, th, rsq64(sigma2(rt, sn2)));
+            const double upR = dir > 0 ? ahR : bhR, upI = dir > 0 ? ahI : bhI;
+            const double dnR = dir > 0 ? bhR : ahR, dnI = dir > 0 ? bhI : ahI;
+            const double d1R = (upR - dnR) * A.ih1, d1I = (upI - dnI) * A.ih1;
+            const double d2R = (upR - 2.0 * phR + dnR) * A.ih2;
+            const double d2I = (upI - 2.0 * phI + dnI) * A.ih2;
+            const double FphR = piR - c.b * dPhR;
+            const double FphI = piI - c.b * dPhI;
+            const double FpiR = c.b * dPiR - (c.m3r * dPhR - c.m3i * dPhI) + (c.btr * piR - c.bti * piI) +
+                                c.ath * d2R + c.bth * d1R + (c.cr * phR - c.ci * phI);
+            const double FpiI = c.b * dPiI - (c.m3r * dPhI + c.m3i * dPhR) + (c.btr * piI + c.bti * piR) +
+                                c.ath * d2I + c.bth * d1I + (c.cr * phI + c.ci * phR);
+            if (kMode == kRhsOnly) {
+                stb(outp[0] + row, oc, FphR);
+                stb(outp[1] + row, oc, FphI);
+                stb(outp[2] + row, oc, FpiR);
+                stb(outp[3] + row, oc, FpiI);
+            } else if (kMode == kStageFirst) {
+                stb(outp[0] + row, oc, phR + A.dt * FphR);
+                stb(outp[1] + row, oc, phI + A.dt * FphI);
+                stb(outp[2] + row, oc, piR + A.dt * FpiR);
+                stb(outp[3] + row, oc, piI + A.dt * FpiI);
+            } else {
+                stb(outp[0] + row, oc, A.ca * n0 + A.cb * (phR + A.dt * FphR));
+                stb(outp[1] + row, oc, A.ca * n1 + A.cb * (phI + A.dt * FphI));
+                stb(outp[2] + row, oc, A.ca * n2 + A.cb * (piR + A.dt * FpiR));
+                stb(outp[3] + row, oc, A.ca * n3 + A.cb * (piI + A.dt * FpiI));
+            }
+        }
+        bhR = phR;
+        bhI = phI;
+    }
+    vm_wait<0>();   // nothing of this strip may still be landing in the ring
+}
+
 // Launch layout: every radial strip is cut into the same number `segs` of theta
 // segments (an even number when there is more than one), workgroup
 // rank = strip * segs + i owns segment i of its strip, and even segments march
@@ -500,14 +698,27 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
 // of neighbouring strips -- which share the radial halo -- march the same rows
 // in step, so the shared lines are read from HBM once and hit in L2 for the
 // second reader.
+// LDS of one stage workgroup: the four-row DMA ring (chart T) or the two-row
+// staging ring (chart H).
+constexpr unsigned kLdsBytes = kRing * kSlotBytes;   // 9216 >= 2 * 4 * kRow * 8
+
 template <int WP, int kMode, int kChart>
-__device__ __forceinline__ void run_tile(const StageArgs& A, double (*s)[4][kRow], int rank)
+__device__ __forceinline__ void march(const StageArgs& A, char* lds, int strip, int k0, int k1, int dir)
+{
+    if constexpr (kChart == kChartT)
+        march_strip_t<WP, kMode>(A, lds, strip, k0, k1, dir);
+    else
+        march_strip<WP, kMode, kChart>(A, reinterpret_cast<double (*)[4][kRow]>(lds), strip, k0, k1, dir);
+}
+
+template <int WP, int kMode, int kChart>
+__device__ __forceinline__ void run_tile(const StageArgs& A, char* lds, int rank)
 {
     const int strip = rank / A.segs;
     const int seg = rank - strip * A.segs;
     const int k0 = (int)((long long)A.nth * seg / A.segs);
     const int k1 = (int)((long long)A.nth * (seg + 1) / A.segs);
-    if (k1 > k0) march_strip<WP, kMode, kChart>(A, s, strip, k0, k1, (seg & 1) ? -1 : 1);
+    if (k1 > k0) march<WP, kMode, kChart>(A, lds, strip, k0, k1, (seg & 1) ? -1 : 1);
 }
 
 // Ranks are dealt so that each XCD (which receives every eighth workgroup id)
@@ -522,8 +733,8 @@ __device__ __forceinline__ int xcd_rank(int bid, int G)
 template <int WP, int kMode, int kChart>
 __global__ __launch_bounds__(kWave) void stage_kernel(StageArgs A)
 {
-    __shared__ double s[2][4][kRow];
-    run_tile<WP, kMode, kChart>(A, s, xcd_rank((int)blockIdx.x, (int)gridDim.x));
+    __shared__ __attribute__((aligned(16))) char lds[kLdsBytes];
+    run_tile<WP, kMode, kChart>(A, lds, xcd_rank((int)blockIdx.x, (int)gridDim.x));
 }
 
 // One stage of several independent solves in one launch.  Member m is cut
@@ -545,7 +756,7 @@ __global__ __launch_bounds__(kWave) void group_stage_kernel(const StageArgs* __r
                                                             const long long* __restrict__ start, int nmem,
                                                             long long tiles)
 {
-    __shared__ double s[2][4][kRow];
+    __shared__ __attribute__((aligned(16))) char lds[kLdsBytes];
     const int G = (int)gridDim.x;
     for (long long t = xcd_rank((int)blockIdx.x, G); t < tiles; t += G) {
         int lo = 0, hi = nmem - 1;
@@ -560,7 +771,7 @@ __global__ __launch_bounds__(kWave) void group_stage_kernel(const StageArgs* __r
         const int strip = local - seg * A.nstrips;
         const int k0 = (int)((long long)A.nth * seg / A.segs);
         const int k1 = (int)((long long)A.nth * (seg + 1) / A.segs);
-        if (k1 > k0) march_strip<WP, kMode, kChart>(A, s, strip, k0, k1, (seg & 1) ? -1 : 1);
+        if (k1 > k0) march<WP, kMode, kChart>(A, lds, strip, k0, k1, (seg & 1) ? -1 : 1);
     }
 }
 
