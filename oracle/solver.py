@@ -1,5 +1,7 @@
 """Oracle: Python driver for the plain FP64 Teukolsky solver in teuk_oracle.c.
 
+(The binary128 build of the same source is driven by ``oracle.quad``.)
+
 TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
 leg of the benchmark import this module; the product path never does.
 
@@ -26,23 +28,33 @@ _LIB = os.path.join(_HERE, "_liboracle.so")
 _dp = ctypes.POINTER(ctypes.c_double)
 
 
-def build_oracle(verbose: bool = False) -> str:
-    """Compile teuk_oracle.c with gcc (rounding exactly as written: no
-    contraction, no fast math).  Returns the library path."""
+_LIBQ = os.path.join(_HERE, "_liboracle_q.so")
+
+
+def _compile(out: str, defines, verbose: bool):
     cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
-           "-shared", _SRC, "-o", _LIB + ".tmp", "-lm"]
+           *defines, "-shared", _SRC, "-o", out + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(_LIB + ".tmp", _LIB)
+    os.replace(out + ".tmp", out)
+
+
+def build_oracle(verbose: bool = False) -> str:
+    """Compile teuk_oracle.c with gcc (rounding exactly as written: no
+    contraction, no fast math), once with FP64 and once with binary128 as the
+    working precision.  Returns the FP64 library path."""
+    _compile(_LIB, [], verbose)
+    _compile(_LIBQ, ["-DORACLE_QUAD"], verbose)
     return _LIB
 
 
 class _OracleTeuk(ctypes.Structure):
     _fields_ = [("nr", ctypes.c_long), ("nth", ctypes.c_long),
-                ("dx", ctypes.c_double), ("dth", ctypes.c_double), ("eps", ctypes.c_double),
-                ("parity", ctypes.c_double)] + [
-                (n, _dp) for n in ("lam1", "lam2", "m3r", "m3i", "btr", "bti", "cr", "ci", "ath", "bth")]
+                ("dx", ctypes.c_double), ("dx_lo", ctypes.c_double),
+                ("dth", ctypes.c_double), ("dth_lo", ctypes.c_double), ("eps", ctypes.c_double),
+                ("parity", ctypes.c_double), ("wmode", ctypes.c_int)] + [
+                (n, ctypes.c_void_p) for n in ("lam1", "lam2", "m3r", "m3i", "btr", "bti", "cr", "ci", "ath", "bth")]
 
 
 RHS_FN = ctypes.CFUNCTYPE(None, _dp, _dp, ctypes.c_void_p)
@@ -55,7 +67,7 @@ def lib() -> ctypes.CDLL:
     global _lib_handle
     if _lib_handle is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build_oracle()
+            _compile(_LIB, [], False)
         L = ctypes.CDLL(_LIB)
         L.oracle_weno5_weights_plus.argtypes = [_dp, ctypes.c_double, _dp]
         L.oracle_weno5_weights_minus.argtypes = [_dp, ctypes.c_double, _dp]
@@ -66,14 +78,16 @@ def lib() -> ctypes.CDLL:
             getattr(L, fn).argtypes = [_dp, _dp]
             getattr(L, fn).restype = ctypes.c_double
         for fn in ("oracle_dplus", "oracle_dminus"):
-            getattr(L, fn).argtypes = [_dp, ctypes.c_long, ctypes.c_double, ctypes.c_double]
+            getattr(L, fn).argtypes = [_dp, ctypes.c_long, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int]
             getattr(L, fn).restype = ctypes.c_double
         L.oracle_ssprk3_step.argtypes = [_dp, ctypes.c_long, ctypes.c_double, RHS_FN, ctypes.c_void_p, _dp]
-        L.oracle_advect1d.argtypes = [_dp, ctypes.c_long, ctypes.c_double, ctypes.c_double,
-                                      ctypes.c_double, ctypes.c_long, ctypes.c_double]
+        L.oracle_advect1d.argtypes = [_dp, ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_long, ctypes.c_double,
+                                      ctypes.c_int]
         L.oracle_teuk_rhs.argtypes = [ctypes.POINTER(_OracleTeuk), _dp, _dp]
-        L.oracle_teuk_evolve.argtypes = [ctypes.POINTER(_OracleTeuk), _dp, ctypes.c_double, ctypes.c_long,
-                                         ctypes.c_long, ctypes.c_long, _dp, ctypes.c_long]
+        L.oracle_teuk_evolve.argtypes = [ctypes.POINTER(_OracleTeuk), _dp, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_long, ctypes.c_long, ctypes.c_long, _dp, ctypes.c_long]
         L.oracle_teuk_evolve.restype = ctypes.c_long
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
@@ -123,12 +137,12 @@ def derivative(p_padded, j, dx, side, eps=1e-6):
     base = p.ctypes.data + 3 * 8
     pp = ctypes.cast(base, _dp)
     fn = lib().oracle_dplus if side > 0 else lib().oracle_dminus
-    return fn(pp, j, dx, eps)
+    return fn(pp, j, dx, 0.0, eps, 0)
 
 
 def advect1d(u0, dx, speed, dt, nsteps, eps=1e-6):
     u = np.ascontiguousarray(u0, dtype=np.float64).copy()
-    lib().oracle_advect1d(ptr(u), u.size, dx, speed, dt, nsteps, eps)
+    lib().oracle_advect1d(ptr(u), u.size, dx, 0.0, speed, dt, 0.0, nsteps, eps, 0)
     return u
 
 
@@ -216,9 +230,9 @@ class TeukOracle:
                 "cr": f(c["C"].real), "ci": f(c["C"].imag),
                 "ath": f(c["Ath"]), "bth": f(c["Bth"]),
             }
-        self._s = _OracleTeuk(prob.nr, prob.nth, prob.dx, prob.dth, prob.eps, prob.parity(),
-                              *[ptr(self.tab[n]) for n in ("lam1", "lam2", "m3r", "m3i", "btr",
-                                                           "bti", "cr", "ci", "ath", "bth")])
+        self._s = _OracleTeuk(prob.nr, prob.nth, prob.dx, 0.0, prob.dth, 0.0, prob.eps, prob.parity(), 0,
+                              *[self.tab[n].ctypes.data for n in ("lam1", "lam2", "m3r", "m3i", "btr",
+                                                                  "bti", "cr", "ci", "ath", "bth")])
 
     # a8: stability bound (reading of the SSP framework of Sec. 3.2)
     def dt_bound(self, cfl=0.5):
@@ -269,7 +283,7 @@ class TeukOracle:
             if max_samples <= 0:
                 max_samples = nsteps // every + 1
             wave = np.zeros((max_samples, self.prob.nth, 2))
-        n = lib().oracle_teuk_evolve(ctypes.byref(self._s), ptr(u), dt, nsteps, j_e, every,
+        n = lib().oracle_teuk_evolve(ctypes.byref(self._s), ptr(u), dt, 0.0, nsteps, j_e, every,
                                      ptr(wave) if wave is not None else None, max_samples)
         if wave is not None:
             wave = wave[:n]

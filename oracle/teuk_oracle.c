@@ -1,10 +1,16 @@
 /*
- * Oracle: plain, scalar FP64 solver for the first-order Teukolsky system.
+ * Oracle: plain, scalar solver for the first-order Teukolsky system.
  *
  * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
  * baseline of the benchmark load this library; the product path never does.
  * It is built with -O2 -fno-fast-math -ffp-contract=off so that every
  * operation is rounded exactly as written.
+ *
+ * The same source is built twice: with `real` = double (FP64, the default
+ * build) and, with -DORACLE_QUAD, with `real` = __float128 (IEEE binary128,
+ * the "quad precision" of Sec. 3.1.3; every name then carries the suffix _q).
+ * Scalars that must be exact in either precision are passed as (hi, lo)
+ * pairs of doubles and formed as (real)hi + (real)lo.
  *
  * What it computes, step by step, in the paper's order:
  *   - WENO5 smoothness indicators IS_k, weights alpha_k / omega_k and the
@@ -21,6 +27,13 @@
  *   - SSP-RK(3,3) in the Shu-Osher form of Sec. 3.2.
  * Ghost values: three cells per radial side copied from the end point, and in
  * theta one cell per pole equal to (-1)^(m+s) times the mirrored cell.
+ *
+ * Weight precision (Sec. 3.1.3).  wmode 0 forms IS_k, alpha_k and omega_k in
+ * `real` exactly as printed.  wmode 1 is the paper's mixed variant: the five
+ * stencil values are rounded to double, IS_k, alpha_k, omega_0 and omega_1 are
+ * formed from them in double arithmetic as printed, and omega_2 is the
+ * complement 1 - omega_0 - omega_1 taken in `real`; the candidate fluxes and
+ * their combination stay in `real`.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -29,132 +42,203 @@
 #include <omp.h>
 #endif
 
-static double sq(double v) { return v * v; }
+#ifdef ORACLE_QUAD
+typedef __float128 real;
+#define FN(name) name##_q
+#else
+typedef double real;
+#define FN(name) name
+#endif
+#define R(v) ((real)(v))
+
+static real sq(real v) { return v * v; }
+static double sqd(double v) { return v * v; }
+static real pair(double hi, double lo) { return R(hi) + R(lo); }
 
 /* ---------------------------------------------------------------- WENO5 (Sec. 3.1.2) */
 
 /* f points at f_{j-2}; f[0..4] = f_{j-2..j+2}.  Weights of f^+_{j+1/2}. */
-void oracle_weno5_weights_plus(const double* f, double eps, double w[3])
+void FN(oracle_weno5_weights_plus)(const real* f, double eps, real w[3])
 {
-    double IS0 = 13.0 / 12.0 * sq(f[0] - 2.0 * f[1] + f[2]) + 0.25 * sq(f[0] - 4.0 * f[1] + 3.0 * f[2]);
-    double IS1 = 13.0 / 12.0 * sq(f[1] - 2.0 * f[2] + f[3]) + 0.25 * sq(f[1] - f[3]);
-    double IS2 = 13.0 / 12.0 * sq(f[2] - 2.0 * f[3] + f[4]) + 0.25 * sq(3.0 * f[2] - 4.0 * f[3] + f[4]);
-    double a0 = (1.0 / 10.0) * sq(1.0 / (eps + IS0));
-    double a1 = (6.0 / 10.0) * sq(1.0 / (eps + IS1));
-    double a2 = (3.0 / 10.0) * sq(1.0 / (eps + IS2));
-    double sum = a0 + a1 + a2;
+    const real e = R(eps);
+    real IS0 = R(13) / R(12) * sq(f[0] - R(2) * f[1] + f[2]) + R(1) / R(4) * sq(f[0] - R(4) * f[1] + R(3) * f[2]);
+    real IS1 = R(13) / R(12) * sq(f[1] - R(2) * f[2] + f[3]) + R(1) / R(4) * sq(f[1] - f[3]);
+    real IS2 = R(13) / R(12) * sq(f[2] - R(2) * f[3] + f[4]) + R(1) / R(4) * sq(R(3) * f[2] - R(4) * f[3] + f[4]);
+    real a0 = R(1) / R(10) * sq(R(1) / (e + IS0));
+    real a1 = R(6) / R(10) * sq(R(1) / (e + IS1));
+    real a2 = R(3) / R(10) * sq(R(1) / (e + IS2));
+    real sum = a0 + a1 + a2;
     w[0] = a0 / sum;
     w[1] = a1 / sum;
     w[2] = a2 / sum;
+}
+
+/* The same weights, mixed variant: f rounded to double, IS/alpha/omega_0,1 in
+ * double, omega_2 = 1 - omega_0 - omega_1 in real. */
+void FN(oracle_weno5_weights_plus_w64)(const real* f, double eps, real w[3])
+{
+    double g[5];
+    for (int i = 0; i < 5; ++i) g[i] = (double)f[i];
+    double IS0 = 13.0 / 12.0 * sqd(g[0] - 2.0 * g[1] + g[2]) + 0.25 * sqd(g[0] - 4.0 * g[1] + 3.0 * g[2]);
+    double IS1 = 13.0 / 12.0 * sqd(g[1] - 2.0 * g[2] + g[3]) + 0.25 * sqd(g[1] - g[3]);
+    double IS2 = 13.0 / 12.0 * sqd(g[2] - 2.0 * g[3] + g[4]) + 0.25 * sqd(3.0 * g[2] - 4.0 * g[3] + g[4]);
+    double a0 = (1.0 / 10.0) * sqd(1.0 / (eps + IS0));
+    double a1 = (6.0 / 10.0) * sqd(1.0 / (eps + IS1));
+    double a2 = (3.0 / 10.0) * sqd(1.0 / (eps + IS2));
+    double sum = a0 + a1 + a2;
+    w[0] = R(a0 / sum);
+    w[1] = R(a1 / sum);
+    w[2] = R(1) - w[0] - w[1];
 }
 
 /* f^+_{j+1/2} from f_{j-2..j+2} with given weights. */
-double oracle_weno5_combine_plus(const double* f, const double w[3])
+real FN(oracle_weno5_combine_plus)(const real* f, const real w[3])
 {
-    return w[0] * ((2.0 / 6.0) * f[0] - (7.0 / 6.0) * f[1] + (11.0 / 6.0) * f[2])
-         + w[1] * (-(1.0 / 6.0) * f[1] + (5.0 / 6.0) * f[2] + (2.0 / 6.0) * f[3])
-         + w[2] * ((2.0 / 6.0) * f[2] + (5.0 / 6.0) * f[3] - (1.0 / 6.0) * f[4]);
+    return w[0] * (R(2) / R(6) * f[0] - R(7) / R(6) * f[1] + R(11) / R(6) * f[2])
+         + w[1] * (-(R(1) / R(6)) * f[1] + R(5) / R(6) * f[2] + R(2) / R(6) * f[3])
+         + w[2] * (R(2) / R(6) * f[2] + R(5) / R(6) * f[3] - R(1) / R(6) * f[4]);
 }
 
-double oracle_weno5_flux_plus(const double* f, double eps)
+static real flux_plus(const real* f, double eps, int wmode)
 {
-    double w[3];
-    oracle_weno5_weights_plus(f, eps, w);
-    return oracle_weno5_combine_plus(f, w);
+    real w[3];
+    if (wmode) FN(oracle_weno5_weights_plus_w64)(f, eps, w);
+    else FN(oracle_weno5_weights_plus)(f, eps, w);
+    return FN(oracle_weno5_combine_plus)(f, w);
 }
+
+real FN(oracle_weno5_flux_plus)(const real* f, double eps) { return flux_plus(f, eps, 0); }
 
 /* g points at f_{j-1}; g[0..4] = f_{j-1..j+3}.  Weights of f^-_{j+1/2}. */
-void oracle_weno5_weights_minus(const double* g, double eps, double w[3])
+void FN(oracle_weno5_weights_minus)(const real* g, double eps, real w[3])
 {
-    double IS0 = 13.0 / 12.0 * sq(g[2] - 2.0 * g[3] + g[4]) + 0.25 * sq(3.0 * g[2] - 4.0 * g[3] + g[4]);
-    double IS1 = 13.0 / 12.0 * sq(g[1] - 2.0 * g[2] + g[3]) + 0.25 * sq(g[1] - g[3]);
-    double IS2 = 13.0 / 12.0 * sq(g[0] - 2.0 * g[1] + g[2]) + 0.25 * sq(g[0] - 4.0 * g[1] + 3.0 * g[2]);
-    double a0 = (1.0 / 10.0) * sq(1.0 / (eps + IS0));
-    double a1 = (6.0 / 10.0) * sq(1.0 / (eps + IS1));
-    double a2 = (3.0 / 10.0) * sq(1.0 / (eps + IS2));
-    double sum = a0 + a1 + a2;
+    const real e = R(eps);
+    real IS0 = R(13) / R(12) * sq(g[2] - R(2) * g[3] + g[4]) + R(1) / R(4) * sq(R(3) * g[2] - R(4) * g[3] + g[4]);
+    real IS1 = R(13) / R(12) * sq(g[1] - R(2) * g[2] + g[3]) + R(1) / R(4) * sq(g[1] - g[3]);
+    real IS2 = R(13) / R(12) * sq(g[0] - R(2) * g[1] + g[2]) + R(1) / R(4) * sq(g[0] - R(4) * g[1] + R(3) * g[2]);
+    real a0 = R(1) / R(10) * sq(R(1) / (e + IS0));
+    real a1 = R(6) / R(10) * sq(R(1) / (e + IS1));
+    real a2 = R(3) / R(10) * sq(R(1) / (e + IS2));
+    real sum = a0 + a1 + a2;
     w[0] = a0 / sum;
     w[1] = a1 / sum;
     w[2] = a2 / sum;
 }
 
-double oracle_weno5_combine_minus(const double* g, const double w[3])
+void FN(oracle_weno5_weights_minus_w64)(const real* g, double eps, real w[3])
 {
-    return w[2] * (-(1.0 / 6.0) * g[0] + (5.0 / 6.0) * g[1] + (2.0 / 6.0) * g[2])
-         + w[1] * ((2.0 / 6.0) * g[1] + (5.0 / 6.0) * g[2] - (1.0 / 6.0) * g[3])
-         + w[0] * ((11.0 / 6.0) * g[2] - (7.0 / 6.0) * g[3] + (2.0 / 6.0) * g[4]);
+    double h[5];
+    for (int i = 0; i < 5; ++i) h[i] = (double)g[i];
+    double IS0 = 13.0 / 12.0 * sqd(h[2] - 2.0 * h[3] + h[4]) + 0.25 * sqd(3.0 * h[2] - 4.0 * h[3] + h[4]);
+    double IS1 = 13.0 / 12.0 * sqd(h[1] - 2.0 * h[2] + h[3]) + 0.25 * sqd(h[1] - h[3]);
+    double IS2 = 13.0 / 12.0 * sqd(h[0] - 2.0 * h[1] + h[2]) + 0.25 * sqd(h[0] - 4.0 * h[1] + 3.0 * h[2]);
+    double a0 = (1.0 / 10.0) * sqd(1.0 / (eps + IS0));
+    double a1 = (6.0 / 10.0) * sqd(1.0 / (eps + IS1));
+    double a2 = (3.0 / 10.0) * sqd(1.0 / (eps + IS2));
+    double sum = a0 + a1 + a2;
+    w[0] = R(a0 / sum);
+    w[1] = R(a1 / sum);
+    w[2] = R(1) - w[0] - w[1];
 }
 
-double oracle_weno5_flux_minus(const double* g, double eps)
+real FN(oracle_weno5_combine_minus)(const real* g, const real w[3])
 {
-    double w[3];
-    oracle_weno5_weights_minus(g, eps, w);
-    return oracle_weno5_combine_minus(g, w);
+    return w[2] * (-(R(1) / R(6)) * g[0] + R(5) / R(6) * g[1] + R(2) / R(6) * g[2])
+         + w[1] * (R(2) / R(6) * g[1] + R(5) / R(6) * g[2] - R(1) / R(6) * g[3])
+         + w[0] * (R(11) / R(6) * g[2] - R(7) / R(6) * g[3] + R(2) / R(6) * g[4]);
 }
+
+static real flux_minus(const real* g, double eps, int wmode)
+{
+    real w[3];
+    if (wmode) FN(oracle_weno5_weights_minus_w64)(g, eps, w);
+    else FN(oracle_weno5_weights_minus)(g, eps, w);
+    return FN(oracle_weno5_combine_minus)(g, w);
+}
+
+real FN(oracle_weno5_flux_minus)(const real* g, double eps) { return flux_minus(g, eps, 0); }
 
 /* Flux-difference derivatives at point j of a padded row p (p[j] is point j,
  * valid for j-3 .. j+3). */
-double oracle_dplus(const double* p, long j, double dx, double eps)
+static real dplus(const real* p, long j, real dx, double eps, int wmode)
 {
-    return (oracle_weno5_flux_plus(p + j - 2, eps) - oracle_weno5_flux_plus(p + j - 3, eps)) / dx;
+    return (flux_plus(p + j - 2, eps, wmode) - flux_plus(p + j - 3, eps, wmode)) / dx;
 }
 
-double oracle_dminus(const double* p, long j, double dx, double eps)
+static real dminus(const real* p, long j, real dx, double eps, int wmode)
 {
-    return (oracle_weno5_flux_minus(p + j - 1, eps) - oracle_weno5_flux_minus(p + j - 2, eps)) / dx;
+    return (flux_minus(p + j - 1, eps, wmode) - flux_minus(p + j - 2, eps, wmode)) / dx;
+}
+
+real FN(oracle_dplus)(const real* p, long j, double dx, double dx_lo, double eps, int wmode)
+{
+    return dplus(p, j, pair(dx, dx_lo), eps, wmode);
+}
+
+real FN(oracle_dminus)(const real* p, long j, double dx, double dx_lo, double eps, int wmode)
+{
+    return dminus(p, j, pair(dx, dx_lo), eps, wmode);
 }
 
 /* Upwinded derivative: speed >= 0 -> f^+ treatment, speed < 0 -> f^-. */
-static double upwind_d(const double* p, long j, double speed, double dx, double eps)
+static real upwind_d(const real* p, long j, real speed, real dx, double eps, int wmode)
 {
-    return speed < 0.0 ? oracle_dminus(p, j, dx, eps) : oracle_dplus(p, j, dx, eps);
+    return speed < R(0) ? dminus(p, j, dx, eps, wmode) : dplus(p, j, dx, eps, wmode);
 }
 
 /* ---------------------------------------------------------------- SSP-RK(3,3) (Sec. 3.2) */
 
-typedef void (*oracle_rhs_fn)(const double* u, double* F, void* ctx);
+typedef void (*oracle_rhs_fn)(const real* u, real* F, void* ctx);
 
 /* One step of SSP-RK(3,3):
  *   u1 = u + dt F(u)
  *   u2 = 3/4 u + 1/4 (u1 + dt F(u1))
  *   u  = 1/3 u + 2/3 (u2 + dt F(u2))
- * work holds 3n doubles. */
-void oracle_ssprk3_step(double* u, long n, double dt, oracle_rhs_fn rhs, void* ctx, double* work)
+ * work holds 3n values. */
+static void ssprk3_step(real* u, long n, real dt, oracle_rhs_fn rhs, void* ctx, real* work)
 {
-    double* F = work;
-    double* u1 = work + n;
-    double* u2 = work + 2 * n;
+    real* F = work;
+    real* u1 = work + n;
+    real* u2 = work + 2 * n;
     rhs(u, F, ctx);
     for (long i = 0; i < n; ++i) u1[i] = u[i] + dt * F[i];
     rhs(u1, F, ctx);
-    for (long i = 0; i < n; ++i) u2[i] = (3.0 / 4.0) * u[i] + (1.0 / 4.0) * (u1[i] + dt * F[i]);
+    for (long i = 0; i < n; ++i) u2[i] = R(3) / R(4) * u[i] + R(1) / R(4) * (u1[i] + dt * F[i]);
     rhs(u2, F, ctx);
-    for (long i = 0; i < n; ++i) u[i] = (1.0 / 3.0) * u[i] + (2.0 / 3.0) * (u2[i] + dt * F[i]);
+    for (long i = 0; i < n; ++i) u[i] = R(1) / R(3) * u[i] + R(2) / R(3) * (u2[i] + dt * F[i]);
+}
+
+void FN(oracle_ssprk3_step)(real* u, long n, double dt, oracle_rhs_fn rhs, void* ctx, real* work)
+{
+    ssprk3_step(u, n, R(dt), rhs, ctx, work);
 }
 
 /* ---------------------------------------------------------------- 1D advection (tests) */
 
 typedef struct {
     long n;
-    double dx, speed, eps;
+    real dx, speed;
+    double eps;
+    int wmode;
 } oracle_advect;
 
 /* u_t + speed u_x = 0 on a periodic grid: F = -speed * D u. */
-static void advect_rhs(const double* u, double* F, void* vctx)
+static void advect_rhs(const real* u, real* F, void* vctx)
 {
     const oracle_advect* A = (const oracle_advect*)vctx;
     long n = A->n;
-    double* p = (double*)malloc((size_t)(n + 6) * sizeof(double));
+    real* p = (real*)malloc((size_t)(n + 6) * sizeof(real));
     for (long i = 0; i < n + 6; ++i) p[i] = u[((i - 3) % n + n) % n];
-    for (long j = 0; j < n; ++j) F[j] = -A->speed * upwind_d(p + 3, j, A->speed, A->dx, A->eps);
+    for (long j = 0; j < n; ++j) F[j] = -A->speed * upwind_d(p + 3, j, A->speed, A->dx, A->eps, A->wmode);
     free(p);
 }
 
-void oracle_advect1d(double* u, long n, double dx, double speed, double dt, long nsteps, double eps)
+void FN(oracle_advect1d)(real* u, long n, double dx, double dx_lo, double speed, double dt, double dt_lo,
+                         long nsteps, double eps, int wmode)
 {
-    oracle_advect A = {n, dx, speed, eps};
-    double* work = (double*)malloc((size_t)(3 * n) * sizeof(double));
-    for (long s = 0; s < nsteps; ++s) oracle_ssprk3_step(u, n, dt, advect_rhs, &A, work);
+    oracle_advect A = {n, pair(dx, dx_lo), R(speed), eps, wmode};
+    real* work = (real*)malloc((size_t)(3 * n) * sizeof(real));
+    for (long s = 0; s < nsteps; ++s) ssprk3_step(u, n, pair(dt, dt_lo), advect_rhs, &A, work);
     free(work);
 }
 
@@ -162,29 +246,31 @@ void oracle_advect1d(double* u, long n, double dx, double speed, double dt, long
 
 typedef struct {
     long nr, nth;
-    double dx, dth, eps;
+    double dx, dx_lo, dth, dth_lo;   /* grid steps as (hi, lo) pairs */
+    double eps;
     double parity;                   /* (-1)^(m+s) for the pole ghosts */
+    int wmode;                       /* 0: weights in real; 1: mixed (double) */
     /* per point, [nth][nr], radial index fastest */
-    const double *lam1, *lam2;       /* speeds of the Phi rows and the pi rows */
-    const double *m3r, *m3i;         /* m3 = m31 - i m32 */
-    const double *btr, *bti;         /* B~t */
-    const double *cr, *ci;           /* C~ */
-    const double *ath, *bth;         /* A~thth, B~th */
+    const real *lam1, *lam2;         /* speeds of the Phi rows and the pi rows */
+    const real *m3r, *m3i;           /* m3 = m31 - i m32 */
+    const real *btr, *bti;           /* B~t */
+    const real *cr, *ci;             /* C~ */
+    const real *ath, *bth;           /* A~thth, B~th */
 } oracle_teuk;
 
 /* Copy row k of a plane into p[0 .. nr+5] with three end-point copies per side. */
-static void pad_row(const double* plane, long nr, long k, double* p)
+static void pad_row(const real* plane, long nr, long k, real* p)
 {
-    const double* row = plane + k * nr;
+    const real* row = plane + k * nr;
     for (long g = 0; g < 3; ++g) {
         p[g] = row[0];
         p[nr + 3 + g] = row[nr - 1];
     }
-    memcpy(p + 3, row, (size_t)nr * sizeof(double));
+    memcpy(p + 3, row, (size_t)nr * sizeof(real));
 }
 
 /* theta neighbour of (k, j) in a plane, with the pole ghosts. */
-static double theta_nb(const double* plane, long nr, long nth, long k, long j, double parity)
+static real theta_nb(const real* plane, long nr, long nth, long k, long j, real parity)
 {
     if (k < 0) return parity * plane[0 * nr + j];
     if (k >= nth) return parity * plane[(nth - 1) * nr + j];
@@ -192,43 +278,46 @@ static double theta_nb(const double* plane, long nr, long nth, long k, long j, d
 }
 
 /* F = -(M d_x u + L u + A u) at every point; u and F are [4][nth][nr]. */
-void oracle_teuk_rhs(const oracle_teuk* P, const double* u, double* F)
+void FN(oracle_teuk_rhs)(const oracle_teuk* P, const real* u, real* F)
 {
     const long nr = P->nr, nth = P->nth, N = nr * nth;
-    const double *PhR = u, *PhI = u + N, *PiR = u + 2 * N, *PiI = u + 3 * N;
-    const double ih1 = 1.0 / (2.0 * P->dth), ih2 = 1.0 / (P->dth * P->dth);
+    const real *PhR = u, *PhI = u + N, *PiR = u + 2 * N, *PiI = u + 3 * N;
+    const real dx = pair(P->dx, P->dx_lo), dth = pair(P->dth, P->dth_lo), par = R(P->parity);
+    const real ih1 = R(1) / (R(2) * dth), ih2 = R(1) / (dth * dth);
+    const double eps = P->eps;
+    const int wm = P->wmode;
 #pragma omp parallel for schedule(static)
     for (long k = 0; k < nth; ++k) {
-        double* buf = (double*)malloc((size_t)(4 * (nr + 6)) * sizeof(double));
-        double *pPhR = buf + 3, *pPhI = buf + (nr + 6) + 3, *pPiR = buf + 2 * (nr + 6) + 3,
-               *pPiI = buf + 3 * (nr + 6) + 3;
+        real* buf = (real*)malloc((size_t)(4 * (nr + 6)) * sizeof(real));
+        real *pPhR = buf + 3, *pPhI = buf + (nr + 6) + 3, *pPiR = buf + 2 * (nr + 6) + 3,
+             *pPiI = buf + 3 * (nr + 6) + 3;
         pad_row(PhR, nr, k, pPhR - 3);
         pad_row(PhI, nr, k, pPhI - 3);
         pad_row(PiR, nr, k, pPiR - 3);
         pad_row(PiI, nr, k, pPiI - 3);
         for (long j = 0; j < nr; ++j) {
             const long i = k * nr + j;
-            const double l1 = P->lam1[i], l2 = P->lam2[i];
+            const real l1 = P->lam1[i], l2 = P->lam2[i];
             /* d_x u, each plane upwinded by its row's speed */
-            const double dPhR = upwind_d(pPhR, j, l1, P->dx, P->eps);
-            const double dPhI = upwind_d(pPhI, j, l1, P->dx, P->eps);
-            const double dPiR = upwind_d(pPiR, j, l2, P->dx, P->eps);
-            const double dPiI = upwind_d(pPiI, j, l2, P->dx, P->eps);
+            const real dPhR = upwind_d(pPhR, j, l1, dx, eps, wm);
+            const real dPhI = upwind_d(pPhI, j, l1, dx, eps, wm);
+            const real dPiR = upwind_d(pPiR, j, l2, dx, eps, wm);
+            const real dPiI = upwind_d(pPiI, j, l2, dx, eps, wm);
             /* theta derivatives of Phi (second-order centred) */
-            const double phRm = theta_nb(PhR, nr, nth, k - 1, j, P->parity);
-            const double phRp = theta_nb(PhR, nr, nth, k + 1, j, P->parity);
-            const double phIm = theta_nb(PhI, nr, nth, k - 1, j, P->parity);
-            const double phIp = theta_nb(PhI, nr, nth, k + 1, j, P->parity);
-            const double phR = PhR[i], phI = PhI[i], piR = PiR[i], piI = PiI[i];
-            const double d1R = (phRp - phRm) * ih1, d1I = (phIp - phIm) * ih1;
-            const double d2R = (phRp - 2.0 * phR + phRm) * ih2, d2I = (phIp - 2.0 * phI + phIm) * ih2;
+            const real phRm = theta_nb(PhR, nr, nth, k - 1, j, par);
+            const real phRp = theta_nb(PhR, nr, nth, k + 1, j, par);
+            const real phIm = theta_nb(PhI, nr, nth, k - 1, j, par);
+            const real phIp = theta_nb(PhI, nr, nth, k + 1, j, par);
+            const real phR = PhR[i], phI = PhI[i], piR = PiR[i], piI = PiI[i];
+            const real d1R = (phRp - phRm) * ih1, d1I = (phIp - phIm) * ih1;
+            const real d2R = (phRp - R(2) * phR + phRm) * ih2, d2I = (phIp - R(2) * phI + phIm) * ih2;
             /* complex products m3 dPhi, B~t pi, C~ Phi */
-            const double mdR = P->m3r[i] * dPhR - P->m3i[i] * dPhI;
-            const double mdI = P->m3r[i] * dPhI + P->m3i[i] * dPhR;
-            const double bpR = P->btr[i] * piR - P->bti[i] * piI;
-            const double bpI = P->btr[i] * piI + P->bti[i] * piR;
-            const double cpR = P->cr[i] * phR - P->ci[i] * phI;
-            const double cpI = P->cr[i] * phI + P->ci[i] * phR;
+            const real mdR = P->m3r[i] * dPhR - P->m3i[i] * dPhI;
+            const real mdI = P->m3r[i] * dPhI + P->m3i[i] * dPhR;
+            const real bpR = P->btr[i] * piR - P->bti[i] * piI;
+            const real bpI = P->btr[i] * piI + P->bti[i] * piR;
+            const real cpR = P->cr[i] * phR - P->ci[i] * phI;
+            const real cpI = P->cr[i] * phI + P->ci[i] * phR;
             /* rows 1-2: d_t Phi = pi - lam1 d_x Phi */
             F[i] = piR - l1 * dPhR;
             F[N + i] = piI - l1 * dPhI;
@@ -240,23 +329,25 @@ void oracle_teuk_rhs(const oracle_teuk* P, const double* u, double* F)
     }
 }
 
-static void teuk_rhs_cb(const double* u, double* F, void* ctx)
+static void teuk_rhs_cb(const real* u, real* F, void* ctx)
 {
-    oracle_teuk_rhs((const oracle_teuk*)ctx, u, F);
+    FN(oracle_teuk_rhs)((const oracle_teuk*)ctx, u, F);
 }
 
-/* Evolve u in place for nsteps SSP-RK3 steps of size dt.  If wave != NULL,
- * (Phi_R, Phi_I) at radial index j_e is recorded for every theta row at the
- * initial state and after every `every`-th step, as wave[n][nth][2], up to
- * max_samples samples.  Returns the number of samples written. */
-long oracle_teuk_evolve(const oracle_teuk* P, double* u, double dt, long nsteps,
-                        long j_e, long every, double* wave, long max_samples)
+/* Evolve u in place for nsteps SSP-RK3 steps of size dt = dt_hi + dt_lo.  If
+ * wave != NULL, (Phi_R, Phi_I) at radial index j_e is recorded for every theta
+ * row at the initial state and after every `every`-th step, as
+ * wave[n][nth][2], up to max_samples samples.  Returns the number of samples
+ * written. */
+long FN(oracle_teuk_evolve)(const oracle_teuk* P, real* u, double dt, double dt_lo, long nsteps,
+                            long j_e, long every, real* wave, long max_samples)
 {
     const long N = P->nr * P->nth, n = 4 * N;
-    double* work = (double*)malloc((size_t)(3 * n) * sizeof(double));
+    const real h = pair(dt, dt_lo);
+    real* work = (real*)malloc((size_t)(3 * n) * sizeof(real));
     long ns = 0;
     for (long s = 0; s <= nsteps; ++s) {
-        if (s > 0) oracle_ssprk3_step(u, n, dt, teuk_rhs_cb, (void*)P, work);
+        if (s > 0) ssprk3_step(u, n, h, teuk_rhs_cb, (void*)P, work);
         if (wave && every > 0 && s % every == 0 && ns < max_samples) {
             for (long k = 0; k < P->nth; ++k) {
                 wave[(ns * P->nth + k) * 2 + 0] = u[k * P->nr + j_e];
@@ -269,7 +360,56 @@ long oracle_teuk_evolve(const oracle_teuk* P, double* u, double dt, long nsteps,
     return ns;
 }
 
-int oracle_num_threads(void)
+/* u' = lam u, u(0) = 1: nsteps SSP-RK3 steps of size dt; returns u as a
+ * (hi, lo) pair (tests of the integrator's order at this precision). */
+static void ode_rhs(const real* u, real* F, void* ctx)
+{
+    F[0] = *(const real*)ctx * u[0];
+}
+
+void FN(oracle_ode_rk3)(double lam, double dt, double dt_lo, long nsteps, double out[2])
+{
+    real l = R(lam), u = R(1), work[3];
+    const real h = pair(dt, dt_lo);
+    for (long s = 0; s < nsteps; ++s) ssprk3_step(&u, 1, h, ode_rhs, &l, work);
+    out[0] = (double)u;
+    out[1] = (double)(u - R(out[0]));
+}
+
+#ifdef ORACLE_QUAD
+/* Conversions between (hi, lo) pairs of doubles and binary128 values. */
+void oracle_q_from_pairs(const double* p, real* q, long n)
+{
+    for (long i = 0; i < n; ++i) q[i] = pair(p[2 * i], p[2 * i + 1]);
+}
+
+void oracle_q_to_pairs(const real* q, double* p, long n)
+{
+    for (long i = 0; i < n; ++i) {
+        const double hi = (double)q[i];
+        p[2 * i] = hi;
+        p[2 * i + 1] = (double)(q[i] - R(hi));
+    }
+}
+
+/* f^+_{j+1/2} (side > 0, f = f_{j-2..j+2}) or f^-_{j+1/2} (side < 0,
+ * f = f_{j-1..j+3}) as a pair. */
+void oracle_weno5_flux_pair_q(const real* f, double eps, int side, int wmode, double out[2])
+{
+    const real v = side > 0 ? flux_plus(f, eps, wmode) : flux_minus(f, eps, wmode);
+    oracle_q_to_pairs(&v, out, 1);
+}
+
+/* D^+ (side > 0) or D^- (side < 0) at point j of a padded row, as a pair. */
+void oracle_dside_pair_q(const real* p, long j, double dx, double dx_lo, double eps, int side, int wmode,
+                         double out[2])
+{
+    const real d = side > 0 ? dplus(p, j, pair(dx, dx_lo), eps, wmode) : dminus(p, j, pair(dx, dx_lo), eps, wmode);
+    oracle_q_to_pairs(&d, out, 1);
+}
+#endif
+
+int FN(oracle_num_threads)(void)
 {
 #ifdef _OPENMP
     return omp_get_max_threads();
@@ -278,7 +418,7 @@ int oracle_num_threads(void)
 #endif
 }
 
-void oracle_set_threads(int n)
+void FN(oracle_set_threads)(int n)
 {
 #ifdef _OPENMP
     if (n > 0) omp_set_num_threads(n);
