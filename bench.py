@@ -100,11 +100,12 @@ def roofline(points_per_launch: float, t_launch: float, traffic):
             "algorithmic_bytes_per_launch": bytes_launch, "avg_launch_us": t_launch * 1e6}
 
 
-def solver_config(T, wl, weights, total_steps, workgroups=0, every=None):
+def solver_config(T, wl, weights, total_steps, workgroups=0, every=None, state="fp64"):
     every = wl.every if every is None else every
     return T.make_config(s=wl.s, m=wl.m, a=wl.a, nr=wl.nr, ntheta=wl.nth, x_min=wl.x_min, x_max=wl.x_max,
                          M=wl.M, dt=0.0, cfl=0.5, weight_prec=weights, x_extract=wl.x_e, extract_every=every,
-                         max_samples=total_steps // every + 1 if every > 0 else 0, workgroups=workgroups)
+                         max_samples=total_steps // every + 1 if every > 0 else 0, workgroups=workgroups,
+                         state=state)
 
 
 # ----------------------------------------------------------------------------- C2: one solve
@@ -127,20 +128,22 @@ def bench_single(args, torch, T, W):
         log(f"copy probe: {n * 8} bytes read and written per copy")
         del src, dst
 
-    def run(wp):
+    def run(wp, state="fp64", nsteps=None, nwarm=None):
         """Warm up, then time `steps` steps with HIP events on the solver's
         stream.  Returns (seconds, wall seconds, info, waveform samples)."""
-        sv = T.Solver(solver_config(T, wl, wp, warmup + steps, args.workgroups), stream=stream)
+        nsteps = steps if nsteps is None else nsteps
+        nwarm = warmup if nwarm is None else nwarm
+        sv = T.Solver(solver_config(T, wl, wp, nwarm + nsteps, args.workgroups, state=state), stream=stream)
         sv.set_initial(u0)
-        log(f"{wp}: warmup {warmup} steps")
-        sv.step(warmup)
+        log(f"{state}/{wp}: warmup {nwarm} steps")
+        sv.step(nwarm)
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
-        log(f"{wp}: timing {steps} steps")
+        log(f"{state}/{wp}: timing {nsteps} steps")
         w0 = time.perf_counter()
         ev0.record(stream)
-        sv.step(steps)
+        sv.step(nsteps)
         ev1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
@@ -175,6 +178,27 @@ def bench_single(args, torch, T, W):
             err = float(np.linalg.norm(wave_w - wave) / np.linalg.norm(wave))
             mixed[wp] = {"value": pu / sec_w, "speedup_vs_fp64": gpu_s / sec_w, "waveform_rel_l2_vs_fp64": err}
         out["mixed_precision"] = mixed
+    if weights == "fp64" and args.quad_steps > 0:
+        # The paper's own experiment (Sec. 3.1.3): a high-precision state with
+        # weights in that precision, against the same state with weights in
+        # double.  Here the high precision is double-double (106 bits).
+        qs, qw = args.quad_steps, 10
+        pq = 3.0 * wl.points * qs
+        sec64, _, _, wave64 = run("fp64", nsteps=qs, nwarm=qw)
+        sec_dd, _, _, wave_dd = run("dd", state="dd", nsteps=qs, nwarm=qw)
+        sec_mx, _, _, wave_mx = run("fp64", state="dd", nsteps=qs, nwarm=qw)
+        vdd = wave_dd[..., 0] + wave_dd[..., 1]
+        dmx = (wave_mx[..., 0] - wave_dd[..., 0]) + (wave_mx[..., 1] - wave_dd[..., 1])
+        out["quad_baseline"] = {
+            "state": "double-double", "steps": qs, "warmup": qw,
+            "dd_weights": {"value": pq / sec_dd, "ms_per_step": sec_dd / qs * 1e3},
+            "fp64_weights": {"value": pq / sec_mx, "ms_per_step": sec_mx / qs * 1e3},
+            "speedup_fp64_weights_vs_dd_weights": sec_dd / sec_mx,
+            "waveform_rel_l2_fp64_weights_vs_dd_weights": float(np.linalg.norm(dmx) / np.linalg.norm(vdd)),
+            "waveform_rel_l2_fp64_state_vs_dd": float(np.linalg.norm(wave64 - wave_dd[..., 0] - wave_dd[..., 1])
+                                                      / np.linalg.norm(vdd)),
+            "cost_vs_fp64_state": {"dd_weights": sec_dd / sec64, "fp64_weights": sec_mx / sec64},
+        }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, u0, args.cpu_seconds)
@@ -481,6 +505,8 @@ def main():
     ap.add_argument("--rows-per-tile", type=int, default=0, help="C4/C5: theta rows per group tile (0: 8)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/FP16/BF16-weight runs")
+    ap.add_argument("--quad-steps", type=int, default=1000,
+                    help="C2: steps of the double-double state runs (0: skip them)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before the solve, run a plain device copy of MIB MiB three times (a known-size "

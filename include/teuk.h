@@ -20,13 +20,26 @@
  * the weights summing to one in FP64 (Sec. 3.1.3); candidate fluxes, flux
  * differences, the RK combination and extraction are always FP64.
  *
+ * State precision (Sec. 3.1.3: the paper's baseline is quad precision, with a
+ * mixed variant whose weights are computed in double): besides FP64, the state
+ * may be carried in double-double (TEUK_S_DD), every value an unevaluated sum
+ * hi + lo of two doubles (106 significant bits, about 32 digits), with every
+ * operation of the right-hand side and the RK stages in double-double.  Its
+ * weights are then TEUK_W_DD (double-double) or TEUK_W_FP64 (the paper's mixed
+ * variant: the stencil values rounded to double, IS_k, alpha_k, omega_0 and
+ * omega_1 formed in double as printed, omega_2 = 1 - omega_0 - omega_1 in
+ * double-double).  Its coefficients are evaluated on the host in IEEE
+ * binary128 and stored as double-double pairs.  Tortoise chart only.
+ *
  * Grid: x_j = x_min + j (x_max - x_min)/(nr - 1), j = 0..nr-1;
  *       theta_k = (k + 1/2) pi / ntheta, k = 0..ntheta-1 (no node on a pole).
  * Boundaries: three ghost cells per radial side equal to the end value; one
  *       ghost row per pole equal to (-1)^(m+s) times the mirrored row.
  * State layout (host arrays across this ABI): four FP64 planes
  *       [4][ntheta][nr] in the order Phi_R, Phi_I, pi_R, pi_I, radial index
- *       fastest, densely packed.
+ *       fastest, densely packed.  With TEUK_S_DD every value is a (hi, lo)
+ *       pair of doubles, [4][ntheta][nr][2] (value = hi + lo), and so are the
+ *       waveform samples and the per-point coefficients and F(u) below.
  *
  * Conventions for every call:
  *   - Every call returns a teuk_status; nothing aborts, throws or exits across
@@ -49,7 +62,7 @@
 extern "C" {
 #endif
 
-#define TEUK_ABI_VERSION 1
+#define TEUK_ABI_VERSION 2
 
 typedef struct teuk_solver teuk_solver;   /* opaque; owned by the library */
 
@@ -77,7 +90,13 @@ enum { TEUK_CHART_TORTOISE = 0, TEUK_CHART_HYPERBOLOIDAL = 1 };
 /* Precision of the WENO smoothness indicators and nonlinear weights
  * (Sec. 3.1.3).  The six stencil differences, the candidate fluxes and
  * everything after them stay FP64; omega_2 = 1 - omega_0 - omega_1 in FP64. */
-enum { TEUK_W_FP64 = 0, TEUK_W_FP32 = 1, TEUK_W_FP16 = 2, TEUK_W_BF16 = 3 };
+enum { TEUK_W_FP64 = 0, TEUK_W_FP32 = 1, TEUK_W_FP16 = 2, TEUK_W_BF16 = 3,
+       TEUK_W_DD = 4 /* double-double weights: TEUK_S_DD only */ };
+
+/* Precision of the state and of every operation on it.  TEUK_S_DD takes
+ * TEUK_W_DD or TEUK_W_FP64 weights and the tortoise chart (else
+ * UNSUPPORTED); it is not a group member. */
+enum { TEUK_S_FP64 = 0, TEUK_S_DD = 1 };
 
 /* What teuk_extract returns. */
 enum {
@@ -114,6 +133,8 @@ typedef struct {
     int32_t extract_every;   /* steps between waveform samples (0: no waveform)        */
     int32_t max_samples;     /* waveform ring-buffer capacity (samples)                */
     int32_t workgroups;      /* stage-kernel workgroups; 0 = all the GPU holds at once */
+    int32_t state_prec;      /* TEUK_S_*                                              */
+    int32_t reserved;        /* must be 0                                             */
     double M;                /* black-hole mass (> 0)                                  */
     double a;                /* spin, 0 <= a <= M                                      */
     double x_min, x_max;     /* radial range of x (r_* or rho; x_min < x_max)          */
@@ -146,7 +167,7 @@ typedef struct {
     double dt_bound;         /* stability bound (cfl = 1), from the device reduction   */
 } teuk_info_t;
 
-/* Fill cfg with defaults: ABI version, M = 1, chart T, FP64 weights, cfl 0.5,
+/* Fill cfg with defaults: ABI version, M = 1, chart T, FP64 state and weights, cfl 0.5,
  * eps 1e-6, dt from the bound, no waveform.  Sizes and ranges must still be set. */
 void teuk_default_config(teuk_config* cfg);
 
@@ -171,7 +192,9 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
  * with that dense layout, else a host pointer), reset t and the step and
  * sample counters, and record the first waveform sample (t = 0).  The data
  * are copied; u is not retained.  Host input is checked for NaN/Inf
- * (NONFINITE); device input is checked by the device guard.
+ * (NONFINITE); device input is checked by the device guard.  Double-double
+ * pairs are stored normalised (TwoSum of hi and lo: same value, |lo| at most
+ * half an ulp of hi).
  * Errors: INVALID_ARG (NULL), NONFINITE, DEVICE. */
 teuk_status teuk_set_initial(teuk_solver* h, const double* u, int32_t on_device);
 
@@ -187,14 +210,15 @@ teuk_status teuk_step(teuk_solver* h, int64_t nsteps);
  * the number of doubles written (may be NULL).  Synchronises the stream and
  * runs the non-finite guard on the state first (NONFINITE if it trips; the
  * data are still copied for inspection).
- *   TEUK_X_STATE     4*ntheta*nr doubles
+ *   TEUK_X_STATE     4*ntheta*nr doubles (twice that in double-double)
  *   TEUK_X_WAVEFORM  min(samples, max_samples)*ntheta*2 doubles, oldest first
+ *                    (twice that in double-double)
  *   TEUK_X_TIMES     min(samples, max_samples) doubles
  *   TEUK_X_HORIZON   min(samples, max_samples)*ntheta*4 doubles, oldest first
  *                    (hyperboloidal chart; UNSUPPORTED in the tortoise chart)
- *   TEUK_X_COEFFS    TEUK_NCOEF*ntheta*nr doubles
+ *   TEUK_X_COEFFS    TEUK_NCOEF*ntheta*nr doubles (twice that in double-double)
  *   TEUK_X_RHS       4*ntheta*nr doubles (uses the stage scratch buffer; the
- *                    state is unchanged)
+ *                    state is unchanged; twice that in double-double)
  * Errors: INVALID_ARG, CAPACITY (out too small; nothing written), NONFINITE,
  * DEVICE. */
 teuk_status teuk_extract(teuk_solver* h, int32_t what, double* out, size_t capacity, size_t* written);
@@ -215,7 +239,9 @@ const char* teuk_last_error(const teuk_solver* h);
 
 /* Host-only evaluation, in FP64, of the per-point coefficients (TEUK_X_COEFFS
  * layout) from the same tables and the same formula the device uses.  Needs no
- * GPU.  out holds capacity doubles (>= TEUK_NCOEF*ntheta*nr).
+ * GPU.  out holds capacity doubles (>= TEUK_NCOEF*ntheta*nr).  For a
+ * TEUK_S_DD configuration: the double-double table the device streams, as
+ * pairs (>= 2*TEUK_NCOEF*ntheta*nr doubles).
  * Errors: INVALID_ARG, CAPACITY. */
 teuk_status teuk_host_coefficients(const teuk_config* cfg, double* out, size_t capacity);
 
@@ -263,7 +289,7 @@ teuk_status teuk_group_create(const teuk_device_ctx* ctx, int32_t max_members, i
 /* Add a solver (after teuk_set_initial) to the group.  Synchronises the group's
  * stream and uploads the members' descriptors.  Errors: INVALID_ARG (NULL,
  * other stream, already in a group), CAPACITY (group full), STATE (no initial
- * data), DEVICE. */
+ * data), UNSUPPORTED (double-double state), DEVICE. */
 teuk_status teuk_group_add(teuk_group* g, teuk_solver* h);
 
 /* Remove a member (synchronises the group's stream).  The solver stays valid

@@ -153,22 +153,24 @@ def _mp_lambdified():
     return keys, sp.lambdify(args, [ex[k] for k in keys], modules="mpmath")
 
 
-def first_order_tables_mp(prob: S.Problem):
+def first_order_tables_mp(prob: S.Problem, window=None):
     """Per-point first-order coefficients (eq. evln, chart T) at DPS digits,
-    as (hi, lo) pair arrays [nth][nr][2] keyed like the FP64 oracle's tables."""
+    as (hi, lo) pair arrays [nth][nr][2] keyed like the FP64 oracle's tables.
+    window = (j0, k0, nr_w, nth_w) restricts them to those nodes of prob's grid."""
     keys, fn = _mp_lambdified()
-    nr, nth = prob.nr, prob.nth
+    j0, k0, nr, nth = window if window is not None else (0, 0, prob.nr, prob.nth)
     with mp.workdps(DPS):
-        x = [mp.mpf(prob.x_min) + j * (mp.mpf(prob.x_max) - mp.mpf(prob.x_min)) / (nr - 1) for j in range(nr)]
+        x = [mp.mpf(prob.x_min) + (j0 + j) * (mp.mpf(prob.x_max) - mp.mpf(prob.x_min)) / (prob.nr - 1)
+             for j in range(nr)]
     # the x nodes are formed at DPS digits; their double values only seed the
     # Newton solve for r, which is taken at the exact node.
     names = ("lam1", "lam2", "m3r", "m3i", "btr", "bti", "cr", "ci", "ath", "bth")
     tab = {n: np.zeros((nth, nr, 2)) for n in names}
     with mp.workdps(DPS + 10):
         rs, Ds = _r_at_nodes(x, prob.M, prob.a)
-        dth = mp.pi / nth
+        dth = mp.pi / prob.nth
         for k in range(nth):
-            th = (k + mp.mpf(1) / 2) * dth
+            th = (k0 + k + mp.mpf(1) / 2) * dth
             c, s_ = mp.cos(th), mp.sin(th)
             for j in range(nr):
                 v = dict(zip(keys, fn(rs[j], Ds[j], c, s_, mp.mpf(prob.M), mp.mpf(prob.a), prob.s, prob.m)))
@@ -220,22 +222,27 @@ class TeukOracleQ:
 
     NAMES = ("lam1", "lam2", "m3r", "m3i", "btr", "bti", "cr", "ci", "ath", "bth")
 
-    def __init__(self, prob: S.Problem, weights: str = "quad", tables=None):
+    def __init__(self, prob: S.Problem, weights: str = "quad", tables=None, window=None):
+        """window = (j0, k0, nr_w, nth_w): solve on that block of prob's grid
+        alone, its edges taken as grid ends (ghosts by the usual rules), so
+        that values away from the block's edges equal the full grid's."""
         assert prob.chart == "T", "the binary128 oracle covers the tortoise chart"
         assert weights in ("quad", "fp64")
         self.prob = prob
         self.weights = weights
-        self.tab = tables if tables is not None else first_order_tables_mp(prob)
+        self.window = window if window is not None else (0, 0, prob.nr, prob.nth)
+        self.nr, self.nth = self.window[2], self.window[3]
+        self.tab = tables if tables is not None else first_order_tables_mp(prob, window)
         self._q = {n: QBuf.from_pairs(self.tab[n]) for n in self.NAMES}
         with mp.workdps(DPS):
             dx = split((mp.mpf(prob.x_max) - mp.mpf(prob.x_min)) / (prob.nr - 1))
             dth = split(mp.pi / prob.nth)
         self.dx_pair, self.dth_pair = dx, dth
-        self._s = S._OracleTeuk(prob.nr, prob.nth, dx[0], dx[1], dth[0], dth[1], prob.eps, prob.parity(),
+        self._s = S._OracleTeuk(self.nr, self.nth, dx[0], dx[1], dth[0], dth[1], prob.eps, prob.parity(),
                                 1 if weights == "fp64" else 0, *[self._q[n].addr for n in self.NAMES])
 
     def shape(self):
-        return (4, self.prob.nth, self.prob.nr)
+        return (4, self.nth, self.nr)
 
     def rhs(self, u_pairs):
         """F(u) for u of shape [4][nth][nr][2] (pairs); returns pairs."""
@@ -246,7 +253,7 @@ class TeukOracleQ:
 
     def extract_index(self, x_e):
         p = self.prob
-        return int(np.floor((x_e - p.x_min) / p.dx + 0.5))
+        return int(np.floor((x_e - p.x_min) / p.dx + 0.5)) - self.window[0]
 
     def evolve(self, u0_pairs, dt, nsteps, x_e=None, every=0, max_samples=0):
         """nsteps SSP-RK3 steps of size dt (a double, or a (hi, lo) pair).
@@ -259,10 +266,10 @@ class TeukOracleQ:
             j_e = self.extract_index(x_e)
             if max_samples <= 0:
                 max_samples = nsteps // every + 1
-            wave = QBuf(max_samples * self.prob.nth * 2)
+            wave = QBuf(max_samples * self.nth * 2)
         n = lib().oracle_teuk_evolve_q(ctypes.byref(self._s), u.addr, dtp[0], dtp[1], nsteps, j_e, every,
                                        wave.addr if wave is not None else None, max_samples)
         w = None
         if wave is not None:
-            w = wave.pairs((max_samples, self.prob.nth, 2))[:n]
+            w = wave.pairs((max_samples, self.nth, 2))[:n]
         return u.pairs(self.shape()), w

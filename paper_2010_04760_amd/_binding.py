@@ -22,7 +22,7 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-TEUK_ABI_VERSION = 1
+TEUK_ABI_VERSION = 2
 TEUK_OK = 0
 TEUK_ERR_INVALID_ARG = -1
 TEUK_ERR_OUT_OF_MEMORY = -2
@@ -32,11 +32,13 @@ TEUK_ERR_NONFINITE = -5
 TEUK_ERR_UNSUPPORTED = -6
 TEUK_ERR_CAPACITY = -7
 TEUK_CHART_TORTOISE, TEUK_CHART_HYPERBOLOIDAL = 0, 1
-TEUK_W_FP64, TEUK_W_FP32, TEUK_W_FP16, TEUK_W_BF16 = 0, 1, 2, 3
+TEUK_W_FP64, TEUK_W_FP32, TEUK_W_FP16, TEUK_W_BF16, TEUK_W_DD = 0, 1, 2, 3, 4
+TEUK_S_FP64, TEUK_S_DD = 0, 1
 TEUK_X_STATE, TEUK_X_WAVEFORM, TEUK_X_TIMES, TEUK_X_COEFFS, TEUK_X_RHS, TEUK_X_HORIZON = 0, 1, 2, 3, 4, 5
 TEUK_NCOEF = 10
 CHART = {"T": TEUK_CHART_TORTOISE, "H": TEUK_CHART_HYPERBOLOIDAL}
-WEIGHT_PREC = {"fp64": TEUK_W_FP64, "fp32": TEUK_W_FP32, "fp16": TEUK_W_FP16, "bf16": TEUK_W_BF16}
+WEIGHT_PREC = {"fp64": TEUK_W_FP64, "fp32": TEUK_W_FP32, "fp16": TEUK_W_FP16, "bf16": TEUK_W_BF16, "dd": TEUK_W_DD}
+STATE_PREC = {"fp64": TEUK_S_FP64, "dd": TEUK_S_DD}
 
 _STATUS_NAMES = {0: "TEUK_OK", -1: "TEUK_ERR_INVALID_ARG", -2: "TEUK_ERR_OUT_OF_MEMORY", -3: "TEUK_ERR_DEVICE",
                  -4: "TEUK_ERR_STATE", -5: "TEUK_ERR_NONFINITE", -6: "TEUK_ERR_UNSUPPORTED",
@@ -48,6 +50,7 @@ class teuk_config(ctypes.Structure):
                 ("chart", ctypes.c_int32), ("nr", ctypes.c_int32), ("ntheta", ctypes.c_int32),
                 ("weight_prec", ctypes.c_int32), ("extract_every", ctypes.c_int32),
                 ("max_samples", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("state_prec", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("M", ctypes.c_double), ("a", ctypes.c_double), ("x_min", ctypes.c_double),
                 ("x_max", ctypes.c_double), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("weno_eps", ctypes.c_double), ("x_extract", ctypes.c_double), ("S", ctypes.c_double)]
@@ -193,10 +196,12 @@ def teuk_last_error(h: int | None = None) -> str:
 
 
 def teuk_host_coefficients(cfg: teuk_config) -> np.ndarray:
+    """[TEUK_NCOEF][ntheta][nr] (FP64 state) or [TEUK_NCOEF][ntheta][nr][2] pairs (double-double)."""
     n = cfg.nr * cfg.ntheta
-    out = np.empty(TEUK_NCOEF * n, dtype=np.float64)
+    pv = 2 if cfg.state_prec == TEUK_S_DD else 1
+    out = np.empty(TEUK_NCOEF * n * pv, dtype=np.float64)
     _check(_lib.teuk_host_coefficients(ctypes.byref(cfg), out.ctypes.data_as(_dp), out.size))
-    return out.reshape(TEUK_NCOEF, cfg.ntheta, cfg.nr)
+    return out.reshape((TEUK_NCOEF, cfg.ntheta, cfg.nr) + ((2,) if pv == 2 else ()))
 
 
 def teuk_group_create(ctx: teuk_device_ctx | None, max_members: int, workgroups: int = 0,
@@ -237,7 +242,8 @@ def teuk_group_last_error(g: int | None = None) -> str:
 def make_config(*, s: int, m: int, a: float, nr: int, ntheta: int, x_min: float, x_max: float,
                 M: float = 1.0, dt: float = 0.0, cfl: float = 0.5, weno_eps: float = 1e-6,
                 weight_prec="fp64", x_extract: float | None = None, extract_every: int = 0,
-                max_samples: int = 0, workgroups: int = 0, chart="T", S: float = 20.0) -> teuk_config:
+                max_samples: int = 0, workgroups: int = 0, chart="T", S: float = 20.0,
+                state="fp64") -> teuk_config:
     c = teuk_default_config()
     c.s, c.m, c.a, c.M = int(s), int(m), float(a), float(M)
     c.nr, c.ntheta = int(nr), int(ntheta)
@@ -249,6 +255,7 @@ def make_config(*, s: int, m: int, a: float, nr: int, ntheta: int, x_min: float,
     c.workgroups = int(workgroups)
     c.chart = CHART[chart] if isinstance(chart, str) else int(chart)
     c.S = float(S)
+    c.state_prec = STATE_PREC[state] if isinstance(state, str) else int(state)
     return c
 
 
@@ -275,17 +282,28 @@ class Solver:
         self.h = teuk_create(cfg, self.ctx)
 
     @property
+    def dd(self) -> bool:
+        """Double-double state: every value a (hi, lo) pair on a trailing axis."""
+        return self.cfg.state_prec == TEUK_S_DD
+
+    @property
     def plane_shape(self):
-        return (4, self.cfg.ntheta, self.cfg.nr)
+        return (4, self.cfg.ntheta, self.cfg.nr) + ((2,) if self.dd else ())
 
     def set_initial(self, u):
+        """u: [4][ntheta][nr] (FP64 state); for the double-double state
+        [4][ntheta][nr][2] pairs, or [4][ntheta][nr] doubles taken exactly (lo = 0)."""
+        if self.dd and not isinstance(u, torch.Tensor):
+            a = np.asarray(u, dtype=np.float64)
+            if a.shape == (4, self.cfg.ntheta, self.cfg.nr):
+                u = np.stack([a, np.zeros_like(a)], axis=-1)
         teuk_set_initial(self.h, u)
 
     def step(self, nsteps: int):
         teuk_step(self.h, nsteps)
 
     def state(self) -> np.ndarray:
-        n = 4 * self.cfg.ntheta * self.cfg.nr
+        n = int(np.prod(self.plane_shape))
         return teuk_extract(self.h, TEUK_X_STATE, n).reshape(self.plane_shape)
 
     def info(self) -> teuk_info_t:
@@ -294,7 +312,9 @@ class Solver:
     def waveform(self):
         inf = self.info()
         ns = min(inf.samples, self.cfg.max_samples) if self.cfg.extract_every > 0 else 0
-        w = teuk_extract(self.h, TEUK_X_WAVEFORM, ns * self.cfg.ntheta * 2).reshape(ns, self.cfg.ntheta, 2)
+        pv = 2 if self.dd else 1
+        w = teuk_extract(self.h, TEUK_X_WAVEFORM, ns * self.cfg.ntheta * 2 * pv)
+        w = w.reshape((ns, self.cfg.ntheta, 2) + ((2,) if self.dd else ()))
         t = teuk_extract(self.h, TEUK_X_TIMES, ns)
         return t, w
 
@@ -309,12 +329,13 @@ class Solver:
 
     def rhs(self) -> np.ndarray:
         """F(u^n) as the stage kernel evaluates it (the state is unchanged)."""
-        n = 4 * self.cfg.ntheta * self.cfg.nr
+        n = int(np.prod(self.plane_shape))
         return teuk_extract(self.h, TEUK_X_RHS, n).reshape(self.plane_shape)
 
     def coefficients(self) -> np.ndarray:
-        n = self.cfg.ntheta * self.cfg.nr
-        return teuk_extract(self.h, TEUK_X_COEFFS, TEUK_NCOEF * n).reshape(TEUK_NCOEF, self.cfg.ntheta, self.cfg.nr)
+        n = self.cfg.ntheta * self.cfg.nr * (2 if self.dd else 1)
+        shape = (TEUK_NCOEF, self.cfg.ntheta, self.cfg.nr) + ((2,) if self.dd else ())
+        return teuk_extract(self.h, TEUK_X_COEFFS, TEUK_NCOEF * n).reshape(shape)
 
     def check_finite(self):
         teuk_check_finite(self.h)

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "teuk_coef.h"
+#include "teuk_dd_tables.h"
 #include "teuk_internal.h"
 
 using namespace teuk;
@@ -24,6 +25,10 @@ struct teuk_solver {
     double* rtab = nullptr;
     double* ttab = nullptr;
     double* ctab = nullptr;                         // chart H per-point table
+    bool dd = false;                                // double-double state
+    double* dtab = nullptr;                         // double-double per-point table (pairs)
+    DDScalars ddk{};                                // double-double constants
+    long long vals = 0;                             // doubles in the state (4 planes, x2 for pairs)
     double* wave = nullptr;
     double* hwave = nullptr;                        // chart H horizon ring [samples][nth][4]
     int j_h = 0;                                    // chart H: first of the four horizon-stencil nodes
@@ -70,23 +75,26 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t u, rtab, ttab, ctab, wave, hwave, cells, total;
+    size_t u, rtab, ttab, ctab, dtab, wave, hwave, cells, total;
 };
 
 Layout layout_of(const teuk_config& c)
 {
     Layout L;
     const size_t plane = (size_t)c.nr * (size_t)c.ntheta;
-    L.u = align_up(4 * plane * sizeof(double));
+    const bool DD = c.state_prec == TEUK_S_DD;
+    const size_t pv = DD ? 2 : 1;                      // doubles per value
+    L.u = align_up(4 * plane * pv * sizeof(double));
     const bool H = c.chart == TEUK_CHART_HYPERBOLOIDAL;
     L.rtab = H ? 0 : align_up((size_t)kNRT * c.nr * sizeof(double));
     L.ttab = H ? 0 : align_up((size_t)kNTT * c.ntheta * sizeof(double));
     L.ctab = H ? align_up((size_t)kNCH * plane * sizeof(double)) : 0;
+    L.dtab = DD ? align_up((size_t)kNDD * plane * 2 * sizeof(double)) : 0;
     const size_t ns = c.extract_every > 0 ? (size_t)c.max_samples : 0;
-    L.wave = align_up(ns * (size_t)c.ntheta * 2 * sizeof(double));
+    L.wave = align_up(ns * (size_t)c.ntheta * 2 * pv * sizeof(double));
     L.hwave = H ? align_up(ns * (size_t)c.ntheta * 4 * sizeof(double)) : 0;
     L.cells = kAlign;
-    L.total = 3 * L.u + L.rtab + L.ttab + L.ctab + L.wave + L.hwave + L.cells;
+    L.total = 3 * L.u + L.rtab + L.ttab + L.ctab + L.dtab + L.wave + L.hwave + L.cells;
     return L;
 }
 
@@ -137,7 +145,10 @@ bool validate(const teuk_config* c, std::string& err)
     if (c->nr < 7 || c->nr > (1 << 24)) { err = "nr must be in [7, 2^24]"; return false; }
     if (c->ntheta < 2 || c->ntheta > 65536) { err = "ntheta must be in [2, 65536]"; return false; }
     if ((long long)c->nr * c->ntheta > (1LL << 34)) { err = "nr * ntheta too large"; return false; }
-    if (c->weight_prec < TEUK_W_FP64 || c->weight_prec > TEUK_W_BF16) { err = "weight_prec must be a TEUK_W_* value"; return false; }
+    if (c->weight_prec < TEUK_W_FP64 || c->weight_prec > TEUK_W_DD) { err = "weight_prec must be a TEUK_W_* value"; return false; }
+    if (c->state_prec != TEUK_S_FP64 && c->state_prec != TEUK_S_DD) { err = "state_prec must be a TEUK_S_* value"; return false; }
+    if (c->reserved != 0) { err = "reserved must be 0"; return false; }
+    if (c->weight_prec == TEUK_W_DD && c->state_prec != TEUK_S_DD) { err = "TEUK_W_DD weights need the TEUK_S_DD state"; return false; }
     if (!(c->M > 0.0) || !std::isfinite(c->M)) { err = "M must be positive and finite"; return false; }
     if (!(c->a >= 0.0) || !(c->a <= c->M)) { err = "spin a must satisfy 0 <= a <= M"; return false; }
     if (!std::isfinite(c->x_min) || !std::isfinite(c->x_max) || !(c->x_min < c->x_max)) { err = "need finite x_min < x_max"; return false; }
@@ -200,7 +211,7 @@ teuk_status run_guard(teuk_solver* h)
 {
     int e = (int)hipMemsetAsync(h->flag, 0, sizeof(int), h->stream);
     if (e) return hip_fail(h, e, "hipMemsetAsync(flag)");
-    e = launch_guard(h->u[0], 4 * h->plane, h->flag, h->stream);
+    e = launch_guard(h->u[0], h->vals, h->flag, h->stream);
     if (e) return hip_fail(h, e, "guard launch");
     int f = 0;
     e = (int)hipMemcpyAsync(&f, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
@@ -215,14 +226,31 @@ teuk_status record_sample(teuk_solver* h)
 {
     if (h->cfg.extract_every <= 0) return TEUK_OK;
     const long long slot = h->samples % h->cfg.max_samples;
-    double* dst = h->wave + (size_t)slot * h->cfg.ntheta * 2;
-    int e = launch_extract(h->u[0], h->plane, h->cfg.nr, h->cfg.ntheta, h->j_e, dst, h->stream);
+    double* dst = h->wave + (size_t)slot * h->cfg.ntheta * (h->dd ? 4 : 2);
+    int e = h->dd ? launch_dd_extract(h->u[0], h->plane, h->cfg.nr, h->cfg.ntheta, h->j_e, dst, h->stream)
+                  : launch_extract(h->u[0], h->plane, h->cfg.nr, h->cfg.ntheta, h->j_e, dst, h->stream);
     if (!e && h->hwave)
         e = launch_horizon(h->u[0], h->plane, h->cfg.nr, h->cfg.ntheta, h->j_h, h->hw, h->hdw,
                            h->hwave + (size_t)slot * h->cfg.ntheta * 4, h->stream);
     if (e) return hip_fail(h, e, "extract launch");
     ++h->samples;
     return TEUK_OK;
+}
+
+// Double-double table [kNDD][plane][2] -> TEUK_X_COEFFS order, pairs:
+// lam1 = b, Re m3, Im m3, Re B~t, Im B~t, Re C~, Im C~, A~thth, B~th, lam2 = -b.
+void dd_coeff_order(const double* t, long long plane, double* out)
+{
+    const int src[TEUK_NCOEF] = {kDB, kDM3r, kDM3i, kDBtr, kDBti, kDCr, kDCi, kDAth, kDBth, kDB};
+    const size_t n = (size_t)plane * 2;
+    for (int q = 0; q < TEUK_NCOEF; ++q) {
+        const double* a = t + (size_t)src[q] * n;
+        double* o = out + (size_t)q * n;
+        if (q == TEUK_NCOEF - 1)
+            for (size_t i = 0; i < n; ++i) o[i] = -a[i];
+        else
+            std::memcpy(o, a, n * sizeof(double));
+    }
 }
 
 }  // namespace
@@ -256,9 +284,15 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     std::string err;
     if (!validate(cfg, err)) return fail(nullptr, TEUK_ERR_INVALID_ARG, err);
     const bool chartH = cfg->chart == TEUK_CHART_HYPERBOLOIDAL;
-    std::vector<double> rtab, ttab, ctab;
+    const bool dd = cfg->state_prec == TEUK_S_DD;
+    if (dd && (chartH || (cfg->weight_prec != TEUK_W_DD && cfg->weight_prec != TEUK_W_FP64)))
+        return fail(nullptr, TEUK_ERR_UNSUPPORTED,
+                    "double-double state: tortoise chart with TEUK_W_DD or TEUK_W_FP64 weights only");
+    std::vector<double> rtab, ttab, ctab, dtab;
+    DDScalars ddk{};
     if (chartH ? !build_tables_H(*cfg, ctab, err) : !build_tables(*cfg, rtab, ttab, err))
         return fail(nullptr, TEUK_ERR_INVALID_ARG, err);
+    if (dd && !build_tables_dd(*cfg, dtab, &ddk, err)) return fail(nullptr, TEUK_ERR_INVALID_ARG, err);
 
     teuk_solver* h = new (std::nothrow) teuk_solver();
     if (!h) return fail(nullptr, TEUK_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -296,6 +330,9 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     h->rtab = L.rtab ? (double*)p : nullptr; p += L.rtab;
     h->ttab = L.ttab ? (double*)p : nullptr; p += L.ttab;
     h->ctab = L.ctab ? (double*)p : nullptr; p += L.ctab;
+    h->dtab = L.dtab ? (double*)p : nullptr; p += L.dtab;
+    h->dd = dd;
+    h->ddk = ddk;
     h->wave = (double*)p; p += L.wave;
     h->hwave = L.hwave ? (double*)p : nullptr; p += L.hwave;
     if (chartH) (void)horizon_stencil(*cfg, &h->j_h, h->hw, h->hdw);
@@ -303,11 +340,13 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     h->flag = (int*)(p + 64);
 
     h->plane = (long long)cfg->nr * cfg->ntheta;
+    h->vals = 4 * h->plane * (dd ? 2 : 1);
     h->dx = (cfg->x_max - cfg->x_min) / (cfg->nr - 1);
     h->dth = M_PI / cfg->ntheta;
     h->nstrips = (cfg->nr + kStripPoints - 1) / kStripPoints;
-    h->segs[0] = pick_segs(*cfg, h->nstrips, cfg->weight_prec, true);
-    h->segs[1] = pick_segs(*cfg, h->nstrips, cfg->weight_prec, false);
+    // (the double-double kernel runs one wave per strip and theta row)
+    h->segs[0] = dd ? 1 : pick_segs(*cfg, h->nstrips, cfg->weight_prec, true);
+    h->segs[1] = dd ? 1 : pick_segs(*cfg, h->nstrips, cfg->weight_prec, false);
     if (h->segs[0] <= 0 || h->segs[1] <= 0 || (long long)h->nstrips * h->segs[0] > (1LL << 31) - 1 ||
         (long long)h->nstrips * h->segs[1] > (1LL << 31) - 1) {
         free_solver(h);
@@ -323,6 +362,8 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
         e = (int)hipMemcpyAsync(h->rtab, rtab.data(), rtab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
         if (!e) e = (int)hipMemcpyAsync(h->ttab, ttab.data(), ttab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
     }
+    if (!e && dd)
+        e = (int)hipMemcpyAsync(h->dtab, dtab.data(), dtab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
     if (!e) e = (int)hipMemsetAsync(h->cell, 0, sizeof(unsigned long long), h->stream);
     if (!e) e = launch_dt_bound(h->rtab, h->ttab, h->ctab, cfg->nr, cfg->ntheta, h->dx, h->dth, h->cell, h->stream);
     unsigned long long bits = 0;
@@ -349,14 +390,30 @@ teuk_status teuk_set_initial(teuk_solver* h, const double* u, int32_t on_device)
 {
     if (!h) return fail(nullptr, TEUK_ERR_INVALID_ARG, "solver is NULL");
     if (!u) return fail(h, TEUK_ERR_INVALID_ARG, "u is NULL");
-    const size_t n = 4 * (size_t)h->plane;
+    const size_t n = (size_t)h->vals;
+    std::vector<double> norm;
     if (!on_device) {
         for (size_t i = 0; i < n; ++i)
             if (!std::isfinite(u[i])) return fail(h, TEUK_ERR_NONFINITE, "initial data contain NaN or Inf");
+        if (h->dd) {
+            // store each pair normalised: TwoSum(hi, lo)
+            norm.resize(n);
+            for (size_t i = 0; i < n; i += 2) {
+                const double a = u[i], b = u[i + 1];
+                const double s = a + b, bb = s - a;
+                norm[i] = s;
+                norm[i + 1] = (a - (s - bb)) + (b - bb);
+            }
+            u = norm.data();
+        }
     }
     int e = (int)hipMemcpyAsync(h->u[0], u, n * sizeof(double),
                                 on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream);
     if (e) return hip_fail(h, e, "hipMemcpyAsync(initial state)");
+    if (on_device && h->dd) {
+        e = launch_dd_normalise(h->u[0], (long long)n / 2, h->stream);
+        if (e) return hip_fail(h, e, "normalise launch");
+    }
     if (!on_device) {
         e = (int)hipStreamSynchronize(h->stream);   // host array may be released after return
         if (e) return hip_fail(h, e, "hipStreamSynchronize");
@@ -368,6 +425,54 @@ teuk_status teuk_set_initial(teuk_solver* h, const double* u, int32_t on_device)
     h->samples = 0;
     h->have_init = true;
     return record_sample(h);
+}
+
+static DDStageArgs dd_args(const teuk_solver* h)
+{
+    const teuk_config& c = h->cfg;
+    DDStageArgs a{};
+    a.ctab = h->dtab;
+    a.plane = h->plane;
+    a.nr = c.nr;
+    a.nth = c.ntheta;
+    a.nstrips = h->nstrips;
+    auto cp = [](double* d, const double* s) { d[0] = s[0]; d[1] = s[1]; };
+    cp(a.inv_dx, h->ddk.inv_dx);
+    cp(a.ih1, h->ddk.ih1);
+    cp(a.ih2, h->ddk.ih2);
+    cp(a.sixth, h->ddk.sixth);
+    cp(a.c13_3, h->ddk.c13_3);
+    for (int q = 0; q < 3; ++q) cp(a.d[q], h->ddk.d[q]);
+    a.ca[0] = a.ca[1] = a.cb[1] = 0.0;
+    a.cb[0] = 1.0;
+    a.dt = h->dt;
+    a.eps = c.weno_eps;
+    a.parity = ((c.m + c.s) % 2 != 0) ? -1.0 : 1.0;
+    a.uk = a.un = h->u[0];
+    a.out = h->u[1];
+    return a;
+}
+
+// One SSP-RK(3,3) step of the double-double state, the same three stages as
+// the FP64 path with the combination coefficients as double-double pairs.
+static int dd_step(teuk_solver* h)
+{
+    DDStageArgs a = dd_args(h);
+    const int wp = h->cfg.weight_prec;
+    a.uk = h->u[0]; a.un = h->u[0]; a.out = h->u[1];
+    int e = launch_dd_stage(a, 1, wp, h->stream);
+    if (!e) {
+        a.uk = h->u[1]; a.out = h->u[2];
+        a.ca[0] = 0.75; a.cb[0] = 0.25;
+        e = launch_dd_stage(a, 2, wp, h->stream);
+    }
+    if (!e) {
+        a.uk = h->u[2]; a.out = h->u[0];
+        a.ca[0] = h->ddk.third[0]; a.ca[1] = h->ddk.third[1];
+        a.cb[0] = h->ddk.two_thirds[0]; a.cb[1] = h->ddk.two_thirds[1];
+        e = launch_dd_stage(a, 3, wp, h->stream);
+    }
+    return e;
 }
 
 static StageArgs stage_args(const teuk_solver* h)
@@ -402,6 +507,18 @@ teuk_status teuk_step(teuk_solver* h, int64_t nsteps)
     if (nsteps < 0) return fail(h, TEUK_ERR_INVALID_ARG, "nsteps must be >= 0");
     if (!h->have_init) return fail(h, TEUK_ERR_STATE, "teuk_step before teuk_set_initial");
     const teuk_config& c = h->cfg;
+    if (h->dd) {
+        for (int64_t n = 0; n < nsteps; ++n) {
+            const int e = dd_step(h);
+            if (e) return hip_fail(h, e, "stage launch");
+            ++h->steps;
+            if (c.extract_every > 0 && h->steps % c.extract_every == 0) {
+                teuk_status st = record_sample(h);
+                if (st != TEUK_OK) return st;
+            }
+        }
+        return TEUK_OK;
+    }
     StageArgs a = stage_args(h);
     for (int64_t n = 0; n < nsteps; ++n) {
         // u1 = u + dt F(u)
@@ -431,12 +548,13 @@ teuk_status teuk_extract(teuk_solver* h, int32_t what, double* out, size_t capac
     const teuk_config& c = h->cfg;
     const long long nsamp = c.extract_every > 0 ? (h->samples < c.max_samples ? h->samples : c.max_samples) : 0;
     size_t need = 0;
+    const size_t pv = h->dd ? 2 : 1;
     switch (what) {
-    case TEUK_X_STATE: need = 4 * (size_t)h->plane; break;
-    case TEUK_X_WAVEFORM: need = (size_t)nsamp * c.ntheta * 2; break;
+    case TEUK_X_STATE: need = (size_t)h->vals; break;
+    case TEUK_X_WAVEFORM: need = (size_t)nsamp * c.ntheta * 2 * pv; break;
     case TEUK_X_TIMES: need = (size_t)nsamp; break;
-    case TEUK_X_COEFFS: need = (size_t)TEUK_NCOEF * h->plane; break;
-    case TEUK_X_RHS: need = 4 * (size_t)h->plane; break;
+    case TEUK_X_COEFFS: need = (size_t)TEUK_NCOEF * h->plane * pv; break;
+    case TEUK_X_RHS: need = (size_t)h->vals; break;
     case TEUK_X_HORIZON:
         if (!h->hwave) return fail(h, TEUK_ERR_UNSUPPORTED, "horizon samples need the hyperboloidal chart and a waveform cadence");
         need = (size_t)nsamp * c.ntheta * 4;
@@ -456,7 +574,7 @@ teuk_status teuk_extract(teuk_solver* h, int32_t what, double* out, size_t capac
         e = (int)hipMemcpyAsync(out, h->u[0], need * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     } else if (what == TEUK_X_WAVEFORM) {
         const long long first = h->samples - nsamp;          // oldest sample kept
-        const size_t per = (size_t)c.ntheta * 2;
+        const size_t per = (size_t)c.ntheta * 2 * pv;
         for (long long i = 0; i < nsamp && !e; ++i) {
             const long long slot = (first + i) % c.max_samples;
             e = (int)hipMemcpyAsync(out + i * per, h->wave + slot * per, per * sizeof(double),
@@ -473,12 +591,23 @@ teuk_status teuk_extract(teuk_solver* h, int32_t what, double* out, size_t capac
     } else if (what == TEUK_X_RHS) {
         // F(u^n) by the stage kernel itself, written into the u^(1) buffer
         // (scratch between steps), then copied out
-        StageArgs a = stage_args(h);
-        e = launch_stage(a, 0, h->cfg.weight_prec, h->cfg.chart, h->stream);
+        if (h->dd) {
+            DDStageArgs a = dd_args(h);
+            e = launch_dd_stage(a, 0, h->cfg.weight_prec, h->stream);
+        } else {
+            StageArgs a = stage_args(h);
+            e = launch_stage(a, 0, h->cfg.weight_prec, h->cfg.chart, h->stream);
+        }
         if (!e) e = (int)hipMemcpyAsync(out, h->u[1], need * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     } else if (what == TEUK_X_TIMES) {
         const long long first = h->samples - nsamp;
         for (long long i = 0; i < nsamp; ++i) out[i] = (double)((first + i) * (long long)c.extract_every) * h->dt;
+    } else if (h->dd) {
+        // the streamed double-double table, rearranged into the TEUK_X_COEFFS order
+        std::vector<double> t((size_t)kNDD * h->plane * 2);
+        e = (int)hipMemcpyAsync(t.data(), h->dtab, t.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+        if (!e) e = (int)hipStreamSynchronize(h->stream);
+        if (!e) dd_coeff_order(t.data(), h->plane, out);
     } else {
         double* tmp = nullptr;
         e = (int)hipMalloc(&tmp, need * sizeof(double));
@@ -535,6 +664,16 @@ teuk_status teuk_host_coefficients(const teuk_config* cfg, double* out, size_t c
     if (!validate(cfg, err)) return fail(nullptr, TEUK_ERR_INVALID_ARG, err);
     if (!out) return fail(nullptr, TEUK_ERR_INVALID_ARG, "out is NULL");
     const size_t n = (size_t)cfg->nr * cfg->ntheta;
+    if (cfg->state_prec == TEUK_S_DD) {
+        if (cfg->chart != TEUK_CHART_TORTOISE)
+            return fail(nullptr, TEUK_ERR_UNSUPPORTED, "double-double state: tortoise chart only");
+        if (capacity < 2 * TEUK_NCOEF * n) return fail(nullptr, TEUK_ERR_CAPACITY, "out too small");
+        std::vector<double> dtab;
+        DDScalars sc;
+        if (!build_tables_dd(*cfg, dtab, &sc, err)) return fail(nullptr, TEUK_ERR_INVALID_ARG, err);
+        dd_coeff_order(dtab.data(), (long long)n, out);
+        return TEUK_OK;
+    }
     if (capacity < TEUK_NCOEF * n) return fail(nullptr, TEUK_ERR_CAPACITY, "out too small");
     if (cfg->chart == TEUK_CHART_HYPERBOLOIDAL) {
         std::vector<double> ctab;
@@ -677,6 +816,7 @@ teuk_status teuk_group_add(teuk_group* g, teuk_solver* h)
 {
     if (!g) return gfail(nullptr, TEUK_ERR_INVALID_ARG, "group is NULL");
     if (!h) return gfail(g, TEUK_ERR_INVALID_ARG, "solver is NULL");
+    if (h->dd) return gfail(g, TEUK_ERR_UNSUPPORTED, "double-double solvers are not group members");
     if (h->group) return gfail(g, TEUK_ERR_INVALID_ARG, "solver already belongs to a group");
     if (h->stream != g->stream) return gfail(g, TEUK_ERR_INVALID_ARG, "solver and group use different streams");
     if (h->device != g->device) return gfail(g, TEUK_ERR_INVALID_ARG, "solver and group are on different devices");

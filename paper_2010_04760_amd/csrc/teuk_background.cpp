@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "teuk_coef.h"
+#include "teuk_dd_tables.h"
 #include "teuk_internal.h"
 
 namespace teuk {
@@ -86,6 +87,11 @@ double solve_lny(const Kerr& k, double x)
 }
 
 }  // namespace
+
+double tortoise_lny(const teuk_config& c, double x)
+{
+    return solve_lny(make_kerr(c.M, c.a), x);
+}
 
 bool build_tables(const teuk_config& c, std::vector<double>& rtab, std::vector<double>& ttab,
                   std::string& err)

@@ -44,6 +44,21 @@ struct StageArgs {
     double eps, parity;    // WENO epsilon, (-1)^(m+s)
 };
 
+// Arguments of one stage of the double-double state path (tortoise chart).
+// Every array holds (hi, lo) pairs: state [4][nth][nr], table [kNDD][nth][nr].
+struct DDStageArgs {
+    const double* uk;      // u^(k)
+    const double* un;      // u^n, read at the own point only (stages 2, 3)
+    double* out;           // u^(k+1); may alias un
+    const double* ctab;    // double-double coefficient table
+    long long plane;       // nth * nr (pairs)
+    int nr, nth, nstrips;
+    double inv_dx[2], ih1[2], ih2[2];
+    double ca[2], cb[2];   // out = ca un + cb (uk + dt F) for stages 2, 3
+    double sixth[2], c13_3[2], d[3][2];
+    double dt, eps, parity;
+};
+
 // Resident workgroup count of a stage-kernel instantiation on the current
 // device (0 if the weight precision is not built).  The launch uses
 // nstrips * segs workgroups with segs chosen from it.
@@ -65,6 +80,12 @@ int launch_extract(const double* u, long long plane, int nr, int nth, int j_e, d
                    void* stream);
 int launch_coef_dump(const double* rtab, const double* ttab, const double* ctab, int nr, int nth, double* out,
                      void* stream);
+// Double-double path: one stage (0 = F only, 1, 2, 3) with weights in FP64
+// (TEUK_W_FP64, the mixed variant) or double-double (TEUK_W_DD); the waveform
+// sample of one radial index ([nth][2] pairs); TwoSum normalisation of n pairs.
+int launch_dd_stage(const DDStageArgs& a, int stage, int weight_prec, void* stream);
+int launch_dd_extract(const double* u, long long plane, int nr, int nth, int j_e, double* slot, void* stream);
+int launch_dd_normalise(double* u, long long n, void* stream);
 // Horizon sample: Phi and d_rho Phi from the nodes j0 .. j0+3 with value
 // weights w[4] and derivative weights dw[4] (divided by dx); slot is [nth][4].
 int launch_horizon(const double* u, long long plane, int nr, int nth, int j0, const double* w, const double* dw,

@@ -1,0 +1,70 @@
+"""Host-side checks of the double-double state path (no GPU needed): its
+per-point coefficient table, evaluated by the library in binary128, agrees
+with the oracle's 45-digit evaluation of the symbolic derivation to about the
+precision of a double-double pair, and its configurations are validated."""
+import mpmath as mp
+import numpy as np
+import pytest
+
+import paper_2010_04760_amd as T
+from oracle import quad as Q
+from oracle import solver as S
+
+NAMES = ["lam1", "m3r", "m3i", "btr", "bti", "cr", "ci", "ath", "bth", "lam2"]
+
+
+@pytest.mark.parametrize("s,m,a,x0,x1", [(-2, 2, 0.999, -60.0, 90.0), (0, 0, 1.0, -40.0, 70.0),
+                                         (-2, 4, 0.5, -30.0, 50.0), (1, -3, 0.3, -20.0, 40.0)])
+def test_dd_table_matches_the_45_digit_oracle_tables(s, m, a, x0, x1):
+    nr, nth = 23, 5
+    cfg = T.make_config(s=s, m=m, a=a, nr=nr, ntheta=nth, x_min=x0, x_max=x1, state="dd", weight_prec="dd")
+    hc = T.teuk_host_coefficients(cfg)
+    assert hc.shape == (10, nth, nr, 2)
+    tq = Q.first_order_tables_mp(S.Problem(s, m, a, nr, nth, x0, x1))
+    mp.mp.dps = 50
+    scale = max(float(np.max(np.abs(tq[n][..., 0]))) for n in NAMES)
+    for i, n in enumerate(NAMES):
+        for k in range(nth):
+            for j in range(nr):
+                got = Q.to_mpf(hc[i, k, j])
+                ref = Q.to_mpf(tq[n][k, j])
+                assert abs(got - ref) <= mp.mpf("2e-30") * (abs(ref) + mp.mpf(1e-3) * scale), (n, k, j, got, ref)
+                # normalised pairs
+                assert abs(hc[i, k, j, 1]) <= 0.5 * np.spacing(abs(hc[i, k, j, 0])) or hc[i, k, j, 0] == 0.0
+
+
+def test_dd_table_hi_parts_match_the_fp64_table():
+    cfg64 = T.make_config(s=-2, m=2, a=0.999, nr=101, ntheta=9, x_min=-50.0, x_max=80.0)
+    cfgdd = T.make_config(s=-2, m=2, a=0.999, nr=101, ntheta=9, x_min=-50.0, x_max=80.0, state="dd")
+    c64 = T.teuk_host_coefficients(cfg64)
+    cdd = T.teuk_host_coefficients(cfgdd)
+    for i in range(10):
+        sc = np.max(np.abs(c64[i])) + 1e-300
+        assert np.max(np.abs(cdd[i, ..., 0] - c64[i])) <= 1e-13 * sc, i
+
+
+def test_dd_validation():
+    base = dict(s=-2, m=2, a=0.9, nr=128, ntheta=8, x_min=-20.0, x_max=40.0)
+    fp64 = T.teuk_footprint_bytes(T.make_config(**base))
+    dd = T.teuk_footprint_bytes(T.make_config(**base, state="dd", weight_prec="dd"))
+    plane = 128 * 8
+    assert dd >= fp64 + 3 * 4 * plane * 8 + 9 * plane * 16
+    # double-double weights need the double-double state
+    with pytest.raises(T.TeukError) as ei:
+        T.teuk_create(T.make_config(**base, weight_prec="dd"))
+    assert ei.value.status == T.TEUK_ERR_INVALID_ARG
+    assert T.teuk_footprint_bytes(T.make_config(**base, weight_prec="dd")) == 0
+    assert T.teuk_footprint_bytes(T.make_config(**base, state=2)) == 0
+    c = T.make_config(**base)
+    c.reserved = 1
+    assert T.teuk_footprint_bytes(c) == 0
+    # valid but not offered: reduced-precision weights or the hyperboloidal chart
+    for kw in (dict(weight_prec="fp32"), dict(weight_prec="bf16")):
+        with pytest.raises(T.TeukError) as ei:
+            T.teuk_create(T.make_config(**base, state="dd", **kw))
+        assert ei.value.status == T.TEUK_ERR_UNSUPPORTED
+    ch = T.make_config(s=-2, m=0, a=1.0, nr=101, ntheta=8, x_min=20 / 21, x_max=19.0, chart="H", state="dd",
+                       weight_prec="dd")
+    with pytest.raises(T.TeukError) as ei:
+        T.teuk_create(ch)
+    assert ei.value.status == T.TEUK_ERR_UNSUPPORTED

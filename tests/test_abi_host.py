@@ -44,6 +44,7 @@ int main(void) {
   printf("teuk_device_ctx %zu\\n", sizeof(teuk_device_ctx));
   printf("teuk_info_t %zu\\n", sizeof(teuk_info_t));
   F(teuk_config, M) F(teuk_config, a) F(teuk_config, x_extract) F(teuk_config, workgroups) F(teuk_config, S)
+  F(teuk_config, state_prec) F(teuk_config, reserved)
   F(teuk_info_t, samples) F(teuk_info_t, dt_bound) F(teuk_device_ctx, workspace_bytes)
   return 0; }
 """)
@@ -143,7 +144,7 @@ def test_footprint_and_validation():
     fp = T.teuk_footprint_bytes(ok)
     assert fp >= 3 * 4 * 512 * 32 * 8
     bad = []
-    for field, val in [("a", 1.5), ("nr", 6), ("ntheta", 1), ("weight_prec", 7), ("abi_version", 2),
+    for field, val in [("a", 1.5), ("nr", 6), ("ntheta", 1), ("weight_prec", 7), ("abi_version", 99),
                        ("chart", 3), ("weno_eps", 0.0), ("M", -1.0), ("s", 3)]:
         c = T.make_config(s=0, m=0, a=0.5, nr=512, ntheta=32, x_min=-64, x_max=64)
         setattr(c, field, val)

@@ -313,3 +313,23 @@ def test_teuk_rhs_and_steps_agree_with_the_fp64_oracle():
     um, _ = oqm.evolve(Q.promote(u0), dt, 4)
     diff = np.max(np.abs((um[..., 0] - uq[..., 0]) + (um[..., 1] - uq[..., 1])))
     assert 0 < diff <= 1e-14 * np.max(np.abs(u))
+
+
+def test_window_solve_matches_the_full_grid_inside():
+    # The window oracle (used for sampled checks of large grids) solves a block
+    # as if it were the whole grid; one step moves information 9 radial nodes
+    # and 3 theta rows, so inside that margin it must equal the full solve.
+    import workloads as W
+    prob = S.Problem(-2, 2, 0.999, 60, 12, -30.0, 50.0)
+    full = Q.TeukOracleQ(prob)
+    u0 = Q.promote(W.random_state(prob.nr, prob.nth, seed=9, smooth=True))
+    dt = 0.4 * S.TeukOracle(prob).dt_bound(1.0)
+    uf, _ = full.evolve(u0, dt, 1)
+    j0, k0, nw, kw = 17, 3, 30, 8
+    win = Q.TeukOracleQ(prob, window=(j0, k0, nw, kw))
+    for n in win.tab:
+        assert np.array_equal(win.tab[n], full.tab[n][k0:k0 + kw, j0:j0 + nw]), n
+    uw, _ = win.evolve(u0[:, k0:k0 + kw, j0:j0 + nw], dt, 1)
+    inner = (slice(None), slice(3, kw - 3), slice(9, nw - 9))
+    assert np.array_equal(uw[inner], uf[:, k0:k0 + kw, j0:j0 + nw][inner])
+    assert not np.array_equal(uw, uf[:, k0:k0 + kw, j0:j0 + nw])
