@@ -100,6 +100,22 @@ def roofline(points_per_launch: float, t_launch: float, traffic):
             "algorithmic_bytes_per_launch": bytes_launch, "avg_launch_us": t_launch * 1e6}
 
 
+# FP64 operations (FMA counted twice) and VALU instructions per point-stage of
+# the double-double stage kernel, counted in its gfx950 ISA (stages 2 and 3;
+# one lane per point): it is bound by FP64 instruction issue.
+DD_OPS = {"dd_weights": (4701, 4311), "fp64_weights": (2807, 2697)}
+FP64_VECTOR_TFLOPS = 78.6                 # MI355X FP64 vector peak (FMA = 2 flops)
+VALU_ISSUE_PER_S = 256 * 4 * 16 * 2.4e9   # lane-instructions/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+
+
+def dd_roofline(points_per_launch: float, t_launch: float, variant: str):
+    flops, instrs = DD_OPS[variant]
+    achieved = flops * points_per_launch / t_launch / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_VECTOR_TFLOPS, "traffic": None, "avg_launch_us": t_launch * 1e6,
+            "valu_issue_frac": instrs * points_per_launch / t_launch / VALU_ISSUE_PER_S}
+
+
 def solver_config(T, wl, weights, total_steps, workgroups=0, every=None, state="fp64"):
     every = wl.every if every is None else every
     return T.make_config(s=wl.s, m=wl.m, a=wl.a, nr=wl.nr, ntheta=wl.nth, x_min=wl.x_min, x_max=wl.x_max,
@@ -198,6 +214,8 @@ def bench_single(args, torch, T, W):
             "waveform_rel_l2_fp64_state_vs_dd": float(np.linalg.norm(wave64 - wave_dd[..., 0] - wave_dd[..., 1])
                                                       / np.linalg.norm(vdd)),
             "cost_vs_fp64_state": {"dd_weights": sec_dd / sec64, "fp64_weights": sec_mx / sec64},
+            "roofline": {wv: dd_roofline(wl.points, sec / (3 * qs), wv)
+                         for wv, sec in (("dd_weights", sec_dd), ("fp64_weights", sec_mx))},
         }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
