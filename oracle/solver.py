@@ -82,6 +82,11 @@ def lib() -> ctypes.CDLL:
                                        ctypes.c_double, ctypes.c_int]
             getattr(L, fn).restype = ctypes.c_double
         L.oracle_ssprk3_step.argtypes = [_dp, ctypes.c_long, ctypes.c_double, RHS_FN, ctypes.c_void_p, _dp]
+        L.oracle_ssprk104_step.argtypes = [_dp, ctypes.c_long, ctypes.c_double, RHS_FN, ctypes.c_void_p, _dp]
+        L.oracle_teuk_evolve_rk.argtypes = [ctypes.POINTER(_OracleTeuk), _dp, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_long, ctypes.c_long, ctypes.c_long, _dp, ctypes.c_long,
+                                            ctypes.c_int]
+        L.oracle_teuk_evolve_rk.restype = ctypes.c_long
         L.oracle_advect1d.argtypes = [_dp, ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_long, ctypes.c_double,
                                       ctypes.c_int]
@@ -146,11 +151,23 @@ def advect1d(u0, dx, speed, dt, nsteps, eps=1e-6):
     return u
 
 
+INTEGRATORS = {"rk3": 0, "rk104": 1}
+
+
 def ssprk3_step(u0, dt, rhs):
     """One SSP-RK(3,3) step of the oracle with a Python right-hand side rhs(u)->F."""
+    return _rk_step(u0, dt, rhs, "oracle_ssprk3_step", 3)
+
+
+def ssprk104_step(u0, dt, rhs):
+    """One SSP-RK(10,4) step of the oracle with a Python right-hand side rhs(u)->F."""
+    return _rk_step(u0, dt, rhs, "oracle_ssprk104_step", 5)
+
+
+def _rk_step(u0, dt, rhs, name, nwork):
     u = np.ascontiguousarray(u0, dtype=np.float64).copy()
     n = u.size
-    work = np.zeros(3 * n)
+    work = np.zeros(nwork * n)
 
     def cb(up, Fp, _ctx):
         uu = np.ctypeslib.as_array(up, shape=(n,))
@@ -158,7 +175,7 @@ def ssprk3_step(u0, dt, rhs):
         FF[:] = rhs(uu.copy())
 
     f = RHS_FN(cb)
-    lib().oracle_ssprk3_step(ptr(u), n, dt, f, None, ptr(work))
+    getattr(lib(), name)(ptr(u), n, dt, f, None, ptr(work))
     return u
 
 
@@ -273,8 +290,9 @@ class TeukOracle:
         win = ph[:, j0:j0 + 4]
         return win @ w, (win @ dw) / p.dx
 
-    def evolve(self, u0, dt, nsteps, x_e=None, every=0, max_samples=0):
-        """Run nsteps SSP-RK3 steps.  Returns (u, wave[n][nth][2] or None)."""
+    def evolve(self, u0, dt, nsteps, x_e=None, every=0, max_samples=0, integrator="rk3"):
+        """Run nsteps steps of SSP-RK(3,3) (integrator "rk3") or SSP-RK(10,4)
+        ("rk104").  Returns (u, wave[n][nth][2] or None)."""
         u = np.ascontiguousarray(u0, dtype=np.float64).copy()
         wave = None
         j_e = 0
@@ -283,8 +301,9 @@ class TeukOracle:
             if max_samples <= 0:
                 max_samples = nsteps // every + 1
             wave = np.zeros((max_samples, self.prob.nth, 2))
-        n = lib().oracle_teuk_evolve(ctypes.byref(self._s), ptr(u), dt, 0.0, nsteps, j_e, every,
-                                     ptr(wave) if wave is not None else None, max_samples)
+        n = lib().oracle_teuk_evolve_rk(ctypes.byref(self._s), ptr(u), dt, 0.0, nsteps, j_e, every,
+                                        ptr(wave) if wave is not None else None, max_samples,
+                                        INTEGRATORS[integrator])
         if wave is not None:
             wave = wave[:n]
         return u, wave

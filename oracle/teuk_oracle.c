@@ -213,6 +213,46 @@ void FN(oracle_ssprk3_step)(real* u, long n, double dt, oracle_rhs_fn rhs, void*
     ssprk3_step(u, n, R(dt), rhs, ctx, work);
 }
 
+/* One step of the low-storage ten-stage, fourth-order SSP-RK(10,4) as the
+ * paper writes it (Sec. 3.2):
+ *   u(1)    = u^n + dt/6 F(u^n),  u(i) = u(i-1) + dt/6 F(u(i-1)), i = 2..4,
+ *   u(5)    = 3/5 u^n + 2/5 u(4) + 1/15 dt F(u(4)),
+ *   u(i)    = u(i-1) + dt/6 F(u(i-1)), i = 6..9,
+ *   u^{n+1} = 1/25 u^n + 9/25 u(4) + 3/5 u(9) + 3/50 dt F(u(4)) + 1/10 dt F(u(9)).
+ * work holds 5n values (u^n, u(4), F(u(4)), the current stage, F). */
+static void ssprk104_step(real* u, long n, real dt, oracle_rhs_fn rhs, void* ctx, real* work)
+{
+    real* un = work;
+    real* u4 = work + n;
+    real* F4 = work + 2 * n;
+    real* cur = work + 3 * n;
+    real* F = work + 4 * n;
+    const real h6 = dt / R(6);
+    memcpy(un, u, (size_t)n * sizeof(real));
+    memcpy(cur, u, (size_t)n * sizeof(real));
+    for (int st = 1; st <= 4; ++st) {
+        rhs(cur, F, ctx);
+        for (long i = 0; i < n; ++i) cur[i] = cur[i] + h6 * F[i];
+    }
+    memcpy(u4, cur, (size_t)n * sizeof(real));
+    rhs(u4, F4, ctx);
+    for (long i = 0; i < n; ++i)
+        cur[i] = R(3) / R(5) * un[i] + R(2) / R(5) * u4[i] + R(1) / R(15) * dt * F4[i];
+    for (int st = 6; st <= 9; ++st) {
+        rhs(cur, F, ctx);
+        for (long i = 0; i < n; ++i) cur[i] = cur[i] + h6 * F[i];
+    }
+    rhs(cur, F, ctx);
+    for (long i = 0; i < n; ++i)
+        u[i] = R(1) / R(25) * un[i] + R(9) / R(25) * u4[i] + R(3) / R(5) * cur[i] + R(3) / R(50) * dt * F4[i] +
+               R(1) / R(10) * dt * F[i];
+}
+
+void FN(oracle_ssprk104_step)(real* u, long n, double dt, oracle_rhs_fn rhs, void* ctx, real* work)
+{
+    ssprk104_step(u, n, R(dt), rhs, ctx, work);
+}
+
 /* ---------------------------------------------------------------- 1D advection (tests) */
 
 typedef struct {
@@ -334,20 +374,24 @@ static void teuk_rhs_cb(const real* u, real* F, void* ctx)
     FN(oracle_teuk_rhs)((const oracle_teuk*)ctx, u, F);
 }
 
-/* Evolve u in place for nsteps SSP-RK3 steps of size dt = dt_hi + dt_lo.  If
+/* Evolve u in place for nsteps steps of size dt = dt_hi + dt_lo of SSP-RK(3,3)
+ * (integrator 0) or SSP-RK(10,4) (integrator 1).  If
  * wave != NULL, (Phi_R, Phi_I) at radial index j_e is recorded for every theta
  * row at the initial state and after every `every`-th step, as
  * wave[n][nth][2], up to max_samples samples.  Returns the number of samples
  * written. */
-long FN(oracle_teuk_evolve)(const oracle_teuk* P, real* u, double dt, double dt_lo, long nsteps,
-                            long j_e, long every, real* wave, long max_samples)
+long FN(oracle_teuk_evolve_rk)(const oracle_teuk* P, real* u, double dt, double dt_lo, long nsteps,
+                               long j_e, long every, real* wave, long max_samples, int integrator)
 {
     const long N = P->nr * P->nth, n = 4 * N;
     const real h = pair(dt, dt_lo);
-    real* work = (real*)malloc((size_t)(3 * n) * sizeof(real));
+    real* work = (real*)malloc((size_t)(5 * n) * sizeof(real));
     long ns = 0;
     for (long s = 0; s <= nsteps; ++s) {
-        if (s > 0) ssprk3_step(u, n, h, teuk_rhs_cb, (void*)P, work);
+        if (s > 0) {
+            if (integrator == 1) ssprk104_step(u, n, h, teuk_rhs_cb, (void*)P, work);
+            else ssprk3_step(u, n, h, teuk_rhs_cb, (void*)P, work);
+        }
         if (wave && every > 0 && s % every == 0 && ns < max_samples) {
             for (long k = 0; k < P->nth; ++k) {
                 wave[(ns * P->nth + k) * 2 + 0] = u[k * P->nr + j_e];
@@ -358,6 +402,13 @@ long FN(oracle_teuk_evolve)(const oracle_teuk* P, real* u, double dt, double dt_
     }
     free(work);
     return ns;
+}
+
+/* SSP-RK(3,3) (integrator 0) as above. */
+long FN(oracle_teuk_evolve)(const oracle_teuk* P, real* u, double dt, double dt_lo, long nsteps,
+                            long j_e, long every, real* wave, long max_samples)
+{
+    return FN(oracle_teuk_evolve_rk)(P, u, dt, dt_lo, nsteps, j_e, every, wave, max_samples, 0);
 }
 
 /* u' = lam u, u(0) = 1: nsteps SSP-RK3 steps of size dt; returns u as a
