@@ -100,6 +100,11 @@ def roofline(points_per_launch: float, t_launch: float, traffic):
             "algorithmic_bytes_per_launch": bytes_launch, "avg_launch_us": t_launch * 1e6}
 
 
+# SSP-RK(10,4) step: eight stages read u and write u (64 B per point), the
+# fifth reads u^(4) and u^n and writes two outputs (128 B), the last reads
+# u^(9) and q and writes (96 B): 736 B per point-step.
+RK104_BYTES_PER_POINT_STEP = 8 * 64 + 128 + 96
+
 # FP64 operations (FMA counted twice) and VALU instructions per point-stage of
 # the double-double stage kernel, counted in its gfx950 ISA (stages 2 and 3;
 # one lane per point): it is bound by FP64 instruction issue.
@@ -116,12 +121,12 @@ def dd_roofline(points_per_launch: float, t_launch: float, variant: str):
             "valu_issue_frac": instrs * points_per_launch / t_launch / VALU_ISSUE_PER_S}
 
 
-def solver_config(T, wl, weights, total_steps, workgroups=0, every=None, state="fp64"):
+def solver_config(T, wl, weights, total_steps, workgroups=0, every=None, state="fp64", integrator="rk3"):
     every = wl.every if every is None else every
     return T.make_config(s=wl.s, m=wl.m, a=wl.a, nr=wl.nr, ntheta=wl.nth, x_min=wl.x_min, x_max=wl.x_max,
                          M=wl.M, dt=0.0, cfl=0.5, weight_prec=weights, x_extract=wl.x_e, extract_every=every,
                          max_samples=total_steps // every + 1 if every > 0 else 0, workgroups=workgroups,
-                         state=state)
+                         state=state, integrator=integrator)
 
 
 # ----------------------------------------------------------------------------- C2: one solve
@@ -144,12 +149,13 @@ def bench_single(args, torch, T, W):
         log(f"copy probe: {n * 8} bytes read and written per copy")
         del src, dst
 
-    def run(wp, state="fp64", nsteps=None, nwarm=None):
+    def run(wp, state="fp64", nsteps=None, nwarm=None, integrator="rk3", every=None):
         """Warm up, then time `steps` steps with HIP events on the solver's
         stream.  Returns (seconds, wall seconds, info, waveform samples)."""
         nsteps = steps if nsteps is None else nsteps
         nwarm = warmup if nwarm is None else nwarm
-        sv = T.Solver(solver_config(T, wl, wp, nwarm + nsteps, args.workgroups, state=state), stream=stream)
+        sv = T.Solver(solver_config(T, wl, wp, nwarm + nsteps, args.workgroups, state=state,
+                                    integrator=integrator, every=every), stream=stream)
         sv.set_initial(u0)
         log(f"{state}/{wp}: warmup {nwarm} steps")
         sv.step(nwarm)
@@ -194,6 +200,27 @@ def bench_single(args, torch, T, W):
             err = float(np.linalg.norm(wave_w - wave) / np.linalg.norm(wave))
             mixed[wp] = {"value": pu / sec_w, "speedup_vs_fp64": gpu_s / sec_w, "waveform_rel_l2_vs_fp64": err}
         out["mixed_precision"] = mixed
+    if weights == "fp64" and not args.no_rk104:
+        # SSP-RK(10,4) (Sec. 3.2) over the same simulated time: its default step
+        # is 6x the SSP-RK(3,3) step (SSP coefficients 6 and 1), ten stages per
+        # step.  Waveforms compared at common sample times (every 5th step of
+        # SSP-RK(10,4) = every 30th of SSP-RK(3,3)).
+        n4, w4 = max(steps // 6, 1), warmup // 6
+        sec4, _, info4, wave4 = run("fp64", nsteps=n4, nwarm=w4, integrator="rk104", every=5)
+        ref = wave[::3][: wave4.shape[0]]
+        m = min(ref.shape[0], wave4.shape[0])
+        stages = 10 * n4
+        t_stage = sec4 / stages
+        out["rk104"] = {
+            "steps": n4, "warmup": w4, "dt": info4.dt, "ms_per_step": sec4 / n4 * 1e3,
+            "value": wl.points * stages / sec4, "unit": "point-updates/s",
+            "simulated_time_per_s_vs_rk3": (n4 * info4.dt / sec4) / (steps * info.dt / gpu_s),
+            "waveform_rel_l2_vs_rk3": float(np.linalg.norm(wave4[:m] - ref[:m]) / np.linalg.norm(ref[:m])),
+            "hbm": {"bytes_per_point_step": RK104_BYTES_PER_POINT_STEP,
+                    "achieved_GBs": RK104_BYTES_PER_POINT_STEP * wl.points * n4 / sec4 / 1e9,
+                    "frac": RK104_BYTES_PER_POINT_STEP * wl.points * n4 / sec4 / 1e9 / HBM_PEAK_GBS,
+                    "avg_launch_us": t_stage * 1e6},
+        }
     if weights == "fp64" and args.quad_steps > 0:
         # The paper's own experiment (Sec. 3.1.3): a high-precision state with
         # weights in that precision, against the same state with weights in
@@ -523,6 +550,7 @@ def main():
     ap.add_argument("--rows-per-tile", type=int, default=0, help="C4/C5: theta rows per group tile (0: 8)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/FP16/BF16-weight runs")
+    ap.add_argument("--no-rk104", action="store_true", help="C2: skip the SSP-RK(10,4) run")
     ap.add_argument("--quad-steps", type=int, default=1000,
                     help="C2: steps of the double-double state runs (0: skip them)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)

@@ -98,6 +98,18 @@ enum { TEUK_W_FP64 = 0, TEUK_W_FP32 = 1, TEUK_W_FP16 = 2, TEUK_W_BF16 = 3,
  * UNSUPPORTED); it is not a group member. */
 enum { TEUK_S_FP64 = 0, TEUK_S_DD = 1 };
 
+/* Time integrator (Sec. 3.2), each step a sequence of fused stage kernels.
+ *   TEUK_RK_SSP33:  SSP-RK(3,3) in Shu-Osher form, SSP coefficient C = 1.
+ *   TEUK_RK_SSP104: the low-storage ten-stage fourth-order SSP-RK(10,4), C = 6:
+ *       u(1) = u^n + dt/6 F(u^n), u(i) = u(i-1) + dt/6 F(u(i-1)) for i = 2..4,
+ *       u(5) = 3/5 u^n + 2/5 u(4) + 1/15 dt F(u(4)), u(i) as before for i = 6..9,
+ *       u^{n+1} = 1/25 u^n + 9/25 u(4) + 3/5 u(9) + 3/50 dt F(u(4)) + 1/10 dt F(u(9)),
+ *     run in three state buffers: the fifth stage also writes
+ *     q = 1/25 u^n + 9/25 (u(4) + dt/6 F(u(4))) over u^n, and the last is
+ *     u^{n+1} = q + 3/5 (u(9) + dt/6 F(u(9))).  FP64 state, single solves only
+ *     (UNSUPPORTED with TEUK_S_DD or in a group). */
+enum { TEUK_RK_SSP33 = 0, TEUK_RK_SSP104 = 1 };
+
 /* What teuk_extract returns. */
 enum {
     TEUK_X_STATE = 0,     /* [4][ntheta][nr] current state u^n                        */
@@ -134,11 +146,12 @@ typedef struct {
     int32_t max_samples;     /* waveform ring-buffer capacity (samples)                */
     int32_t workgroups;      /* stage-kernel workgroups; 0 = all the GPU holds at once */
     int32_t state_prec;      /* TEUK_S_*                                              */
-    int32_t reserved;        /* must be 0                                             */
+    int32_t integrator;      /* TEUK_RK_*                                             */
     double M;                /* black-hole mass (> 0)                                  */
     double a;                /* spin, 0 <= a <= M                                      */
     double x_min, x_max;     /* radial range of x (r_* or rho; x_min < x_max)          */
-    double dt;               /* > 0: time step used as given; <= 0: cfl * stability bound */
+    double dt;               /* > 0: time step used as given; <= 0: cfl * C * stability bound,
+                                C the integrator's SSP coefficient (1 or 6)            */
     double cfl;              /* used when dt <= 0 (e.g. 0.5)                           */
     double weno_eps;         /* epsilon of the WENO weights (e.g. 1e-6), in [1e-30, 1e30]
                                 (normal in FP32, so reduced-precision weights stay finite) */
@@ -167,7 +180,8 @@ typedef struct {
     double dt_bound;         /* stability bound (cfl = 1), from the device reduction   */
 } teuk_info_t;
 
-/* Fill cfg with defaults: ABI version, M = 1, chart T, FP64 state and weights, cfl 0.5,
+/* Fill cfg with defaults: ABI version, M = 1, chart T, FP64 state and weights,
+ * SSP-RK(3,3), cfl 0.5,
  * eps 1e-6, dt from the bound, no waveform.  Sizes and ranges must still be set. */
 void teuk_default_config(teuk_config* cfg);
 
@@ -181,7 +195,8 @@ size_t teuk_footprint_bytes(const teuk_config* cfg);
  * host in FP64 (Sec. 2.1-2.3), upload them, and compute the stability bound by
  * a device max-reduction over every grid point (Sec. 3.2, dt <= C dt_FE):
  *     dt_bound = 1 / max( b/dx + sqrt(4 A~thth/dtheta^2 + |B~th|/dtheta + |C~|) ).
- * If cfg->dt <= 0 the step is cfl * dt_bound.  ctx may be NULL.  On success
+ * If cfg->dt <= 0 the step is cfl * C * dt_bound (C = 1 for SSP-RK(3,3), 6 for
+ * SSP-RK(10,4)).  ctx may be NULL.  On success
  * *out owns its device buffers (or lives in ctx->workspace, which the caller
  * keeps alive until teuk_destroy and which the library never frees).
  * Errors: INVALID_ARG, OUT_OF_MEMORY (allocation, or workspace too small),
@@ -198,8 +213,10 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
  * Errors: INVALID_ARG (NULL), NONFINITE, DEVICE. */
 teuk_status teuk_set_initial(teuk_solver* h, const double* u, int32_t on_device);
 
-/* Advance nsteps SSP-RK(3,3) steps (Sec. 3.2), each three fused stage kernels
+/* Advance nsteps steps of the configured integrator (Sec. 3.2).  SSP-RK(3,3)
+ * is three fused stage kernels
  *     u1 = u + dt F(u);  u2 = 3/4 u + 1/4 (u1 + dt F(u1));  u = 1/3 u + 2/3 (u2 + dt F(u2)),
+ * SSP-RK(10,4) ten (see TEUK_RK_SSP104),
  * with F(u) = -(M d_x u + L u + A u) of eq. evln and WENO5 radial derivatives
  * (Sec. 3.1.2).  A waveform sample is taken after every extract_every-th step.
  * Asynchronous on the solver's stream.  nsteps = 0 is a no-op.

@@ -147,7 +147,7 @@ bool validate(const teuk_config* c, std::string& err)
     if ((long long)c->nr * c->ntheta > (1LL << 34)) { err = "nr * ntheta too large"; return false; }
     if (c->weight_prec < TEUK_W_FP64 || c->weight_prec > TEUK_W_DD) { err = "weight_prec must be a TEUK_W_* value"; return false; }
     if (c->state_prec != TEUK_S_FP64 && c->state_prec != TEUK_S_DD) { err = "state_prec must be a TEUK_S_* value"; return false; }
-    if (c->reserved != 0) { err = "reserved must be 0"; return false; }
+    if (c->integrator != TEUK_RK_SSP33 && c->integrator != TEUK_RK_SSP104) { err = "integrator must be a TEUK_RK_* value"; return false; }
     if (c->weight_prec == TEUK_W_DD && c->state_prec != TEUK_S_DD) { err = "TEUK_W_DD weights need the TEUK_S_DD state"; return false; }
     if (!(c->M > 0.0) || !std::isfinite(c->M)) { err = "M must be positive and finite"; return false; }
     if (!(c->a >= 0.0) || !(c->a <= c->M)) { err = "spin a must satisfy 0 <= a <= M"; return false; }
@@ -288,6 +288,8 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     if (dd && (chartH || (cfg->weight_prec != TEUK_W_DD && cfg->weight_prec != TEUK_W_FP64)))
         return fail(nullptr, TEUK_ERR_UNSUPPORTED,
                     "double-double state: tortoise chart with TEUK_W_DD or TEUK_W_FP64 weights only");
+    if (dd && cfg->integrator != TEUK_RK_SSP33)
+        return fail(nullptr, TEUK_ERR_UNSUPPORTED, "double-double state: SSP-RK(3,3) only");
     std::vector<double> rtab, ttab, ctab, dtab;
     DDScalars ddk{};
     if (chartH ? !build_tables_H(*cfg, ctab, err) : !build_tables(*cfg, rtab, ttab, err))
@@ -381,7 +383,8 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
         return fail(nullptr, TEUK_ERR_NONFINITE, "stability bound is not finite");
     }
     h->dt_bound = 1.0 / mx;
-    h->dt = cfg->dt > 0.0 ? cfg->dt : cfg->cfl * h->dt_bound;
+    const double ssp_c = cfg->integrator == TEUK_RK_SSP104 ? 6.0 : 1.0;   // SSP coefficient (Sec. 3.2)
+    h->dt = cfg->dt > 0.0 ? cfg->dt : cfg->cfl * ssp_c * h->dt_bound;
     *out = h;
     return TEUK_OK;
 }
@@ -494,11 +497,74 @@ static StageArgs stage_args(const teuk_solver* h)
     a.dt = h->dt;
     a.ca = 0.0;
     a.cb = 1.0;
+    a.out2 = nullptr;
+    a.ca2 = a.cb2 = 0.0;
     a.eps = c.weno_eps;
     a.parity = ((c.m + c.s) % 2 != 0) ? -1.0 : 1.0;
     a.uk = a.un = h->u[0];
     a.out = h->u[1];
     return a;
+}
+
+// One SSP-RK(10,4) step (Sec. 3.2) in the three state buffers U = u^n,
+// A = u[1], B = u[2]: stages 1-4 ping-pong U -> A -> B -> A -> B (= u(4)) with
+// out = u + dt/6 F(u); stage 5 reads B and u^n and writes u(5) = 3/5 u^n + 2/5 v
+// into A and q = 1/25 u^n + 9/25 v over U (v = u(4) + dt/6 F(u(4)), u^n read at
+// the own point only); stages 6-9 ping-pong A -> B -> A -> B -> A (= u(9));
+// stage 10 writes u^{n+1} = q + 3/5 (u(9) + dt/6 F(u(9))) over U.
+static int rk104_step(teuk_solver* h, StageArgs a)
+{
+    const teuk_config& c = h->cfg;
+    double* U = h->u[0];
+    double* AB[2] = {h->u[1], h->u[2]};
+    a.dt = h->dt / 6.0;
+    a.segs = h->segs[0];
+    a.grid = h->nstrips * h->segs[0];
+    a.ca = 0.0;
+    a.cb = 1.0;
+    int e = 0;
+    const double* in = U;
+    for (int st = 1; st <= 4 && !e; ++st) {
+        a.uk = in;
+        a.un = in;
+        a.out = AB[(st - 1) & 1];   // A, B, A, B
+        e = launch_stage(a, 1, c.weight_prec, c.chart, h->stream);
+        in = a.out;
+    }
+    if (e) return e;
+    a.segs = h->segs[1];
+    a.grid = h->nstrips * h->segs[1];
+    a.uk = AB[1];
+    a.un = U;
+    a.out = AB[0];
+    a.ca = 3.0 / 5.0;
+    a.cb = 2.0 / 5.0;
+    a.out2 = U;
+    a.ca2 = 1.0 / 25.0;
+    a.cb2 = 9.0 / 25.0;
+    e = launch_stage(a, 4, c.weight_prec, c.chart, h->stream);
+    a.out2 = nullptr;
+    a.segs = h->segs[0];
+    a.grid = h->nstrips * h->segs[0];
+    a.ca = 0.0;
+    a.cb = 1.0;
+    in = AB[0];
+    for (int st = 6; st <= 9 && !e; ++st) {
+        a.uk = in;
+        a.un = in;
+        a.out = AB[(st - 5) & 1];   // B, A, B, A
+        e = launch_stage(a, 1, c.weight_prec, c.chart, h->stream);
+        in = a.out;
+    }
+    if (e) return e;
+    a.segs = h->segs[1];
+    a.grid = h->nstrips * h->segs[1];
+    a.uk = in;                 // u(9), in A
+    a.un = U;                  // q
+    a.out = U;
+    a.ca = 1.0;
+    a.cb = 3.0 / 5.0;
+    return launch_stage(a, 2, c.weight_prec, c.chart, h->stream);
 }
 
 teuk_status teuk_step(teuk_solver* h, int64_t nsteps)
@@ -520,6 +586,18 @@ teuk_status teuk_step(teuk_solver* h, int64_t nsteps)
         return TEUK_OK;
     }
     StageArgs a = stage_args(h);
+    if (c.integrator == TEUK_RK_SSP104) {
+        for (int64_t n = 0; n < nsteps; ++n) {
+            const int e = rk104_step(h, a);
+            if (e) return hip_fail(h, e, "stage launch");
+            ++h->steps;
+            if (c.extract_every > 0 && h->steps % c.extract_every == 0) {
+                teuk_status st = record_sample(h);
+                if (st != TEUK_OK) return st;
+            }
+        }
+        return TEUK_OK;
+    }
     for (int64_t n = 0; n < nsteps; ++n) {
         // u1 = u + dt F(u)
         a.uk = h->u[0]; a.un = h->u[0]; a.out = h->u[1]; a.ca = 0.0; a.cb = 1.0; a.segs = h->segs[0]; a.grid = h->nstrips * h->segs[0];
@@ -817,6 +895,8 @@ teuk_status teuk_group_add(teuk_group* g, teuk_solver* h)
     if (!g) return gfail(nullptr, TEUK_ERR_INVALID_ARG, "group is NULL");
     if (!h) return gfail(g, TEUK_ERR_INVALID_ARG, "solver is NULL");
     if (h->dd) return gfail(g, TEUK_ERR_UNSUPPORTED, "double-double solvers are not group members");
+    if (h->cfg.integrator != TEUK_RK_SSP33)
+        return gfail(g, TEUK_ERR_UNSUPPORTED, "group members step with SSP-RK(3,3)");
     if (h->group) return gfail(g, TEUK_ERR_INVALID_ARG, "solver already belongs to a group");
     if (h->stream != g->stream) return gfail(g, TEUK_ERR_INVALID_ARG, "solver and group use different streams");
     if (h->device != g->device) return gfail(g, TEUK_ERR_INVALID_ARG, "solver and group are on different devices");

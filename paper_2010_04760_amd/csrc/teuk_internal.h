@@ -41,6 +41,8 @@ struct StageArgs {
     double inv6dx;         // 1 / (6 dx): candidate fluxes are carried times 6
     double ih1, ih2;       // 1/(2 dtheta), 1/dtheta^2
     double dt, ca, cb;     // out = ca un + cb (uk + dt F)
+    double* out2;          // dual stage: second output ca2 un + cb2 (uk + dt F); may alias un
+    double ca2, cb2;
     double eps, parity;    // WENO epsilon, (-1)^(m+s)
 };
 
@@ -65,7 +67,8 @@ struct DDStageArgs {
 int stage_grid(int weight_prec, bool first, int chart);
 
 // Launchers (all asynchronous on `stream`; they return the hipError_t as int).
-// stage: 1 = first SSP stage, 2/3 = later stages, 0 = write F(u) only.
+// stage: 1 = out = u + dt F(u), 2/3 = later stages (ca u^n + cb (u^(k) + dt F)),
+// 4 = dual (out and out2 from the same v = u^(k) + dt F), 0 = write F(u) only.
 int launch_stage(const StageArgs& a, int stage, int weight_prec, int chart, void* stream);
 // One stage (1, 2 or 3) of several solves in one launch of `grid` workgroups:
 // args[0..nmem) are the members' stage arguments (segs = theta segments per

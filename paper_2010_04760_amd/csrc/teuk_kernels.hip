@@ -39,6 +39,10 @@ constexpr int kRow = kWave + 5;   // staged positions j0-3 .. j0+65
 constexpr int kStageFirst = 0;    // out = u + dt F(u)
 constexpr int kStageLater = 1;    // out = ca u^n + cb (u^(k) + dt F(u^(k)))
 constexpr int kRhsOnly = 2;       // out = F(u)
+constexpr int kStageDual = 3;     // v = u^(k) + dt F(u^(k)): out = ca u^n + cb v, out2 = ca2 u^n + cb2 v
+// stage modes that read u^n at the own point
+template <int kMode>
+constexpr bool reads_un() { return kMode == kStageLater || kMode == kStageDual; }
 
 // Radial chart (TEUK_CHART_*).
 constexpr int kChartT = TEUK_CHART_TORTOISE;
@@ -340,7 +344,7 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
     const unsigned oc = (unsigned)jc * 8u;                                 // own point
     const bool halo = l < 5;
     const double* __restrict__ ukp[4] = {A.uk, A.uk + P, A.uk + 2 * P, A.uk + 3 * P};
-    const double* unp[4] = {A.un, A.un + P, A.un + 2 * P, A.un + 3 * P};   // read in kStageLater only
+    const double* unp[4] = {A.un, A.un + P, A.un + 2 * P, A.un + 3 * P};   // read where reads_un<kMode>()
     double* outp[4] = {A.out, A.out + P, A.out + 2 * P, A.out + 3 * P};
 
     double rt[kNRT];
@@ -416,7 +420,7 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
         const bool pre = i + 2 < nst;
         if (pre) load_row(k + 2 * dir);
         double n0, n1, n2, n3;
-        if (kMode == kStageLater) {
+        if (reads_un<kMode>()) {
             n0 = ldb(unp[0] + row, oc);
             n1 = ldb(unp[1] + row, oc);
             n2 = ldb(unp[2] + row, oc);
@@ -519,11 +523,22 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
                 stb(outp[1] + row, oc, phI + A.dt * FphI);
                 stb(outp[2] + row, oc, piR + A.dt * FpiR);
                 stb(outp[3] + row, oc, piI + A.dt * FpiI);
-            } else {
+            } else if (kMode == kStageLater) {
                 stb(outp[0] + row, oc, A.ca * n0 + A.cb * (phR + A.dt * FphR));
                 stb(outp[1] + row, oc, A.ca * n1 + A.cb * (phI + A.dt * FphI));
                 stb(outp[2] + row, oc, A.ca * n2 + A.cb * (piR + A.dt * FpiR));
                 stb(outp[3] + row, oc, A.ca * n3 + A.cb * (piI + A.dt * FpiI));
+            } else {
+                const double v0 = phR + A.dt * FphR, v1 = phI + A.dt * FphI;
+                const double v2 = piR + A.dt * FpiR, v3 = piI + A.dt * FpiI;
+                stb(outp[0] + row, oc, A.ca * n0 + A.cb * v0);
+                stb(outp[1] + row, oc, A.ca * n1 + A.cb * v1);
+                stb(outp[2] + row, oc, A.ca * n2 + A.cb * v2);
+                stb(outp[3] + row, oc, A.ca * n3 + A.cb * v3);
+                stb(A.out2 + row, oc, A.ca2 * n0 + A.cb2 * v0);
+                stb(A.out2 + P + row, oc, A.ca2 * n1 + A.cb2 * v1);
+                stb(A.out2 + 2 * P + row, oc, A.ca2 * n2 + A.cb2 * v2);
+                stb(A.out2 + 3 * P + row, oc, A.ca2 * n3 + A.cb2 * v3);
             }
         }
         bhR = phR;
@@ -618,14 +633,14 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
         const double cot = tt[kCot * nth + k];
         const double th = tt[kTh * nth + k];
         double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
-        if (kMode == kStageLater) {
+        if (reads_un<kMode>()) {
             n0 = ld_async(oc, unp[0] + row);
             n1 = ld_async(oc, unp[1] + row);
             n2 = ld_async(oc, unp[2] + row);
             n3 = ld_async(oc, unp[3] + row);
         }
         issue_row(i + 3);
-        constexpr int it = kMode == kStageLater ? 16 : 12;
+        constexpr int it = reads_un<kMode>() ? 16 : 12;
         if (i == 0) vm_wait<12 + it>();
         else vm_wait<2 * it>();
         const int b = i & (kRing - 1), bn = (i + 1) & (kRing - 1);
@@ -649,7 +664,7 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
         const double gR1 = __shfl_down(gR, 1);
         const double gI1 = __shfl_down(gI, 1);
 
-        if (kMode == kStageLater) vm_wait<12>(n0, n1, n2, n3);
+        if (reads_un<kMode>()) vm_wait<12>(n0, n1, n2, n3);
         if (active) {
             const double dPhR = (fR1 - fR) * A.inv6dx;
             const double dPhI = (fI1 - fI) * A.inv6dx;
@@ -677,11 +692,22 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
                 stb(outp[1] + row, oc, phI + A.dt * FphI);
                 stb(outp[2] + row, oc, piR + A.dt * FpiR);
                 stb(outp[3] + row, oc, piI + A.dt * FpiI);
-            } else {
+            } else if (kMode == kStageLater) {
                 stb(outp[0] + row, oc, A.ca * n0 + A.cb * (phR + A.dt * FphR));
                 stb(outp[1] + row, oc, A.ca * n1 + A.cb * (phI + A.dt * FphI));
                 stb(outp[2] + row, oc, A.ca * n2 + A.cb * (piR + A.dt * FpiR));
                 stb(outp[3] + row, oc, A.ca * n3 + A.cb * (piI + A.dt * FpiI));
+            } else {
+                const double v0 = phR + A.dt * FphR, v1 = phI + A.dt * FphI;
+                const double v2 = piR + A.dt * FpiR, v3 = piI + A.dt * FpiI;
+                stb(outp[0] + row, oc, A.ca * n0 + A.cb * v0);
+                stb(outp[1] + row, oc, A.ca * n1 + A.cb * v1);
+                stb(outp[2] + row, oc, A.ca * n2 + A.cb * v2);
+                stb(outp[3] + row, oc, A.ca * n3 + A.cb * v3);
+                stb(A.out2 + row, oc, A.ca2 * n0 + A.cb2 * v0);
+                stb(A.out2 + P + row, oc, A.ca2 * n1 + A.cb2 * v1);
+                stb(A.out2 + 2 * P + row, oc, A.ca2 * n2 + A.cb2 * v2);
+                stb(A.out2 + 3 * P + row, oc, A.ca2 * n3 + A.cb2 * v3);
             }
         }
         bhR = phR;
@@ -942,6 +968,8 @@ int launch_stage(const StageArgs& a, int stage, int weight_prec, int chart, void
             hipLaunchKernelGGL((stage_kernel<W, kStageFirst, C>), grid, block, 0, st, a);     \
         else if (stage == 0)                                                                  \
             hipLaunchKernelGGL((stage_kernel<W, kRhsOnly, C>), grid, block, 0, st, a);        \
+        else if (stage == 4)                                                                  \
+            hipLaunchKernelGGL((stage_kernel<W, kStageDual, C>), grid, block, 0, st, a);      \
         else                                                                                  \
             hipLaunchKernelGGL((stage_kernel<W, kStageLater, C>), grid, block, 0, st, a);     \
         done = true;                                                                          \

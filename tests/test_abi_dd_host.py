@@ -56,8 +56,11 @@ def test_dd_validation():
     assert T.teuk_footprint_bytes(T.make_config(**base, weight_prec="dd")) == 0
     assert T.teuk_footprint_bytes(T.make_config(**base, state=2)) == 0
     c = T.make_config(**base)
-    c.reserved = 1
+    c.integrator = 2
     assert T.teuk_footprint_bytes(c) == 0
+    with pytest.raises(T.TeukError) as ei:
+        T.teuk_create(T.make_config(**base, state="dd", weight_prec="dd", integrator="rk104"))
+    assert ei.value.status == T.TEUK_ERR_UNSUPPORTED
     # valid but not offered: reduced-precision weights or the hyperboloidal chart
     for kw in (dict(weight_prec="fp32"), dict(weight_prec="bf16")):
         with pytest.raises(T.TeukError) as ei:
