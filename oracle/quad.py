@@ -239,7 +239,8 @@ class TeukOracleQ:
             dth = split(mp.pi / prob.nth)
         self.dx_pair, self.dth_pair = dx, dth
         self._s = S._OracleTeuk(self.nr, self.nth, dx[0], dx[1], dth[0], dth[1], prob.eps, prob.parity(),
-                                1 if weights == "fp64" else 0, *[self._q[n].addr for n in self.NAMES])
+                                1 if weights == "fp64" else 0, S.SCHEMES[prob.scheme], prob.ko_sigma,
+                                *[self._q[n].addr for n in self.NAMES])
 
     def shape(self):
         return (4, self.nth, self.nr)

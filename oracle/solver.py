@@ -53,7 +53,8 @@ class _OracleTeuk(ctypes.Structure):
     _fields_ = [("nr", ctypes.c_long), ("nth", ctypes.c_long),
                 ("dx", ctypes.c_double), ("dx_lo", ctypes.c_double),
                 ("dth", ctypes.c_double), ("dth_lo", ctypes.c_double), ("eps", ctypes.c_double),
-                ("parity", ctypes.c_double), ("wmode", ctypes.c_int)] + [
+                ("parity", ctypes.c_double), ("wmode", ctypes.c_int), ("scheme", ctypes.c_int),
+                ("ko_sigma", ctypes.c_double)] + [
                 (n, ctypes.c_void_p) for n in ("lam1", "lam2", "m3r", "m3i", "btr", "bti", "cr", "ci", "ath", "bth")]
 
 
@@ -91,6 +92,16 @@ def lib() -> ctypes.CDLL:
                                       ctypes.c_double, ctypes.c_double, ctypes.c_long, ctypes.c_double,
                                       ctypes.c_int]
         L.oracle_teuk_rhs.argtypes = [ctypes.POINTER(_OracleTeuk), _dp, _dp]
+        for fn in ("oracle_weno3_weights_plus", "oracle_weno3_weights_minus"):
+            getattr(L, fn).argtypes = [_dp, ctypes.c_double, _dp]
+        for fn in ("oracle_weno3_flux_plus", "oracle_weno3_flux_minus"):
+            getattr(L, fn).argtypes = [_dp, ctypes.c_double]
+            getattr(L, fn).restype = ctypes.c_double
+        L.oracle_radial_d.argtypes = [_dp, ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_int]
+        L.oracle_radial_d.restype = ctypes.c_double
+        L.oracle_advect1d_scheme.argtypes = [_dp, ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_long, ctypes.c_double, ctypes.c_int, ctypes.c_double]
         L.oracle_teuk_evolve.argtypes = [ctypes.POINTER(_OracleTeuk), _dp, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_long, ctypes.c_long, ctypes.c_long, _dp, ctypes.c_long]
         L.oracle_teuk_evolve.restype = ctypes.c_long
@@ -143,6 +154,35 @@ def derivative(p_padded, j, dx, side, eps=1e-6):
     pp = ctypes.cast(base, _dp)
     fn = lib().oracle_dplus if side > 0 else lib().oracle_dminus
     return fn(pp, j, dx, 0.0, eps, 0)
+
+
+SCHEMES = {"weno5": 0, "weno3": 1, "fd6ko8": 2}
+
+
+def weno3_weights(f3, side, eps=1e-6):
+    """omega_1, omega_2 of f^+_{j+1/2} (side=+1, f_{j-1..j+1}) or f^- (side=-1, f_{j..j+2})."""
+    f = np.ascontiguousarray(f3, dtype=np.float64)
+    w = np.zeros(2)
+    (lib().oracle_weno3_weights_plus if side > 0 else lib().oracle_weno3_weights_minus)(ptr(f), eps, ptr(w))
+    return w
+
+
+def weno3_flux(f3, side, eps=1e-6):
+    f = np.ascontiguousarray(f3, dtype=np.float64)
+    return (lib().oracle_weno3_flux_plus if side > 0 else lib().oracle_weno3_flux_minus)(ptr(f), eps)
+
+
+def radial_derivative(row, j, dx, speed, scheme, eps=1e-6):
+    """Radial derivative at index j of `row` (entries j-4 .. j+4 must exist)."""
+    p = np.ascontiguousarray(row, dtype=np.float64)
+    return lib().oracle_radial_d(ptr(p), j, speed, dx, 0.0, eps, SCHEMES[scheme])
+
+
+def advect1d_scheme(u0, dx, speed, dt, nsteps, scheme, sigma=0.01, eps=1e-6):
+    """Periodic u_t + speed u_x = 0 by the chosen radial scheme and SSP-RK3."""
+    u = np.ascontiguousarray(u0, dtype=np.float64).copy()
+    lib().oracle_advect1d_scheme(ptr(u), u.size, dx, speed, dt, nsteps, eps, SCHEMES[scheme], sigma)
+    return u
 
 
 def advect1d(u0, dx, speed, dt, nsteps, eps=1e-6):
@@ -199,6 +239,8 @@ class Problem:
     eps: float = 1e-6
     chart: str = "T"
     S: float = 20.0
+    scheme: str = "weno5"        # radial scheme: "weno5", "weno3" or "fd6ko8" (Sec. 3.1)
+    ko_sigma: float = 0.01       # Kreiss-Oliger sigma (fd6ko8)
 
     @property
     def dx(self):
@@ -248,6 +290,7 @@ class TeukOracle:
                 "ath": f(c["Ath"]), "bth": f(c["Bth"]),
             }
         self._s = _OracleTeuk(prob.nr, prob.nth, prob.dx, 0.0, prob.dth, 0.0, prob.eps, prob.parity(), 0,
+                              SCHEMES[prob.scheme], prob.ko_sigma,
                               *[self.tab[n].ctypes.data for n in ("lam1", "lam2", "m3r", "m3i", "btr",
                                                                   "bti", "cr", "ci", "ath", "bth")])
 

@@ -28,6 +28,17 @@
  * Ghost values: three cells per radial side copied from the end point, and in
  * theta one cell per pole equal to (-1)^(m+s) times the mirrored cell.
  *
+ * Radial schemes (Sec. 3.1): WENO5 (scheme 0, above), the third-order WENO of
+ * Sec. 3.1.2 (scheme 1: two candidate stencils, IS_1 = (f_j - f_{j-1})^2,
+ * IS_2 = (f_{j+1} - f_j)^2, linear weights 1/3, 2/3; the printed f^- flux is
+ * read as the mirror image of f^+ about j + 1/2, i.e. built from
+ * f_j, f_{j+1}, f_{j+2}), and the sixth-order centred difference with
+ * eighth-order Kreiss-Oliger dissipation of Sec. 3.1.1 (scheme 2:
+ * D u = (u_{j+3} - 9 u_{j+2} + 45 u_{j+1} - 45 u_{j-1} + 9 u_{j-2} - u_{j-3})/(60 dx),
+ * and every plane's right-hand side receives -Q u with
+ * Q = sigma dx^7 (D_+ D_-)^4 / 256 = sigma delta^8 / (256 dx), the sign that
+ * makes it dissipative; four ghost cells per side).
+ *
  * Weight precision (Sec. 3.1.3).  wmode 0 forms IS_k, alpha_k and omega_k in
  * `real` exactly as printed.  wmode 1 is the paper's mixed variant: the five
  * stencil values are rounded to double, IS_k, alpha_k, omega_0 and omega_1 are
@@ -186,6 +197,82 @@ static real upwind_d(const real* p, long j, real speed, real dx, double eps, int
     return speed < R(0) ? dminus(p, j, dx, eps, wmode) : dplus(p, j, dx, eps, wmode);
 }
 
+/* ---------------------------------------------------------------- WENO3 (Sec. 3.1.2) */
+
+/* f = f_{j-1..j+1}: weights of f^+_{j+1/2}. */
+void FN(oracle_weno3_weights_plus)(const real* f, double eps, real w[2])
+{
+    const real e = R(eps);
+    real IS1 = sq(f[1] - f[0]);
+    real IS2 = sq(f[2] - f[1]);
+    real a1 = R(1) / R(3) * sq(R(1) / (e + IS1));
+    real a2 = R(2) / R(3) * sq(R(1) / (e + IS2));
+    w[0] = a1 / (a1 + a2);
+    w[1] = a2 / (a1 + a2);
+}
+
+real FN(oracle_weno3_flux_plus)(const real* f, double eps)
+{
+    real w[2];
+    FN(oracle_weno3_weights_plus)(f, eps, w);
+    return w[0] * (R(3) / R(2) * f[1] - R(1) / R(2) * f[0]) + w[1] * (R(1) / R(2) * f[1] + R(1) / R(2) * f[2]);
+}
+
+/* g = f_{j..j+2}: weights of f^-_{j+1/2}, the mirror image of f^+. */
+void FN(oracle_weno3_weights_minus)(const real* g, double eps, real w[2])
+{
+    const real e = R(eps);
+    real IS1 = sq(g[2] - g[1]);
+    real IS2 = sq(g[1] - g[0]);
+    real a1 = R(1) / R(3) * sq(R(1) / (e + IS1));
+    real a2 = R(2) / R(3) * sq(R(1) / (e + IS2));
+    w[0] = a1 / (a1 + a2);
+    w[1] = a2 / (a1 + a2);
+}
+
+real FN(oracle_weno3_flux_minus)(const real* g, double eps)
+{
+    real w[2];
+    FN(oracle_weno3_weights_minus)(g, eps, w);
+    return w[0] * (R(3) / R(2) * g[1] - R(1) / R(2) * g[2]) + w[1] * (R(1) / R(2) * g[1] + R(1) / R(2) * g[0]);
+}
+
+/* ---------------------------------------------------------------- FD6 + KO8 (Sec. 3.1.1) */
+
+static real fd6(const real* p, long j, real dx)
+{
+    return (p[j + 3] - R(9) * p[j + 2] + R(45) * p[j + 1] - R(45) * p[j - 1] + R(9) * p[j - 2] - p[j - 3]) /
+           (R(60) * dx);
+}
+
+/* Q u at j = sigma dx^7 (D_+ D_-)^4 u / 256 = sigma delta^8 u / (256 dx). */
+static real ko8(const real* p, long j, real dx, real sigma)
+{
+    const real d8 = p[j - 4] - R(8) * p[j - 3] + R(28) * p[j - 2] - R(56) * p[j - 1] + R(70) * p[j] -
+                    R(56) * p[j + 1] + R(28) * p[j + 2] - R(8) * p[j + 3] + p[j + 4];
+    return sigma * d8 / (R(256) * dx);
+}
+
+/* Radial derivative of a padded row at j by the chosen scheme; speed picks
+ * the upwind side of the WENO schemes. */
+static real radial_d(const real* p, long j, real speed, real dx, double eps, int wmode, int scheme)
+{
+    if (scheme == 2) return fd6(p, j, dx);
+    if (scheme == 1) {
+        if (speed < R(0))
+            return (FN(oracle_weno3_flux_minus)(p + j, eps) - FN(oracle_weno3_flux_minus)(p + j - 1, eps)) / dx;
+        return (FN(oracle_weno3_flux_plus)(p + j - 1, eps) - FN(oracle_weno3_flux_plus)(p + j - 2, eps)) / dx;
+    }
+    return upwind_d(p, j, speed, dx, eps, wmode);
+}
+
+/* The radial derivative at point j of a row padded by four cells per side
+ * (pairs for dx), for tests of the schemes. */
+real FN(oracle_radial_d)(const real* p, long j, double speed, double dx, double dx_lo, double eps, int scheme)
+{
+    return radial_d(p, j, R(speed), pair(dx, dx_lo), eps, 0, scheme);
+}
+
 /* ---------------------------------------------------------------- SSP-RK(3,3) (Sec. 3.2) */
 
 typedef void (*oracle_rhs_fn)(const real* u, real* F, void* ctx);
@@ -259,7 +346,8 @@ typedef struct {
     long n;
     real dx, speed;
     double eps;
-    int wmode;
+    int wmode, scheme;
+    real sigma;
 } oracle_advect;
 
 /* u_t + speed u_x = 0 on a periodic grid: F = -speed * D u. */
@@ -267,18 +355,31 @@ static void advect_rhs(const real* u, real* F, void* vctx)
 {
     const oracle_advect* A = (const oracle_advect*)vctx;
     long n = A->n;
-    real* p = (real*)malloc((size_t)(n + 6) * sizeof(real));
-    for (long i = 0; i < n + 6; ++i) p[i] = u[((i - 3) % n + n) % n];
-    for (long j = 0; j < n; ++j) F[j] = -A->speed * upwind_d(p + 3, j, A->speed, A->dx, A->eps, A->wmode);
+    real* p = (real*)malloc((size_t)(n + 8) * sizeof(real));
+    for (long i = 0; i < n + 8; ++i) p[i] = u[((i - 4) % n + n) % n];
+    for (long j = 0; j < n; ++j) {
+        F[j] = -A->speed * radial_d(p + 4, j, A->speed, A->dx, A->eps, A->wmode, A->scheme);
+        if (A->scheme == 2) F[j] -= ko8(p + 4, j, A->dx, A->sigma);
+    }
     free(p);
 }
 
 void FN(oracle_advect1d)(real* u, long n, double dx, double dx_lo, double speed, double dt, double dt_lo,
                          long nsteps, double eps, int wmode)
 {
-    oracle_advect A = {n, pair(dx, dx_lo), R(speed), eps, wmode};
+    oracle_advect A = {n, pair(dx, dx_lo), R(speed), eps, wmode, 0, R(0)};
     real* work = (real*)malloc((size_t)(3 * n) * sizeof(real));
     for (long s = 0; s < nsteps; ++s) ssprk3_step(u, n, pair(dt, dt_lo), advect_rhs, &A, work);
+    free(work);
+}
+
+/* The same with a radial scheme (0 WENO5, 1 WENO3, 2 FD6 + KO8 with sigma). */
+void FN(oracle_advect1d_scheme)(real* u, long n, double dx, double speed, double dt, long nsteps, double eps,
+                                int scheme, double sigma)
+{
+    oracle_advect A = {n, R(dx), R(speed), eps, 0, scheme, R(sigma)};
+    real* work = (real*)malloc((size_t)(3 * n) * sizeof(real));
+    for (long s = 0; s < nsteps; ++s) ssprk3_step(u, n, R(dt), advect_rhs, &A, work);
     free(work);
 }
 
@@ -290,6 +391,8 @@ typedef struct {
     double eps;
     double parity;                   /* (-1)^(m+s) for the pole ghosts */
     int wmode;                       /* 0: weights in real; 1: mixed (double) */
+    int scheme;                      /* 0 WENO5, 1 WENO3, 2 FD6 + KO8 */
+    double ko_sigma;                 /* sigma of the Kreiss-Oliger term (scheme 2) */
     /* per point, [nth][nr], radial index fastest */
     const real *lam1, *lam2;         /* speeds of the Phi rows and the pi rows */
     const real *m3r, *m3i;           /* m3 = m31 - i m32 */
@@ -298,15 +401,16 @@ typedef struct {
     const real *ath, *bth;           /* A~thth, B~th */
 } oracle_teuk;
 
-/* Copy row k of a plane into p[0 .. nr+5] with three end-point copies per side. */
+/* Copy row k of a plane into p[0 .. nr+7] with four end-point copies per side
+ * (WENO5 reads three of them, KO8 four). */
 static void pad_row(const real* plane, long nr, long k, real* p)
 {
     const real* row = plane + k * nr;
-    for (long g = 0; g < 3; ++g) {
+    for (long g = 0; g < 4; ++g) {
         p[g] = row[0];
-        p[nr + 3 + g] = row[nr - 1];
+        p[nr + 4 + g] = row[nr - 1];
     }
-    memcpy(p + 3, row, (size_t)nr * sizeof(real));
+    memcpy(p + 4, row, (size_t)nr * sizeof(real));
 }
 
 /* theta neighbour of (k, j) in a plane, with the pole ghosts. */
@@ -325,24 +429,25 @@ void FN(oracle_teuk_rhs)(const oracle_teuk* P, const real* u, real* F)
     const real dx = pair(P->dx, P->dx_lo), dth = pair(P->dth, P->dth_lo), par = R(P->parity);
     const real ih1 = R(1) / (R(2) * dth), ih2 = R(1) / (dth * dth);
     const double eps = P->eps;
-    const int wm = P->wmode;
+    const int wm = P->wmode, sc = P->scheme;
+    const real sig = R(P->ko_sigma);
 #pragma omp parallel for schedule(static)
     for (long k = 0; k < nth; ++k) {
-        real* buf = (real*)malloc((size_t)(4 * (nr + 6)) * sizeof(real));
-        real *pPhR = buf + 3, *pPhI = buf + (nr + 6) + 3, *pPiR = buf + 2 * (nr + 6) + 3,
-             *pPiI = buf + 3 * (nr + 6) + 3;
-        pad_row(PhR, nr, k, pPhR - 3);
-        pad_row(PhI, nr, k, pPhI - 3);
-        pad_row(PiR, nr, k, pPiR - 3);
-        pad_row(PiI, nr, k, pPiI - 3);
+        real* buf = (real*)malloc((size_t)(4 * (nr + 8)) * sizeof(real));
+        real *pPhR = buf + 4, *pPhI = buf + (nr + 8) + 4, *pPiR = buf + 2 * (nr + 8) + 4,
+             *pPiI = buf + 3 * (nr + 8) + 4;
+        pad_row(PhR, nr, k, pPhR - 4);
+        pad_row(PhI, nr, k, pPhI - 4);
+        pad_row(PiR, nr, k, pPiR - 4);
+        pad_row(PiI, nr, k, pPiI - 4);
         for (long j = 0; j < nr; ++j) {
             const long i = k * nr + j;
             const real l1 = P->lam1[i], l2 = P->lam2[i];
             /* d_x u, each plane upwinded by its row's speed */
-            const real dPhR = upwind_d(pPhR, j, l1, dx, eps, wm);
-            const real dPhI = upwind_d(pPhI, j, l1, dx, eps, wm);
-            const real dPiR = upwind_d(pPiR, j, l2, dx, eps, wm);
-            const real dPiI = upwind_d(pPiI, j, l2, dx, eps, wm);
+            const real dPhR = radial_d(pPhR, j, l1, dx, eps, wm, sc);
+            const real dPhI = radial_d(pPhI, j, l1, dx, eps, wm, sc);
+            const real dPiR = radial_d(pPiR, j, l2, dx, eps, wm, sc);
+            const real dPiI = radial_d(pPiI, j, l2, dx, eps, wm, sc);
             /* theta derivatives of Phi (second-order centred) */
             const real phRm = theta_nb(PhR, nr, nth, k - 1, j, par);
             const real phRp = theta_nb(PhR, nr, nth, k + 1, j, par);
@@ -364,6 +469,13 @@ void FN(oracle_teuk_rhs)(const oracle_teuk* P, const real* u, real* F)
             /* rows 3-4: d_t pi = -lam2 d_x pi - m3 d_x Phi + B~t pi + A~thth Phi_thth + B~th Phi_th + C~ Phi */
             F[2 * N + i] = -l2 * dPiR - mdR + bpR + P->ath[i] * d2R + P->bth[i] * d1R + cpR;
             F[3 * N + i] = -l2 * dPiI - mdI + bpI + P->ath[i] * d2I + P->bth[i] * d1I + cpI;
+            if (sc == 2) {
+                /* Kreiss-Oliger dissipation on every plane (radial only) */
+                F[i] -= ko8(pPhR, j, dx, sig);
+                F[N + i] -= ko8(pPhI, j, dx, sig);
+                F[2 * N + i] -= ko8(pPiR, j, dx, sig);
+                F[3 * N + i] -= ko8(pPiI, j, dx, sig);
+            }
         }
         free(buf);
     }
