@@ -317,11 +317,11 @@ def bench_sweep(args, torch, T, W):
 
 
 # ----------------------------------------------------------------------------- C3-H: horizon chart
-def horizon_series(T, torch, wl, weights, steps, every, stream):
+def horizon_series(T, torch, wl, weights, steps, every, stream, scheme="weno5"):
     """Run the hyperboloidal-chart workload; returns (seconds, dt, tau, Phi_H, dPhi_H, theta)."""
     cfg = T.make_config(s=wl.s, m=wl.m, a=wl.a, nr=wl.nr, ntheta=wl.nth, x_min=wl.x_min, x_max=wl.x_max,
                         M=wl.M, dt=0.0, cfl=0.5, weight_prec=weights, x_extract=wl.x_e, extract_every=every,
-                        max_samples=steps // every + 1, chart="H", S=wl.S)
+                        max_samples=steps // every + 1, chart="H", S=wl.S, scheme=scheme)
     import workloads as W
     sv = T.Solver(cfg, stream=stream)
     sv.set_initial(W.gaussian_pulse(wl))
@@ -335,7 +335,7 @@ def horizon_series(T, torch, wl, weights, steps, every, stream):
         sv.step(k)
         done += k
         torch.cuda.synchronize()
-        log(f"  {weights}: {done}/{steps} steps")
+        log(f"  {scheme}/{weights}: {done}/{steps} steps")
     ev1.record(stream)
     torch.cuda.synchronize()
     sec = ev0.elapsed_time(ev1) / 1e3
@@ -419,6 +419,38 @@ def bench_horizon(args, torch, T, W):
             "phi_h_floor_coarse": float(yc[-1]), "phi_h_floor_fine": float(yf[-1]),
             "dphi_h_end_fine": float(df[-1]), "seconds_fine": secf, "steps_fine": nf,
         }
+    if not args.no_schemes:
+        # The paper's scheme comparison (Sec. 4, Fig. 2): Phi and d_rho Phi on the
+        # horizon from WENO5, WENO3 and FD6 + KO8 (sigma 0.01) on one grid.
+        pw = wl.with_(nr=args.physics_nr, nth=32)
+        cfg = T.make_config(s=pw.s, m=pw.m, a=pw.a, nr=pw.nr, ntheta=pw.nth, x_min=pw.x_min, x_max=pw.x_max,
+                            chart="H", S=pw.S)
+        probe = T.Solver(cfg, stream=stream)
+        dtp = probe.info().dt
+        probe.close()
+        nsteps = int(np.ceil(args.scheme_tau / dtp))
+        every = max(1, nsteps // 2000)
+        sch = {}
+        for scheme in ("weno5", "weno3", "fd6ko8"):
+            log(f"C3-H scheme {scheme}: {pw.nr}x{pw.nth}, {nsteps} steps to tau = {args.scheme_tau}")
+            secs, _, ts, phs, dphs, _ = horizon_series(T, torch, pw, "fp64", nsteps, every, stream, scheme=scheme)
+            sch[scheme] = (ts, phs[:, pw.nth // 4].real, dphs[:, pw.nth // 4].real, secs)
+        t5, y5, d5, _ = sch["weno5"]
+        res = {}
+        for scheme, (ts, ys, ds, secs) in sch.items():
+            li = local_index(ts, ys)
+            early = (ts[1:-1] >= 50.0) & (ts[1:-1] <= 110.0)
+            late = ts[1:-1] >= 0.5 * ts[-1]
+            res[scheme] = {
+                "ms_per_step": secs / nsteps * 1e3,
+                "phi_h_local_index_tau_50_110": float(np.mean(li[early])),
+                "dphi_h_local_index_late": float(np.mean(local_index(ts, ds)[late])),
+                "dphi_h_end": float(ds[-1]),
+                "phi_h_rel_l2_vs_weno5": float(np.linalg.norm(ys - y5) / np.linalg.norm(y5)),
+                "dphi_h_rel_l2_vs_weno5": float(np.linalg.norm(ds - d5) / np.linalg.norm(d5)),
+            }
+        out["schemes"] = {"grid": f"{pw.nr}x{pw.nth}", "tau_end": float(t5[-1]), "steps": nsteps,
+                          "ko_sigma": 0.01, "per_scheme": res}
     return out
 
 
@@ -568,6 +600,8 @@ def main():
     ap.add_argument("--physics-nr", type=int, default=4096,
                     help="C3H: radial points of the coarser horizon-law run (the finer has twice as many)")
     ap.add_argument("--tau-end", type=float, default=2000.0, help="C3H: end time of the coarse run")
+    ap.add_argument("--no-schemes", action="store_true", help="C3H: skip the WENO5/WENO3/FD6 comparison")
+    ap.add_argument("--scheme-tau", type=float, default=500.0, help="C3H: end time of the scheme comparison")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

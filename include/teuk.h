@@ -110,6 +110,19 @@ enum { TEUK_S_FP64 = 0, TEUK_S_DD = 1 };
  *     (UNSUPPORTED with TEUK_S_DD or in a group). */
 enum { TEUK_RK_SSP33 = 0, TEUK_RK_SSP104 = 1 };
 
+/* Radial scheme (Sec. 3.1).  WENO5 is the hot path; the other two are the
+ * paper's comparison schemes, run by a separate FP64 stage kernel (FP64 state
+ * and weights, single solves; UNSUPPORTED otherwise):
+ *   TEUK_SCHEME_WENO3:  third-order WENO, IS_1 = (f_j - f_{j-1})^2,
+ *                       IS_2 = (f_{j+1} - f_j)^2, linear weights 1/3, 2/3; the f^-
+ *                       flux is the mirror image of f^+ about j + 1/2.
+ *   TEUK_SCHEME_FD6KO8: sixth-order centred difference
+ *                       (u_{j+3} - 9 u_{j+2} + 45 u_{j+1} - 45 u_{j-1} + 9 u_{j-2} - u_{j-3})/(60 dx)
+ *                       with eighth-order Kreiss-Oliger dissipation: every plane's
+ *                       right-hand side receives -Q u, Q = ko_sigma dx^7 (D+ D-)^4 / 256,
+ *                       the dissipative sign; four end-value ghosts per side. */
+enum { TEUK_SCHEME_WENO5 = 0, TEUK_SCHEME_WENO3 = 1, TEUK_SCHEME_FD6KO8 = 2 };
+
 /* What teuk_extract returns. */
 enum {
     TEUK_X_STATE = 0,     /* [4][ntheta][nr] current state u^n                        */
@@ -147,6 +160,8 @@ typedef struct {
     int32_t workgroups;      /* stage-kernel workgroups; 0 = all the GPU holds at once */
     int32_t state_prec;      /* TEUK_S_*                                              */
     int32_t integrator;      /* TEUK_RK_*                                             */
+    int32_t scheme;          /* TEUK_SCHEME_*                                         */
+    int32_t reserved;        /* must be 0                                             */
     double M;                /* black-hole mass (> 0)                                  */
     double a;                /* spin, 0 <= a <= M                                      */
     double x_min, x_max;     /* radial range of x (r_* or rho; x_min < x_max)          */
@@ -161,6 +176,7 @@ typedef struct {
                                 rho_H = S r+/(r+ + S) on it (at most half a step
                                 outside); for a = M start it on the horizon, where
                                 the pi-row speed vanishes (no incoming data) */
+    double ko_sigma;         /* Kreiss-Oliger sigma of TEUK_SCHEME_FD6KO8, in [0, 1] (e.g. 0.01) */
 } teuk_config;
 
 typedef struct {
@@ -181,7 +197,7 @@ typedef struct {
 } teuk_info_t;
 
 /* Fill cfg with defaults: ABI version, M = 1, chart T, FP64 state and weights,
- * SSP-RK(3,3), cfl 0.5,
+ * SSP-RK(3,3), WENO5 (ko_sigma 0.01 for FD6), cfl 0.5,
  * eps 1e-6, dt from the bound, no waveform.  Sizes and ranges must still be set. */
 void teuk_default_config(teuk_config* cfg);
 

@@ -36,6 +36,8 @@ TEUK_W_FP64, TEUK_W_FP32, TEUK_W_FP16, TEUK_W_BF16, TEUK_W_DD = 0, 1, 2, 3, 4
 TEUK_S_FP64, TEUK_S_DD = 0, 1
 TEUK_RK_SSP33, TEUK_RK_SSP104 = 0, 1
 INTEGRATOR = {"rk3": TEUK_RK_SSP33, "rk104": TEUK_RK_SSP104}
+TEUK_SCHEME_WENO5, TEUK_SCHEME_WENO3, TEUK_SCHEME_FD6KO8 = 0, 1, 2
+SCHEME = {"weno5": TEUK_SCHEME_WENO5, "weno3": TEUK_SCHEME_WENO3, "fd6ko8": TEUK_SCHEME_FD6KO8}
 TEUK_X_STATE, TEUK_X_WAVEFORM, TEUK_X_TIMES, TEUK_X_COEFFS, TEUK_X_RHS, TEUK_X_HORIZON = 0, 1, 2, 3, 4, 5
 TEUK_NCOEF = 10
 CHART = {"T": TEUK_CHART_TORTOISE, "H": TEUK_CHART_HYPERBOLOIDAL}
@@ -53,9 +55,11 @@ class teuk_config(ctypes.Structure):
                 ("weight_prec", ctypes.c_int32), ("extract_every", ctypes.c_int32),
                 ("max_samples", ctypes.c_int32), ("workgroups", ctypes.c_int32),
                 ("state_prec", ctypes.c_int32), ("integrator", ctypes.c_int32),
+                ("scheme", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("M", ctypes.c_double), ("a", ctypes.c_double), ("x_min", ctypes.c_double),
                 ("x_max", ctypes.c_double), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
-                ("weno_eps", ctypes.c_double), ("x_extract", ctypes.c_double), ("S", ctypes.c_double)]
+                ("weno_eps", ctypes.c_double), ("x_extract", ctypes.c_double), ("S", ctypes.c_double),
+                ("ko_sigma", ctypes.c_double)]
 
 
 class teuk_device_ctx(ctypes.Structure):
@@ -245,7 +249,7 @@ def make_config(*, s: int, m: int, a: float, nr: int, ntheta: int, x_min: float,
                 M: float = 1.0, dt: float = 0.0, cfl: float = 0.5, weno_eps: float = 1e-6,
                 weight_prec="fp64", x_extract: float | None = None, extract_every: int = 0,
                 max_samples: int = 0, workgroups: int = 0, chart="T", S: float = 20.0,
-                state="fp64", integrator="rk3") -> teuk_config:
+                state="fp64", integrator="rk3", scheme="weno5", ko_sigma: float = 0.01) -> teuk_config:
     c = teuk_default_config()
     c.s, c.m, c.a, c.M = int(s), int(m), float(a), float(M)
     c.nr, c.ntheta = int(nr), int(ntheta)
@@ -259,6 +263,8 @@ def make_config(*, s: int, m: int, a: float, nr: int, ntheta: int, x_min: float,
     c.S = float(S)
     c.state_prec = STATE_PREC[state] if isinstance(state, str) else int(state)
     c.integrator = INTEGRATOR[integrator] if isinstance(integrator, str) else int(integrator)
+    c.scheme = SCHEME[scheme] if isinstance(scheme, str) else int(scheme)
+    c.ko_sigma = float(ko_sigma)
     return c
 
 

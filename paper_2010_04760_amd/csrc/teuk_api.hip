@@ -148,6 +148,9 @@ bool validate(const teuk_config* c, std::string& err)
     if (c->weight_prec < TEUK_W_FP64 || c->weight_prec > TEUK_W_DD) { err = "weight_prec must be a TEUK_W_* value"; return false; }
     if (c->state_prec != TEUK_S_FP64 && c->state_prec != TEUK_S_DD) { err = "state_prec must be a TEUK_S_* value"; return false; }
     if (c->integrator != TEUK_RK_SSP33 && c->integrator != TEUK_RK_SSP104) { err = "integrator must be a TEUK_RK_* value"; return false; }
+    if (c->scheme < TEUK_SCHEME_WENO5 || c->scheme > TEUK_SCHEME_FD6KO8) { err = "scheme must be a TEUK_SCHEME_* value"; return false; }
+    if (c->reserved != 0) { err = "reserved must be 0"; return false; }
+    if (!(c->ko_sigma >= 0.0) || !(c->ko_sigma <= 1.0)) { err = "ko_sigma must lie in [0, 1]"; return false; }
     if (c->weight_prec == TEUK_W_DD && c->state_prec != TEUK_S_DD) { err = "TEUK_W_DD weights need the TEUK_S_DD state"; return false; }
     if (!(c->M > 0.0) || !std::isfinite(c->M)) { err = "M must be positive and finite"; return false; }
     if (!(c->a >= 0.0) || !(c->a <= c->M)) { err = "spin a must satisfy 0 <= a <= M"; return false; }
@@ -268,6 +271,7 @@ void teuk_default_config(teuk_config* c)
     c->cfl = 0.5;
     c->weno_eps = 1e-6;
     c->S = 20.0;
+    c->ko_sigma = 0.01;
 }
 
 size_t teuk_footprint_bytes(const teuk_config* cfg)
@@ -290,6 +294,8 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
                     "double-double state: tortoise chart with TEUK_W_DD or TEUK_W_FP64 weights only");
     if (dd && cfg->integrator != TEUK_RK_SSP33)
         return fail(nullptr, TEUK_ERR_UNSUPPORTED, "double-double state: SSP-RK(3,3) only");
+    if (cfg->scheme != TEUK_SCHEME_WENO5 && (dd || cfg->weight_prec != TEUK_W_FP64))
+        return fail(nullptr, TEUK_ERR_UNSUPPORTED, "comparison schemes: FP64 state and weights only");
     std::vector<double> rtab, ttab, ctab, dtab;
     DDScalars ddk{};
     if (chartH ? !build_tables_H(*cfg, ctab, err) : !build_tables(*cfg, rtab, ttab, err))
@@ -499,11 +505,21 @@ static StageArgs stage_args(const teuk_solver* h)
     a.cb = 1.0;
     a.out2 = nullptr;
     a.ca2 = a.cb2 = 0.0;
+    a.inv_dx = 1.0 / h->dx;
+    a.ko_sigma = c.ko_sigma;
     a.eps = c.weno_eps;
     a.parity = ((c.m + c.s) % 2 != 0) ? -1.0 : 1.0;
     a.uk = a.un = h->u[0];
     a.out = h->u[1];
     return a;
+}
+
+// One stage launch of the solver's radial scheme.
+static int run_stage(const teuk_solver* h, const StageArgs& a, int stage)
+{
+    const teuk_config& c = h->cfg;
+    if (c.scheme != TEUK_SCHEME_WENO5) return launch_cmp_stage(a, stage, c.scheme, c.chart, h->stream);
+    return launch_stage(a, stage, c.weight_prec, c.chart, h->stream);
 }
 
 // One SSP-RK(10,4) step (Sec. 3.2) in the three state buffers U = u^n,
@@ -514,7 +530,6 @@ static StageArgs stage_args(const teuk_solver* h)
 // stage 10 writes u^{n+1} = q + 3/5 (u(9) + dt/6 F(u(9))) over U.
 static int rk104_step(teuk_solver* h, StageArgs a)
 {
-    const teuk_config& c = h->cfg;
     double* U = h->u[0];
     double* AB[2] = {h->u[1], h->u[2]};
     a.dt = h->dt / 6.0;
@@ -528,7 +543,7 @@ static int rk104_step(teuk_solver* h, StageArgs a)
         a.uk = in;
         a.un = in;
         a.out = AB[(st - 1) & 1];   // A, B, A, B
-        e = launch_stage(a, 1, c.weight_prec, c.chart, h->stream);
+        e = run_stage(h, a, 1);
         in = a.out;
     }
     if (e) return e;
@@ -542,7 +557,7 @@ static int rk104_step(teuk_solver* h, StageArgs a)
     a.out2 = U;
     a.ca2 = 1.0 / 25.0;
     a.cb2 = 9.0 / 25.0;
-    e = launch_stage(a, 4, c.weight_prec, c.chart, h->stream);
+    e = run_stage(h, a, 4);
     a.out2 = nullptr;
     a.segs = h->segs[0];
     a.grid = h->nstrips * h->segs[0];
@@ -553,7 +568,7 @@ static int rk104_step(teuk_solver* h, StageArgs a)
         a.uk = in;
         a.un = in;
         a.out = AB[(st - 5) & 1];   // B, A, B, A
-        e = launch_stage(a, 1, c.weight_prec, c.chart, h->stream);
+        e = run_stage(h, a, 1);
         in = a.out;
     }
     if (e) return e;
@@ -564,7 +579,7 @@ static int rk104_step(teuk_solver* h, StageArgs a)
     a.out = U;
     a.ca = 1.0;
     a.cb = 3.0 / 5.0;
-    return launch_stage(a, 2, c.weight_prec, c.chart, h->stream);
+    return run_stage(h, a, 2);
 }
 
 teuk_status teuk_step(teuk_solver* h, int64_t nsteps)
@@ -601,13 +616,13 @@ teuk_status teuk_step(teuk_solver* h, int64_t nsteps)
     for (int64_t n = 0; n < nsteps; ++n) {
         // u1 = u + dt F(u)
         a.uk = h->u[0]; a.un = h->u[0]; a.out = h->u[1]; a.ca = 0.0; a.cb = 1.0; a.segs = h->segs[0]; a.grid = h->nstrips * h->segs[0];
-        int e = launch_stage(a, 1, c.weight_prec, c.chart, h->stream);
+        int e = run_stage(h, a, 1);
         // u2 = 3/4 u + 1/4 (u1 + dt F(u1))
         if (!e) { a.uk = h->u[1]; a.un = h->u[0]; a.out = h->u[2]; a.ca = 0.75; a.cb = 0.25; a.segs = h->segs[1]; a.grid = h->nstrips * h->segs[1];
-                  e = launch_stage(a, 2, c.weight_prec, c.chart, h->stream); }
+                  e = run_stage(h, a, 2); }
         // u = 1/3 u + 2/3 (u2 + dt F(u2)), in place (u^n is read only at the own point)
         if (!e) { a.uk = h->u[2]; a.un = h->u[0]; a.out = h->u[0]; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0; a.segs = h->segs[1]; a.grid = h->nstrips * h->segs[1];
-                  e = launch_stage(a, 3, c.weight_prec, c.chart, h->stream); }
+                  e = run_stage(h, a, 3); }
         if (e) return hip_fail(h, e, "stage launch");
         ++h->steps;
         if (c.extract_every > 0 && h->steps % c.extract_every == 0) {
@@ -674,7 +689,7 @@ teuk_status teuk_extract(teuk_solver* h, int32_t what, double* out, size_t capac
             e = launch_dd_stage(a, 0, h->cfg.weight_prec, h->stream);
         } else {
             StageArgs a = stage_args(h);
-            e = launch_stage(a, 0, h->cfg.weight_prec, h->cfg.chart, h->stream);
+            e = run_stage(h, a, 0);
         }
         if (!e) e = (int)hipMemcpyAsync(out, h->u[1], need * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     } else if (what == TEUK_X_TIMES) {
@@ -895,8 +910,8 @@ teuk_status teuk_group_add(teuk_group* g, teuk_solver* h)
     if (!g) return gfail(nullptr, TEUK_ERR_INVALID_ARG, "group is NULL");
     if (!h) return gfail(g, TEUK_ERR_INVALID_ARG, "solver is NULL");
     if (h->dd) return gfail(g, TEUK_ERR_UNSUPPORTED, "double-double solvers are not group members");
-    if (h->cfg.integrator != TEUK_RK_SSP33)
-        return gfail(g, TEUK_ERR_UNSUPPORTED, "group members step with SSP-RK(3,3)");
+    if (h->cfg.integrator != TEUK_RK_SSP33 || h->cfg.scheme != TEUK_SCHEME_WENO5)
+        return gfail(g, TEUK_ERR_UNSUPPORTED, "group members step with SSP-RK(3,3) and WENO5");
     if (h->group) return gfail(g, TEUK_ERR_INVALID_ARG, "solver already belongs to a group");
     if (h->stream != g->stream) return gfail(g, TEUK_ERR_INVALID_ARG, "solver and group use different streams");
     if (h->device != g->device) return gfail(g, TEUK_ERR_INVALID_ARG, "solver and group are on different devices");

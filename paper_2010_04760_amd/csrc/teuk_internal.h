@@ -43,6 +43,8 @@ struct StageArgs {
     double dt, ca, cb;     // out = ca un + cb (uk + dt F)
     double* out2;          // dual stage: second output ca2 un + cb2 (uk + dt F); may alias un
     double ca2, cb2;
+    double inv_dx;         // 1 / dx (comparison schemes)
+    double ko_sigma;       // Kreiss-Oliger sigma (TEUK_SCHEME_FD6KO8)
     double eps, parity;    // WENO epsilon, (-1)^(m+s)
 };
 
@@ -83,6 +85,9 @@ int launch_extract(const double* u, long long plane, int nr, int nth, int j_e, d
                    void* stream);
 int launch_coef_dump(const double* rtab, const double* ttab, const double* ctab, int nr, int nth, double* out,
                      void* stream);
+// Comparison schemes (TEUK_SCHEME_WENO3 / TEUK_SCHEME_FD6KO8, FP64): one stage,
+// same stage codes as launch_stage.
+int launch_cmp_stage(const StageArgs& a, int stage, int scheme, int chart, void* stream);
 // Double-double path: one stage (0 = F only, 1, 2, 3) with weights in FP64
 // (TEUK_W_FP64, the mixed variant) or double-double (TEUK_W_DD); the waveform
 // sample of one radial index ([nth][2] pairs); TwoSum normalisation of n pairs.

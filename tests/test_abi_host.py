@@ -44,7 +44,7 @@ int main(void) {
   printf("teuk_device_ctx %zu\\n", sizeof(teuk_device_ctx));
   printf("teuk_info_t %zu\\n", sizeof(teuk_info_t));
   F(teuk_config, M) F(teuk_config, a) F(teuk_config, x_extract) F(teuk_config, workgroups) F(teuk_config, S)
-  F(teuk_config, state_prec) F(teuk_config, integrator)
+  F(teuk_config, state_prec) F(teuk_config, integrator) F(teuk_config, scheme) F(teuk_config, ko_sigma)
   F(teuk_info_t, samples) F(teuk_info_t, dt_bound) F(teuk_device_ctx, workspace_bytes)
   return 0; }
 """)
