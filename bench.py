@@ -200,6 +200,17 @@ def bench_single(args, torch, T, W):
             err = float(np.linalg.norm(wave_w - wave) / np.linalg.norm(wave))
             mixed[wp] = {"value": pu / sec_w, "speedup_vs_fp64": gpu_s / sec_w, "waveform_rel_l2_vs_fp64": err}
         out["mixed_precision"] = mixed
+    if weights == "fp64" and not args.no_blocked:
+        # Temporal blocking: the same SSP-RK(3,3) step as one launch per step
+        # (u(1), u(2) in LDS; 64 B of HBM traffic per point-step).
+        secb, _, infob, waveb = run("fp64", integrator="rk3_blocked")
+        out["blocked"] = {
+            "steps": steps, "ms_per_step": secb / steps * 1e3, "value": pu / secb, "unit": "point-updates/s",
+            "speedup_vs_three_launch": gpu_s / secb, "tiles": infob.workgroups,
+            "waveform_rel_diff_vs_three_launch": float(np.max(np.abs(waveb - wave)) / np.max(np.abs(wave))),
+            "hbm": {"bytes_per_point_step": 64, "achieved_GBs": 64.0 * wl.points * steps / secb / 1e9,
+                    "frac": 64.0 * wl.points * steps / secb / 1e9 / HBM_PEAK_GBS},
+        }
     if weights == "fp64" and not args.no_rk104:
         # SSP-RK(10,4) (Sec. 3.2) over the same simulated time: its default step
         # is 6x the SSP-RK(3,3) step (SSP coefficients 6 and 1), ten stages per
@@ -583,6 +594,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/FP16/BF16-weight runs")
     ap.add_argument("--no-rk104", action="store_true", help="C2: skip the SSP-RK(10,4) run")
+    ap.add_argument("--no-blocked", action="store_true", help="C2: skip the temporally blocked run")
     ap.add_argument("--quad-steps", type=int, default=1000,
                     help="C2: steps of the double-double state runs (0: skip them)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)

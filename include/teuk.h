@@ -108,7 +108,15 @@ enum { TEUK_S_FP64 = 0, TEUK_S_DD = 1 };
  *     q = 1/25 u^n + 9/25 (u(4) + dt/6 F(u(4))) over u^n, and the last is
  *     u^{n+1} = q + 3/5 (u(9) + dt/6 F(u(9))).  FP64 state, single solves only
  *     (UNSUPPORTED with TEUK_S_DD or in a group). */
-enum { TEUK_RK_SSP33 = 0, TEUK_RK_SSP104 = 1 };
+enum { TEUK_RK_SSP33 = 0, TEUK_RK_SSP104 = 1, TEUK_RK_SSP33_BLOCKED = 2 };
+/* TEUK_RK_SSP33_BLOCKED: SSP-RK(3,3), each step one launch that computes all
+ * three stages of a tile (temporal blocking): u(1) and u(2) stay in LDS and
+ * HBM sees one read of u^n and one write of u^{n+1} per point.  Tiles are 51
+ * radial points by about nth / segs rows; a tile recomputes the stage-1
+ * values two rows and six points beyond its outputs and the stage-2 values one
+ * row and three points beyond (workgroups, when > 0, sets the tile count).
+ * The result is the same arithmetic as TEUK_RK_SSP33, point by point.
+ * Tortoise chart, FP64 state, WENO5 with FP64 weights, single solves. */
 
 /* Radial scheme (Sec. 3.1).  WENO5 is the hot path; the other two are the
  * paper's comparison schemes, run by a separate FP64 stage kernel (FP64 state

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "teuk_coef.h"
@@ -39,6 +40,7 @@ struct teuk_solver {
     int j_e = 0;
     int nstrips = 0;
     int segs[2] = {0, 0};                           // theta segments per strip: stage 1, stages 2-3
+    int bstrips = 0, bsegs = 0;                     // temporal blocking: tiles per launch = bstrips * bsegs
     long long plane = 0;
     long long steps = 0, samples = 0;
     bool have_init = false;
@@ -147,7 +149,7 @@ bool validate(const teuk_config* c, std::string& err)
     if ((long long)c->nr * c->ntheta > (1LL << 34)) { err = "nr * ntheta too large"; return false; }
     if (c->weight_prec < TEUK_W_FP64 || c->weight_prec > TEUK_W_DD) { err = "weight_prec must be a TEUK_W_* value"; return false; }
     if (c->state_prec != TEUK_S_FP64 && c->state_prec != TEUK_S_DD) { err = "state_prec must be a TEUK_S_* value"; return false; }
-    if (c->integrator != TEUK_RK_SSP33 && c->integrator != TEUK_RK_SSP104) { err = "integrator must be a TEUK_RK_* value"; return false; }
+    if (c->integrator < TEUK_RK_SSP33 || c->integrator > TEUK_RK_SSP33_BLOCKED) { err = "integrator must be a TEUK_RK_* value"; return false; }
     if (c->scheme < TEUK_SCHEME_WENO5 || c->scheme > TEUK_SCHEME_FD6KO8) { err = "scheme must be a TEUK_SCHEME_* value"; return false; }
     if (c->reserved != 0) { err = "reserved must be 0"; return false; }
     if (!(c->ko_sigma >= 0.0) || !(c->ko_sigma <= 1.0)) { err = "ko_sigma must lie in [0, 1]"; return false; }
@@ -296,6 +298,10 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
         return fail(nullptr, TEUK_ERR_UNSUPPORTED, "double-double state: SSP-RK(3,3) only");
     if (cfg->scheme != TEUK_SCHEME_WENO5 && (dd || cfg->weight_prec != TEUK_W_FP64))
         return fail(nullptr, TEUK_ERR_UNSUPPORTED, "comparison schemes: FP64 state and weights only");
+    if (cfg->integrator == TEUK_RK_SSP33_BLOCKED &&
+        (chartH || dd || cfg->scheme != TEUK_SCHEME_WENO5 || cfg->weight_prec != TEUK_W_FP64))
+        return fail(nullptr, TEUK_ERR_UNSUPPORTED,
+                    "temporal blocking: tortoise chart, FP64 state, WENO5 with FP64 weights only");
     std::vector<double> rtab, ttab, ctab, dtab;
     DDScalars ddk{};
     if (chartH ? !build_tables_H(*cfg, ctab, err) : !build_tables(*cfg, rtab, ttab, err))
@@ -359,6 +365,18 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
         (long long)h->nstrips * h->segs[1] > (1LL << 31) - 1) {
         free_solver(h);
         return fail(nullptr, TEUK_ERR_UNSUPPORTED, "weight precision not built (or occupancy query failed)");
+    }
+    if (cfg->integrator == TEUK_RK_SSP33_BLOCKED) {
+        h->bstrips = (cfg->nr + kBlockedPoints - 1) / kBlockedPoints;
+        long long cap = cfg->workgroups > 0 ? cfg->workgroups : blocked_grid();
+        long long segs = cap / h->bstrips;
+        if (segs > cfg->ntheta) segs = cfg->ntheta;
+        if (segs < 1) segs = 1;
+        h->bsegs = (int)segs;
+        if (cap <= 0 || (long long)h->bstrips * h->bsegs > (1LL << 31) - 1) {
+            free_solver(h);
+            return fail(nullptr, TEUK_ERR_UNSUPPORTED, "temporal blocking: occupancy query failed");
+        }
     }
     h->j_e = cfg->extract_every > 0 ? (int)std::floor((cfg->x_extract - cfg->x_min) / h->dx + 0.5) : 0;
     if (h->j_e > cfg->nr - 1) h->j_e = cfg->nr - 1;
@@ -601,6 +619,27 @@ teuk_status teuk_step(teuk_solver* h, int64_t nsteps)
         return TEUK_OK;
     }
     StageArgs a = stage_args(h);
+    if (c.integrator == TEUK_RK_SSP33_BLOCKED) {
+        a.nstrips = h->bstrips;
+        a.segs = h->bsegs;
+        a.grid = h->bstrips * h->bsegs;
+        a.ca = 0.0;
+        a.cb = 1.0;
+        for (int64_t n = 0; n < nsteps; ++n) {
+            a.uk = h->u[0];
+            a.un = h->u[0];
+            a.out = h->u[1];
+            const int e = launch_blocked_step(a, c.weight_prec, h->stream);
+            if (e) return hip_fail(h, e, "blocked step launch");
+            std::swap(h->u[0], h->u[1]);             // u^{n+1} is the new state buffer
+            ++h->steps;
+            if (c.extract_every > 0 && h->steps % c.extract_every == 0) {
+                teuk_status st = record_sample(h);
+                if (st != TEUK_OK) return st;
+            }
+        }
+        return TEUK_OK;
+    }
     if (c.integrator == TEUK_RK_SSP104) {
         for (int64_t n = 0; n < nsteps; ++n) {
             const int e = rk104_step(h, a);
@@ -726,7 +765,7 @@ teuk_status teuk_info(teuk_solver* h, teuk_info_t* info)
     info->steps = h->steps;
     info->samples = h->samples;
     info->j_extract = h->j_e;
-    info->workgroups = h->nstrips * h->segs[1];
+    info->workgroups = h->cfg.integrator == TEUK_RK_SSP33_BLOCKED ? h->bstrips * h->bsegs : h->nstrips * h->segs[1];
     info->dt_bound = h->dt_bound;
     return TEUK_OK;
 }

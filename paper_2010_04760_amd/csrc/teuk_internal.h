@@ -85,6 +85,13 @@ int launch_extract(const double* u, long long plane, int nr, int nth, int j_e, d
                    void* stream);
 int launch_coef_dump(const double* rtab, const double* ttab, const double* ctab, int nr, int nth, double* out,
                      void* stream);
+// Temporal blocking: one whole SSP-RK(3,3) step (tortoise chart, FP64
+// weights) from a.uk into a.out (distinct buffers), tiles of kBlockedPoints
+// radial points by a.nth / a.segs rows, a.grid = a.nstrips * a.segs
+// workgroups.  blocked_grid() is the resident workgroup count.
+constexpr int kBlockedPoints = 51;
+int blocked_grid();
+int launch_blocked_step(const StageArgs& a, int weight_prec, void* stream);
 // Comparison schemes (TEUK_SCHEME_WENO3 / TEUK_SCHEME_FD6KO8, FP64): one stage,
 // same stage codes as launch_stage.
 int launch_cmp_stage(const StageArgs& a, int stage, int scheme, int chart, void* stream);

@@ -801,6 +801,232 @@ __global__ __launch_bounds__(kWave) void group_stage_kernel(const StageArgs* __r
     }
 }
 
+// ---------------------------------------------------------------- temporal blocking
+// One whole SSP-RK(3,3) step per launch (tortoise chart): the three stages of a
+// tile are computed in one wave, the intermediate states u(1) and u(2) never
+// leave LDS, and HBM sees one read of u^n and one write of u^{n+1} per point
+// (64 B instead of 256 B per point-step).  The price is recomputation at the
+// tile edges: a stage needs three radial neighbours and one theta neighbour of
+// its input on each side, so
+//   - lane l of a wave stands for radial point j = 51 strip - 6 + l in all three
+//     stages; stage 1 is valid on lanes 0..62, stage 2 on 3..59, stage 3 (the
+//     output) on 6..56, i.e. 51 outputs per 64 lanes;
+//   - a tile of final rows [k0, k1) computes stage 1 on [k0-2, k1+2) and stage
+//     2 on [k0-1, k1+1) (clipped to the grid; a pole takes the parity ghost of
+//     the stage's own input, as in the three-launch step).
+// The wave marches the rows upward: at step r it stages u^n row r+1 (LDS),
+// computes u(1) at row r, u(2) at row r-1 and u^{n+1} at row r-2.  Radial
+// ghosts of u(1) and u(2) are the end values, read by clamping the lane index
+// to the lanes inside the grid.  The arithmetic of each point and stage is the
+// three-launch stage kernel's, term for term.
+constexpr int kBW = 51;     // output points per wave
+constexpr int kBLead = 6;   // lane of the first output point
+
+template <int WP>
+__global__ __launch_bounds__(kWave) void blocked_step_kernel(StageArgs A)
+{
+    __shared__ double sn[2][4][kRowP];   // u^n rows (positions j - 3 .. j + 65 of lane 0's point)
+    __shared__ double s1[2][4][kWave];   // u(1) rows, one value per lane
+    __shared__ double s2[2][4][kWave];   // u(2) rows
+    const int l = threadIdx.x;
+    const int nr = A.nr, nth = A.nth;
+    const long long P = A.plane;
+    const int rank = xcd_rank((int)blockIdx.x, (int)gridDim.x);
+    const int strip = rank / A.segs;
+    const int seg = rank - strip * A.segs;
+    const int k0 = (int)((long long)nth * seg / A.segs);
+    const int k1 = (int)((long long)nth * (seg + 1) / A.segs);
+    if (k1 <= k0) return;
+    const int p0 = strip * kBW - kBLead;                 // point of lane 0
+    const int j = p0 + l;
+    const int jc = clampi(j, 0, nr - 1);
+    const unsigned oc = (unsigned)jc * 8u;
+    const unsigned oa = (unsigned)clampi(p0 - 3 + l, 0, nr - 1) * 8u;     // staged position l
+    const unsigned ob = (unsigned)clampi(p0 + 61 + l, 0, nr - 1) * 8u;    // staged position 64 + l, l < 5
+    const bool halo = l < 5;
+    const int lo = clampi(-p0, 0, kWave - 1), hi = clampi(nr - 1 - p0, 0, kWave - 1);   // lanes inside the grid
+    const bool out_lane = l >= kBLead && l < kBLead + kBW && j < nr;
+    const double* ukp[4] = {A.uk, A.uk + P, A.uk + 2 * P, A.uk + 3 * P};
+    double* outp[4] = {A.out, A.out + P, A.out + 2 * P, A.out + 3 * P};
+    double rt[kNRT];
+#pragma unroll
+    for (int i = 0; i < kNRT; ++i) rt[i] = ldb(A.rtab + (size_t)i * nr, oc);
+    const __attribute__((address_space(4))) double* tt =
+        (const __attribute__((address_space(4))) double*)A.ttab;
+
+    const int r1lo = max(k0 - 2, 0), r1hi = min(k1 + 2, nth);   // stage-1 rows
+    const int r2lo = max(k0 - 1, 0), r2hi = min(k1 + 1, nth);   // stage-2 rows
+    const int nstage = min(r1hi + 1, nth);                       // u^n rows staged: [r1lo, nstage)
+
+    double xa[4], xb[4];
+    auto load_row = [&](int k) {
+        const size_t row = (size_t)k * nr;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) xa[p] = ldb(ukp[p] + row, oa);
+        if (halo) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) xb[p] = ldb(ukp[p] + row, ob);
+        }
+    };
+    auto store_row = [&](int b) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) sn[b][p][l] = xa[p];
+        if (halo) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) sn[b][p][kWave + l] = xb[p];
+        }
+    };
+    auto cl = [&](int q) { return clampi(q, lo, hi); };
+
+    // one stage at one row for this lane: w[p][t] = input of plane p at j - 3 + t,
+    // dn / up = input Phi at the own point on rows k - 1 / k + 1
+    struct Out { double v[4]; };
+    auto stage = [&](const double (&w)[4][6], double dnR, double dnI, double upR, double upI, int k, double ca,
+                     double cb, const double (&un)[4], bool first) {
+        const double fR = Weno<WP>::flux6(w[0][0], w[0][1], w[0][2], w[0][3], w[0][4], A.eps);
+        const double fI = Weno<WP>::flux6(w[1][0], w[1][1], w[1][2], w[1][3], w[1][4], A.eps);
+        const double gR = Weno<WP>::flux6(w[2][5], w[2][4], w[2][3], w[2][2], w[2][1], A.eps);
+        const double gI = Weno<WP>::flux6(w[3][5], w[3][4], w[3][3], w[3][2], w[3][1], A.eps);
+        const double fR1 = __shfl_down(fR, 1), fI1 = __shfl_down(fI, 1);
+        const double gR1 = __shfl_down(gR, 1), gI1 = __shfl_down(gI, 1);
+        const double sn2 = tt[kSn2 * nth + k], cs = tt[kCs * nth + k];
+        const double cot = tt[kCot * nth + k], th = tt[kTh * nth + k];
+        const double phR = w[0][3], phI = w[1][3], piR = w[2][3], piI = w[3][3];
+        const double dPhR = (fR1 - fR) * A.inv6dx;
+        const double dPhI = (fI1 - fI) * A.inv6dx;
+        const double dPiR = (gR1 - gR) * A.inv6dx;
+        const double dPiI = (gI1 - gI) * A.inv6dx;
+        const PointCoef c = point_coef(rt, sn2, cs, cot, th, rsq64(sigma2(rt, sn2)));
+        const double d1R = (upR - dnR) * A.ih1, d1I = (upI - dnI) * A.ih1;
+        const double d2R = (upR - 2.0 * phR + dnR) * A.ih2;
+        const double d2I = (upI - 2.0 * phI + dnI) * A.ih2;
+        const double FphR = piR - c.b * dPhR;
+        const double FphI = piI - c.b * dPhI;
+        const double FpiR = c.b * dPiR - (c.m3r * dPhR - c.m3i * dPhI) + (c.btr * piR - c.bti * piI) +
+                            c.ath * d2R + c.bth * d1R + (c.cr * phR - c.ci * phI);
+        const double FpiI = c.b * dPiI - (c.m3r * dPhI + c.m3i * dPhR) + (c.btr * piI + c.bti * piR) +
+                            c.ath * d2I + c.bth * d1I + (c.cr * phI + c.ci * phR);
+        Out o;
+        if (first) {
+            o.v[0] = phR + A.dt * FphR;
+            o.v[1] = phI + A.dt * FphI;
+            o.v[2] = piR + A.dt * FpiR;
+            o.v[3] = piI + A.dt * FpiI;
+        } else {
+            o.v[0] = ca * un[0] + cb * (phR + A.dt * FphR);
+            o.v[1] = ca * un[1] + cb * (phI + A.dt * FphI);
+            o.v[2] = ca * un[2] + cb * (piR + A.dt * FpiR);
+            o.v[3] = ca * un[3] + cb * (piI + A.dt * FpiI);
+        }
+        return o;
+    };
+
+    // rolling own-point values: u^n (4 planes) at rows r, r-1, r-2; Phi of
+    // u^n at r-1; Phi of u(1) at r-2, r-1, r; Phi of u(2) at r-3, r-2, r-1
+    double un0[4] = {0, 0, 0, 0}, un1[4] = {0, 0, 0, 0}, un2[4] = {0, 0, 0, 0};
+    double nbR = 0, nbI = 0;                 // u^n Phi on row r - 1
+    double a2R = 0, a2I = 0, a1R = 0, a1I = 0, a0R = 0, a0I = 0;   // u(1) Phi on r-2, r-1, r
+    double c3R = 0, c3I = 0, c2R = 0, c2I = 0, c1R = 0, c1I = 0;   // u(2) Phi on r-3, r-2, r-1
+    {
+        const int kb = r1lo - 1;
+        if (kb >= 0) {
+            nbR = ldb(ukp[0] + (size_t)kb * nr, oc);
+            nbI = ldb(ukp[1] + (size_t)kb * nr, oc);
+        } else {
+            nbR = A.parity * ldb(ukp[0] + (size_t)r1lo * nr, oc);
+            nbI = A.parity * ldb(ukp[1] + (size_t)r1lo * nr, oc);
+        }
+    }
+    load_row(r1lo);
+    store_row(r1lo & 1);
+    if (r1lo + 1 < nstage) {
+        load_row(r1lo + 1);
+        store_row((r1lo + 1) & 1);
+    }
+    if (r1lo + 2 < nstage) load_row(r1lo + 2);
+
+    for (int r = r1lo; r < k1 + 2; ++r) {
+        lds_sync();                                   // u^n rows r, r+1 staged
+        const int r2 = r - 1, r3 = r - 2;
+        if (r < r1hi) {
+            // ---- stage 1 at row r: u(1) = u^n + dt F(u^n)
+            const int b = r & 1;
+            double w[4][6];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int t = 0; t < 6; ++t) w[p][t] = sn[b][p][l + t];
+            double upR, upI;
+            if (r + 1 < nth) {
+                upR = sn[b ^ 1][0][l + 3];
+                upI = sn[b ^ 1][1][l + 3];
+            } else {
+                upR = A.parity * w[0][3];
+                upI = A.parity * w[1][3];
+            }
+            const double none[4] = {0, 0, 0, 0};
+            const Out o = stage(w, nbR, nbI, upR, upI, r, 0.0, 1.0, none, true);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) s1[b][p][l] = o.v[p];
+            un2[0] = un1[0]; un2[1] = un1[1]; un2[2] = un1[2]; un2[3] = un1[3];
+            un1[0] = un0[0]; un1[1] = un0[1]; un1[2] = un0[2]; un1[3] = un0[3];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) un0[p] = w[p][3];
+            nbR = w[0][3];
+            nbI = w[1][3];
+            a2R = a1R; a2I = a1I; a1R = a0R; a1I = a0I;
+            a0R = o.v[0]; a0I = o.v[1];
+        } else {
+            un2[0] = un1[0]; un2[1] = un1[1]; un2[2] = un1[2]; un2[3] = un1[3];
+            un1[0] = un0[0]; un1[1] = un0[1]; un1[2] = un0[2]; un1[3] = un0[3];
+            a2R = a1R; a2I = a1I; a1R = a0R; a1I = a0I;
+        }
+        lds_sync();                                   // u(1) row r in LDS
+        if (r2 >= r2lo && r2 < r2hi) {
+            // ---- stage 2 at row r - 1: u(2) = 3/4 u^n + 1/4 (u(1) + dt F(u(1)))
+            const int b = r2 & 1;
+            double w[4][6];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int t = 0; t < 6; ++t) w[p][t] = s1[b][p][cl(l - 3 + t)];
+            const double dnR = r2 - 1 >= 0 ? a2R : A.parity * a1R, dnI = r2 - 1 >= 0 ? a2I : A.parity * a1I;
+            const double upR = r2 + 1 < nth ? a0R : A.parity * a1R, upI = r2 + 1 < nth ? a0I : A.parity * a1I;
+            const Out o = stage(w, dnR, dnI, upR, upI, r2, 0.75, 0.25, un1, false);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) s2[b][p][l] = o.v[p];
+            c3R = c2R; c3I = c2I; c2R = c1R; c2I = c1I;
+            c1R = o.v[0]; c1I = o.v[1];
+        } else {
+            c3R = c2R; c3I = c2I; c2R = c1R; c2I = c1I;
+        }
+        lds_sync();                                   // u(2) row r - 1 in LDS
+        if (r3 >= k0 && r3 < k1) {
+            // ---- stage 3 at row r - 2: u^{n+1} = 1/3 u^n + 2/3 (u(2) + dt F(u(2)))
+            const int b = r3 & 1;
+            double w[4][6];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int t = 0; t < 6; ++t) w[p][t] = s2[b][p][cl(l - 3 + t)];
+            const double dnR = r3 - 1 >= 0 ? c3R : A.parity * c2R, dnI = r3 - 1 >= 0 ? c3I : A.parity * c2I;
+            const double upR = r3 + 1 < nth ? c1R : A.parity * c2R, upI = r3 + 1 < nth ? c1I : A.parity * c2I;
+            const Out o = stage(w, dnR, dnI, upR, upI, r3, 1.0 / 3.0, 2.0 / 3.0, un2, false);
+            if (out_lane) {
+                const size_t row = (size_t)r3 * nr;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) stb(outp[p] + row, oc, o.v[p]);
+            }
+        }
+        // u^n row r is no longer read: row r + 2 takes its slot
+        if (r + 2 < nstage) {
+            lds_sync();
+            store_row(r & 1);
+            if (r + 3 < nstage) load_row(r + 3);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- stability bound
 // max over points of max(|lam1|, |lam2|)/dx + sqrt(4 A~thth/dtheta^2 + |B~th|/dtheta + |C~|);
 // the values are >= 0, so their bit patterns order like unsigned integers and
@@ -984,6 +1210,32 @@ int launch_stage(const StageArgs& a, int stage, int weight_prec, int chart, void
     TEUK_LAUNCH(TEUK_W_BF16, kChartH)
 #undef TEUK_LAUNCH
     if (!done) return (int)hipErrorInvalidValue;
+    return (int)hipGetLastError();
+}
+
+int blocked_grid()
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, blocked_step_kernel<TEUK_W_FP64>, kWave, 0) !=
+            hipSuccess || per_cu < 1)
+        return 0;
+    return cus * per_cu;
+}
+
+int launch_blocked_step(const StageArgs& a, int weight_prec, void* stream)
+{
+    if (a.nr < 1 || a.nth < 1 || a.nstrips < 1 || a.segs < 1 || a.grid != a.nstrips * a.segs ||
+        (long long)a.nstrips * kBW < a.nr || a.uk == a.out)
+        return (int)hipErrorInvalidValue;
+    (void)hipGetLastError();
+    const dim3 grid((unsigned)a.grid), block(kWave);
+    hipStream_t st = (hipStream_t)stream;
+    if (weight_prec == TEUK_W_FP64)
+        hipLaunchKernelGGL(blocked_step_kernel<TEUK_W_FP64>, grid, block, 0, st, a);
+    else
+        return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();
 }
 

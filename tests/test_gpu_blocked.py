@@ -1,0 +1,126 @@
+"""GPU: temporal blocking (one launch per SSP-RK(3,3) step, the stages of a
+tile fused in LDS) against the three-launch step and the FP64 oracle.
+
+The blocked step runs the same arithmetic per point and stage as the
+three-launch step; the compiler may fuse multiply-adds differently in the two
+kernels, so they agree to rounding (measured: a few ulp after three steps),
+held here to 1e-13 of the state's scale per plane and to the oracle bar
+(whole-state <= 1e-12, planes <= 5e-12).  Cases: ragged
+radial sizes around the 51-point tile (one tile, a tile plus one point,
+several tiles, the 63-point strip of the three-launch kernel), theta sizes
+from 2 rows, tile counts from one tile per strip to one row per tile, both
+pole parities, a = M, the waveform samples, the C2 grid at full size, and
+the configurations not offered."""
+import numpy as np
+import pytest
+
+import paper_2010_04760_amd as T
+import workloads as W
+from oracle import solver as S
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+TOL_PLANE = 5e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def cfg_for(prob, dt, integrator, **kw):
+    return T.make_config(s=prob.s, m=prob.m, a=prob.a, nr=prob.nr, ntheta=prob.nth, x_min=prob.x_min,
+                         x_max=prob.x_max, dt=dt, weno_eps=prob.eps, integrator=integrator, **kw)
+
+
+def run(prob, dt, u0, n, integrator, **kw):
+    with T.Solver(cfg_for(prob, dt, integrator, **kw)) as sv:
+        sv.set_initial(u0)
+        sv.step(n)
+        st = sv.state()
+        inf = sv.info()
+        w = sv.waveform() if kw.get("extract_every") else None
+    return st, inf, w
+
+
+def oracle_errors(g, o):
+    big = max(float(np.max(np.abs(o))), 1e-300)
+    se = float(np.max(np.abs(g - o))) / big
+    pe = [float(np.max(np.abs(g[p] - o[p]))) / max(float(np.max(np.abs(o[p]))), big * 1e-300) for p in range(4)]
+    return se, pe
+
+
+GRIDS = [(7, 2, 0, 0, 0.5), (51, 3, -2, 2, 0.999), (52, 5, 0, 1, 1.0), (63, 4, -2, 1, 0.7), (64, 9, 0, 2, 0.9),
+         (102, 6, -2, 3, 0.999), (153, 17, -2, 0, 0.3), (200, 33, 1, -1, 0.6), (513, 8, 0, 0, 0.5)]
+
+
+@pytest.mark.parametrize("grid", GRIDS)
+def test_equals_three_launch_step_and_oracle(grid):
+    nr, nth, s, m, a = grid
+    say("case blocked", grid)
+    prob = S.Problem(s, m, a, nr, nth, -30.0, 50.0)
+    o = S.TeukOracle(prob)
+    dt = 0.4 * o.dt_bound(1.0)
+    u0 = W.random_state(nr, nth, seed=nr * 3 + nth, smooth=True)
+    ref3, _, _ = run(prob, dt, u0, 3, "rk3")
+    oref, _ = o.evolve(u0, dt, 3)
+    strips = -(-nr // 51)
+    for wg in (0, strips, 2 * strips, strips * nth):
+        got, inf, _ = run(prob, dt, u0, 3, "rk3_blocked", workgroups=wg)
+        d = float(np.max(np.abs(got - ref3)))
+        say("  workgroups", wg, "->", inf.workgroups, "max |blocked - three-launch|", d)
+        se, pe = oracle_errors(got, ref3)
+        assert se <= 1e-13 and max(pe) <= TOL_PLANE, (wg, d, se, pe)
+    se, pe = oracle_errors(got, oref)
+    assert se <= TOL and max(pe) <= TOL_PLANE, (se, pe)
+
+
+def test_waveform_and_counters():
+    say("case blocked waveform")
+    prob = S.Problem(-2, 2, 0.999, 190, 12, -30.0, 50.0)
+    o = S.TeukOracle(prob)
+    dt = 0.4 * o.dt_bound(1.0)
+    u0 = W.random_state(prob.nr, prob.nth, seed=5, smooth=True)
+    kw = dict(x_extract=10.0, extract_every=2, max_samples=8)
+    g3, i3, (t3, w3) = run(prob, dt, u0, 7, "rk3", **kw)
+    gb, ib, (tb, wb) = run(prob, dt, u0, 7, "rk3_blocked", **kw)
+    se, pe = oracle_errors(gb, g3)
+    assert se <= 1e-13 and max(pe) <= TOL_PLANE, (se, pe)
+    assert float(np.max(np.abs(wb - w3))) <= 1e-13 * float(np.max(np.abs(w3)))
+    assert np.array_equal(tb, t3)
+    assert ib.steps == i3.steps == 7 and ib.samples == i3.samples
+
+
+def test_c2_full_size():
+    wl = W.C2
+    say("case blocked C2 full size")
+    prob = S.Problem(wl.s, wl.m, wl.a, wl.nr, wl.nth, wl.x_min, wl.x_max)
+    u0 = W.gaussian_pulse(wl)
+    g3, i3, _ = run(prob, 0.0, u0, 3, "rk3")
+    gb, ib, _ = run(prob, 0.0, u0, 3, "rk3_blocked")
+    say("  tiles", ib.workgroups, "max diff", float(np.max(np.abs(gb - g3))))
+    assert ib.dt == i3.dt
+    se, pe = oracle_errors(gb, g3)
+    assert se <= 1e-13 and max(pe) <= TOL_PLANE, (se, pe)
+    oref, _ = S.TeukOracle(prob).evolve(u0, i3.dt, 3)
+    se, pe = oracle_errors(gb, oref)
+    assert se <= TOL and max(pe) <= TOL_PLANE, (se, pe)
+
+
+def test_not_offered():
+    say("case blocked unsupported")
+    prob = S.Problem(0, 0, 0.5, 64, 4, -10.0, 10.0)
+    for kw in (dict(weight_prec="fp32"), dict(scheme="weno3"), dict(state="dd", weight_prec="dd")):
+        with pytest.raises(T.TeukError) as ei:
+            T.teuk_create(cfg_for(prob, 0.0, "rk3_blocked", **kw))
+        assert ei.value.status == T.TEUK_ERR_UNSUPPORTED
+    ch = T.make_config(s=-2, m=0, a=1.0, nr=101, ntheta=8, x_min=20 / 21, x_max=19.0, chart="H",
+                       integrator="rk3_blocked")
+    with pytest.raises(T.TeukError) as ei:
+        T.teuk_create(ch)
+    assert ei.value.status == T.TEUK_ERR_UNSUPPORTED
+    with T.Solver(cfg_for(prob, 0.0, "rk3_blocked")) as sv, T.Group(2) as g:
+        sv.set_initial(W.random_state(64, 4, seed=1))
+        with pytest.raises(T.TeukError) as ei:
+            g.add(sv)
+        assert ei.value.status == T.TEUK_ERR_UNSUPPORTED
