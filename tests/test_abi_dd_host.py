@@ -56,7 +56,7 @@ def test_dd_validation():
     assert T.teuk_footprint_bytes(T.make_config(**base, weight_prec="dd")) == 0
     assert T.teuk_footprint_bytes(T.make_config(**base, state=2)) == 0
     c = T.make_config(**base)
-    c.integrator = 2
+    c.integrator = 3
     assert T.teuk_footprint_bytes(c) == 0
     with pytest.raises(T.TeukError) as ei:
         T.teuk_create(T.make_config(**base, state="dd", weight_prec="dd", integrator="rk104"))
