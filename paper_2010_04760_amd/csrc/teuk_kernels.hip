@@ -559,7 +559,7 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
 //         i.e. vmcnt <= (12 + it) at i = 0 and vmcnt <= 2 it for i >= 1,
 //         it = loads per iteration (16 later stages, 12 otherwise);
 //     before the stores: u^n of row i has landed, vmcnt <= 12.
-template <int WP, int kMode>
+template <int WP, int kMode, bool kLevel>
 __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, int strip, int k0, int k1, int dir)
 {
     const int l = threadIdx.x;
@@ -626,6 +626,20 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
 
     const double (*sr)[4][kRowP] = reinterpret_cast<const double (*)[4][kRowP]>(ring);
     for (int i = 0; i < n; ++i) {
+        // Waves of one SIMD issue oldest first.  When every workgroup of the
+        // launch is resident from the start (kLevel: the single-solve launch),
+        // the oldest wave of a SIMD would end its segment long before the
+        // youngest (measured: 15 us against 30 us), leaving the SIMD with one
+        // or two waves for the last third of the launch.  Lowering a wave's
+        // priority as it advances lets the younger waves keep up, and the
+        // segments end closer together.  A launch whose tiles are dispatched
+        // as slots free up (the batched launch) measured slower with it.
+        if constexpr (kLevel) {
+            if (i == 0) __builtin_amdgcn_s_setprio(3);
+            else if (i == 2) __builtin_amdgcn_s_setprio(2);
+            else if (i == 4) __builtin_amdgcn_s_setprio(1);
+            else if (i == 6) __builtin_amdgcn_s_setprio(0);
+        }
         const int k = first + dir * i;
         const size_t row = (size_t)k * nr;
         const double sn2 = tt[kSn2 * nth + k];
@@ -728,11 +742,11 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
 // staging ring (chart H).
 constexpr unsigned kLdsBytes = kRing * kSlotBytes;   // 9216 >= 2 * 4 * kRow * 8
 
-template <int WP, int kMode, int kChart>
+template <int WP, int kMode, int kChart, bool kLevel = false>
 __device__ __forceinline__ void march(const StageArgs& A, char* lds, int strip, int k0, int k1, int dir)
 {
     if constexpr (kChart == kChartT)
-        march_strip_t<WP, kMode>(A, lds, strip, k0, k1, dir);
+        march_strip_t<WP, kMode, kLevel>(A, lds, strip, k0, k1, dir);
     else
         march_strip<WP, kMode, kChart>(A, reinterpret_cast<double (*)[4][kRow]>(lds), strip, k0, k1, dir);
 }
@@ -744,7 +758,7 @@ __device__ __forceinline__ void run_tile(const StageArgs& A, char* lds, int rank
     const int seg = rank - strip * A.segs;
     const int k0 = (int)((long long)A.nth * seg / A.segs);
     const int k1 = (int)((long long)A.nth * (seg + 1) / A.segs);
-    if (k1 > k0) march<WP, kMode, kChart>(A, lds, strip, k0, k1, (seg & 1) ? -1 : 1);
+    if (k1 > k0) march<WP, kMode, kChart, true>(A, lds, strip, k0, k1, (seg & 1) ? -1 : 1);
 }
 
 // Ranks are dealt so that each XCD (which receives every eighth workgroup id)
