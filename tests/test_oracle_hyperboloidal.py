@@ -11,7 +11,8 @@
   continuum operator vanish and the discrete right-hand side converge to zero
   at the WENO order;
 * the speeds: lam1 <= 0 everywhere, lam2 has the sign of Delta;
-* the horizon interpolation weights are exact on cubics.
+* the horizon interpolation weights are exact on cubics, and so is the
+  horizon sampler (Phi_H, d_rho Phi_H at rho_H) on fields cubic in rho.
 """
 import mpmath as mp
 import numpy as np
@@ -253,3 +254,40 @@ def test_horizon_weights_exact_on_cubics():
             vals = np.array([p(z) for z in (-1.0, 0.0, 1.0, 2.0)])
             assert abs(vals @ w - p(xi)) < 1e-13
             assert abs(vals @ dw - dp(xi)) < 1e-13
+
+
+@pytest.mark.parametrize("a, start_on_horizon", [(1.0, True), (0.6, False)])
+def test_horizon_samples_exact_on_cubic_fields(a, start_on_horizon):
+    """Phi_H and d_rho Phi_H of the oracle's horizon sampler, for a field that
+    is a cubic in rho on every theta row, against the cubic's value and
+    derivative at rho_H = S r+ / (r+ + S), r+ = M + sqrt(M^2 - a^2) (the outer
+    Kerr horizon, M = 1): pins the horizon location, the node offset, the
+    division by the radial step and the pairing of the real and imaginary
+    planes."""
+    rp = 1.0 + np.sqrt(1.0 - a * a)
+    rho_h = SS * rp / (rp + SS)
+    x0 = rho_h if start_on_horizon else 0.7 * rho_h
+    prob = S.Problem(-2, 0, a, 81, 5, x0, SS - 0.5, chart="H", S=SS)
+    o = S.TeukOracle(prob)
+    x = prob.x()
+    rng = np.random.default_rng(7)
+    cr = rng.standard_normal((prob.nth, 4))
+    ci = rng.standard_normal((prob.nth, 4))
+
+    def cubic(c, z):
+        return c[:, 0:1] + c[:, 1:2] * z + c[:, 2:3] * z**2 + c[:, 3:4] * z**3
+
+    def dcubic(c, z):
+        return c[:, 1] + 2 * c[:, 2] * z + 3 * c[:, 3] * z**2
+
+    u = np.zeros((4, prob.nth, prob.nr))
+    u[0] = cubic(cr, x[None, :])
+    u[1] = cubic(ci, x[None, :])
+    u[2] = rng.standard_normal((prob.nth, prob.nr))
+    u[3] = rng.standard_normal((prob.nth, prob.nr))
+    ph, dph = o.horizon(u)
+    want = cubic(cr, np.array([[rho_h]]))[:, 0] + 1j * cubic(ci, np.array([[rho_h]]))[:, 0]
+    dwant = dcubic(cr, rho_h) + 1j * dcubic(ci, rho_h)
+    scale = 1.0 + float(np.max(np.abs(want)))
+    assert np.max(np.abs(ph - want)) < 1e-12 * scale
+    assert np.max(np.abs(dph - dwant)) < 1e-10 * scale
