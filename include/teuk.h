@@ -111,8 +111,8 @@ enum { TEUK_S_FP64 = 0, TEUK_S_DD = 1 };
 enum { TEUK_RK_SSP33 = 0, TEUK_RK_SSP104 = 1, TEUK_RK_SSP33_BLOCKED = 2 };
 /* TEUK_RK_SSP33_BLOCKED: SSP-RK(3,3), each step one launch that computes all
  * three stages of a tile (temporal blocking): u(1) and u(2) stay in LDS and
- * HBM sees one read of u^n and one write of u^{n+1} per point.  Tiles are 51
- * radial points by about nth / segs rows; a tile recomputes the stage-1
+ * HBM sees one read of u^n and one write of u^{n+1} per point.  Tiles are 114
+ * radial points by about nth / segs rows (one workgroup of two waves); a tile recomputes the stage-1
  * values two rows and six points beyond its outputs and the stage-2 values one
  * row and three points beyond (workgroups, when > 0, sets the tile count).
  * The result is the same arithmetic as TEUK_RK_SSP33, point by point.

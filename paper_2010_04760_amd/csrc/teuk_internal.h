@@ -89,7 +89,7 @@ int launch_coef_dump(const double* rtab, const double* ttab, const double* ctab,
 // weights) from a.uk into a.out (distinct buffers), tiles of kBlockedPoints
 // radial points by a.nth / a.segs rows, a.grid = a.nstrips * a.segs
 // workgroups.  blocked_grid() is the resident workgroup count.
-constexpr int kBlockedPoints = 51;
+constexpr int kBlockedPoints = 114;
 int blocked_grid();
 int launch_blocked_step(const StageArgs& a, int weight_prec, void* stream);
 // Comparison schemes (TEUK_SCHEME_WENO3 / TEUK_SCHEME_FD6KO8, FP64): one stage,

@@ -817,32 +817,43 @@ __global__ __launch_bounds__(kWave) void group_stage_kernel(const StageArgs* __r
 
 // ---------------------------------------------------------------- temporal blocking
 // One whole SSP-RK(3,3) step per launch (tortoise chart): the three stages of a
-// tile are computed in one wave, the intermediate states u(1) and u(2) never
-// leave LDS, and HBM sees one read of u^n and one write of u^{n+1} per point
-// (64 B instead of 256 B per point-step).  The price is recomputation at the
-// tile edges: a stage needs three radial neighbours and one theta neighbour of
-// its input on each side, so
-//   - lane l of a wave stands for radial point j = 51 strip - 6 + l in all three
-//     stages; stage 1 is valid on lanes 0..62, stage 2 on 3..59, stage 3 (the
-//     output) on 6..56, i.e. 51 outputs per 64 lanes;
+// tile are computed in one workgroup of two waves, the intermediate states u(1)
+// and u(2) never leave LDS, and HBM sees one read of u^n and one write of
+// u^{n+1} per point (64 B instead of 256 B per point-step).  The price is
+// recomputation at the tile edges: a stage needs three radial neighbours and one
+// theta neighbour of its input on each side, so
+//   - a tile spans 127 radial points q = 0 .. 126, point q standing for
+//     j = 114 strip - 6 + q in all three stages.  Wave 0 holds points 0..63 and
+//     wave 1 points 63..126: the two overlap by one point so that every point
+//     but the last of each wave finds its j + 1/2 flux in the next lane of its
+//     own wave.  Point 63 is computed by wave 1 (wave 0's copy, lacking that
+//     flux, is never stored);
+//   - stage 1 is valid on points 0..125, stage 2 on 3..122 and stage 3 (the
+//     output) on 6..119: 114 outputs per 128 lanes;
 //   - a tile of final rows [k0, k1) computes stage 1 on [k0-2, k1+2) and stage
 //     2 on [k0-1, k1+1) (clipped to the grid; a pole takes the parity ghost of
 //     the stage's own input, as in the three-launch step).
-// The wave marches the rows upward: at step r it stages u^n row r+1 (LDS),
+// The workgroup marches the rows upward: at step r it stages u^n row r+1 (LDS),
 // computes u(1) at row r, u(2) at row r-1 and u^{n+1} at row r-2.  Radial
-// ghosts of u(1) and u(2) are the end values, read by clamping the lane index
-// to the lanes inside the grid.  The arithmetic of each point and stage is the
-// three-launch stage kernel's, term for term.
-constexpr int kBW = 51;     // output points per wave
-constexpr int kBLead = 6;   // lane of the first output point
+// ghosts of u(1) and u(2) are the end values, read by clamping the point index
+// to the points inside the grid.  The arithmetic of each point and stage is
+// the three-launch stage kernel's, term for term.
+constexpr int kBW = 114;                 // output points per tile
+constexpr int kBLead = 6;                // first output point of a tile
+constexpr int kBThreads = 2 * kWave;     // two waves
+constexpr int kBPts = 2 * kWave - 1;     // points of a tile (the waves share one)
+constexpr int kBStage = kBPts + 6;       // staged u^n positions: q - 3 .. q + 3 of every point
+static_assert(kBLead + kBW + kBLead + 1 == kBPts, "tile geometry");
 
 template <int WP>
-__global__ __launch_bounds__(kWave) void blocked_step_kernel(StageArgs A)
+__global__ __launch_bounds__(kBThreads) void blocked_step_kernel(StageArgs A)
 {
-    __shared__ double sn[2][4][kRowP];   // u^n rows (positions j - 3 .. j + 65 of lane 0's point)
-    __shared__ double s1[2][4][kWave];   // u(1) rows, one value per lane
-    __shared__ double s2[2][4][kWave];   // u(2) rows
-    const int l = threadIdx.x;
+    __shared__ double sn[3][4][kBStage];   // u^n rows (three-slot ring), position s = point p0 - 3 + s
+    __shared__ double s1[2][4][kBPts];     // u(1) rows, one value per point
+    __shared__ double s2[2][4][kBPts];     // u(2) rows
+    const int tid = threadIdx.x;
+    const int l = tid - (tid >= kWave ? 1 : 0);          // point of this lane in the tile
+    const bool dup = tid == kWave - 1;                    // wave 0's copy of point 63
     const int nr = A.nr, nth = A.nth;
     const long long P = A.plane;
     const int rank = xcd_rank((int)blockIdx.x, (int)gridDim.x);
@@ -850,16 +861,16 @@ __global__ __launch_bounds__(kWave) void blocked_step_kernel(StageArgs A)
     const int seg = rank - strip * A.segs;
     const int k0 = (int)((long long)nth * seg / A.segs);
     const int k1 = (int)((long long)nth * (seg + 1) / A.segs);
-    if (k1 <= k0) return;
-    const int p0 = strip * kBW - kBLead;                 // point of lane 0
+    if (k1 <= k0) return;                                 // uniform over the workgroup
+    const int p0 = strip * kBW - kBLead;                  // grid point of tile point 0
     const int j = p0 + l;
     const int jc = clampi(j, 0, nr - 1);
     const unsigned oc = (unsigned)jc * 8u;
-    const unsigned oa = (unsigned)clampi(p0 - 3 + l, 0, nr - 1) * 8u;     // staged position l
-    const unsigned ob = (unsigned)clampi(p0 + 61 + l, 0, nr - 1) * 8u;    // staged position 64 + l, l < 5
-    const bool halo = l < 5;
-    const int lo = clampi(-p0, 0, kWave - 1), hi = clampi(nr - 1 - p0, 0, kWave - 1);   // lanes inside the grid
-    const bool out_lane = l >= kBLead && l < kBLead + kBW && j < nr;
+    const unsigned oa = (unsigned)clampi(p0 - 3 + tid, 0, nr - 1) * 8u;               // staged position tid
+    const unsigned ob = (unsigned)clampi(p0 - 3 + kBThreads + tid, 0, nr - 1) * 8u;   // position 128 + tid
+    const bool halo = tid < kBStage - kBThreads;
+    const int lo = clampi(-p0, 0, kBPts - 1), hi = clampi(nr - 1 - p0, 0, kBPts - 1);   // points inside the grid
+    const bool out_lane = !dup && l >= kBLead && l < kBLead + kBW && j < nr;
     const double* ukp[4] = {A.uk, A.uk + P, A.uk + 2 * P, A.uk + 3 * P};
     double* outp[4] = {A.out, A.out + P, A.out + 2 * P, A.out + 3 * P};
     double rt[kNRT];
@@ -884,10 +895,10 @@ __global__ __launch_bounds__(kWave) void blocked_step_kernel(StageArgs A)
     };
     auto store_row = [&](int b) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) sn[b][p][l] = xa[p];
+        for (int p = 0; p < 4; ++p) sn[b][p][tid] = xa[p];
         if (halo) {
 #pragma unroll
-            for (int p = 0; p < 4; ++p) sn[b][p][kWave + l] = xb[p];
+            for (int p = 0; p < 4; ++p) sn[b][p][kBThreads + tid] = xb[p];
         }
     };
     auto cl = [&](int q) { return clampi(q, lo, hi); };
@@ -951,11 +962,17 @@ __global__ __launch_bounds__(kWave) void blocked_step_kernel(StageArgs A)
             nbI = A.parity * ldb(ukp[1] + (size_t)r1lo * nr, oc);
         }
     }
+    // u^n row k sits in ring slot k mod 3: row r + 2 is stored during step r
+    // into the slot of row r - 1, which every wave finished reading before
+    // the barrier that opens step r, so one barrier per row orders all LDS
+    // traffic (u(1) and u(2) rows are likewise read one step after they are
+    // written, into slots last read one step before).
+    int sc = r1lo % 3;                            // slot of row r
     load_row(r1lo);
-    store_row(r1lo & 1);
+    store_row(sc);
     if (r1lo + 1 < nstage) {
         load_row(r1lo + 1);
-        store_row((r1lo + 1) & 1);
+        store_row(sc == 2 ? 0 : sc + 1);
     }
     if (r1lo + 2 < nstage) load_row(r1lo + 2);
 
@@ -972,7 +989,8 @@ __global__ __launch_bounds__(kWave) void blocked_step_kernel(StageArgs A)
         else if (it == q1) __builtin_amdgcn_s_setprio(2);
         else if (it == q2) __builtin_amdgcn_s_setprio(1);
         else if (it == q3) __builtin_amdgcn_s_setprio(0);
-        lds_sync();                                   // u^n rows r, r+1 staged
+        lds_sync();                                   // u^n rows r, r+1 staged; u(1) row r-1, u(2) row r-2
+        const int su = sc == 2 ? 0 : sc + 1;          // slot of row r + 1
         const int r2 = r - 1, r3 = r - 2;
         if (r < r1hi) {
             // ---- stage 1 at row r: u(1) = u^n + dt F(u^n)
@@ -981,19 +999,21 @@ __global__ __launch_bounds__(kWave) void blocked_step_kernel(StageArgs A)
 #pragma unroll
             for (int p = 0; p < 4; ++p)
 #pragma unroll
-                for (int t = 0; t < 6; ++t) w[p][t] = sn[b][p][l + t];
+                for (int t = 0; t < 6; ++t) w[p][t] = sn[sc][p][l + t];
             double upR, upI;
             if (r + 1 < nth) {
-                upR = sn[b ^ 1][0][l + 3];
-                upI = sn[b ^ 1][1][l + 3];
+                upR = sn[su][0][l + 3];
+                upI = sn[su][1][l + 3];
             } else {
                 upR = A.parity * w[0][3];
                 upI = A.parity * w[1][3];
             }
             const double none[4] = {0, 0, 0, 0};
             const Out o = stage(w, nbR, nbI, upR, upI, r, 0.0, 1.0, none, true);
+            if (!dup) {
 #pragma unroll
-            for (int p = 0; p < 4; ++p) s1[b][p][l] = o.v[p];
+                for (int p = 0; p < 4; ++p) s1[b][p][l] = o.v[p];
+            }
             un2[0] = un1[0]; un2[1] = un1[1]; un2[2] = un1[2]; un2[3] = un1[3];
             un1[0] = un0[0]; un1[1] = un0[1]; un1[2] = un0[2]; un1[3] = un0[3];
 #pragma unroll
@@ -1007,7 +1027,6 @@ __global__ __launch_bounds__(kWave) void blocked_step_kernel(StageArgs A)
             un1[0] = un0[0]; un1[1] = un0[1]; un1[2] = un0[2]; un1[3] = un0[3];
             a2R = a1R; a2I = a1I; a1R = a0R; a1I = a0I;
         }
-        lds_sync();                                   // u(1) row r in LDS
         if (r2 >= r2lo && r2 < r2hi) {
             // ---- stage 2 at row r - 1: u(2) = 3/4 u^n + 1/4 (u(1) + dt F(u(1)))
             const int b = r2 & 1;
@@ -1019,14 +1038,15 @@ __global__ __launch_bounds__(kWave) void blocked_step_kernel(StageArgs A)
             const double dnR = r2 - 1 >= 0 ? a2R : A.parity * a1R, dnI = r2 - 1 >= 0 ? a2I : A.parity * a1I;
             const double upR = r2 + 1 < nth ? a0R : A.parity * a1R, upI = r2 + 1 < nth ? a0I : A.parity * a1I;
             const Out o = stage(w, dnR, dnI, upR, upI, r2, 0.75, 0.25, un1, false);
+            if (!dup) {
 #pragma unroll
-            for (int p = 0; p < 4; ++p) s2[b][p][l] = o.v[p];
+                for (int p = 0; p < 4; ++p) s2[b][p][l] = o.v[p];
+            }
             c3R = c2R; c3I = c2I; c2R = c1R; c2I = c1I;
             c1R = o.v[0]; c1I = o.v[1];
         } else {
             c3R = c2R; c3I = c2I; c2R = c1R; c2I = c1I;
         }
-        lds_sync();                                   // u(2) row r - 1 in LDS
         if (r3 >= k0 && r3 < k1) {
             // ---- stage 3 at row r - 2: u^{n+1} = 1/3 u^n + 2/3 (u(2) + dt F(u(2)))
             const int b = r3 & 1;
@@ -1044,12 +1064,12 @@ __global__ __launch_bounds__(kWave) void blocked_step_kernel(StageArgs A)
                 for (int p = 0; p < 4; ++p) stb(outp[p] + row, oc, o.v[p]);
             }
         }
-        // u^n row r is no longer read: row r + 2 takes its slot
+        // row r + 2 into the slot of row r - 1
         if (r + 2 < nstage) {
-            lds_sync();
-            store_row(r & 1);
+            store_row(sc == 0 ? 2 : sc - 1);
             if (r + 3 < nstage) load_row(r + 3);
         }
+        sc = su;
     }
 }
 
@@ -1244,7 +1264,7 @@ int blocked_grid()
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, blocked_step_kernel<TEUK_W_FP64>, kWave, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, blocked_step_kernel<TEUK_W_FP64>, kBThreads, 0) !=
             hipSuccess || per_cu < 1)
         return 0;
     return cus * per_cu;
@@ -1256,7 +1276,7 @@ int launch_blocked_step(const StageArgs& a, int weight_prec, void* stream)
         (long long)a.nstrips * kBW < a.nr || a.uk == a.out)
         return (int)hipErrorInvalidValue;
     (void)hipGetLastError();
-    const dim3 grid((unsigned)a.grid), block(kWave);
+    const dim3 grid((unsigned)a.grid), block(kBThreads);
     hipStream_t st = (hipStream_t)stream;
     if (weight_prec == TEUK_W_FP64)
         hipLaunchKernelGGL(blocked_step_kernel<TEUK_W_FP64>, grid, block, 0, st, a);

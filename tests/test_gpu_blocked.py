@@ -6,11 +6,11 @@ three-launch step; the compiler may fuse multiply-adds differently in the two
 kernels, so they agree to rounding (measured: a few ulp after three steps),
 held here to 1e-13 of the state's scale per plane and to the oracle bar
 (whole-state <= 1e-12, planes <= 5e-12).  Cases: ragged
-radial sizes around the 51-point tile (one tile, a tile plus one point,
-several tiles, the 63-point strip of the three-launch kernel), theta sizes
-from 2 rows, tile counts from one tile per strip to one row per tile, both
-pole parities, a = M, the waveform samples, the C2 grid at full size, and
-the configurations not offered."""
+radial sizes around the 114-point tile (smaller than one tile, one tile, a
+tile plus one point, the 127 points one workgroup spans, two tiles and one
+more point, several tiles), theta sizes from 2 rows, tile counts from one
+tile per strip to one row per tile, both pole parities, a = M, the waveform
+samples, the C2 grid at full size, and the configurations not offered."""
 import numpy as np
 import pytest
 
@@ -50,8 +50,10 @@ def oracle_errors(g, o):
     return se, pe
 
 
-GRIDS = [(7, 2, 0, 0, 0.5), (51, 3, -2, 2, 0.999), (52, 5, 0, 1, 1.0), (63, 4, -2, 1, 0.7), (64, 9, 0, 2, 0.9),
-         (102, 6, -2, 3, 0.999), (153, 17, -2, 0, 0.3), (200, 33, 1, -1, 0.6), (513, 8, 0, 0, 0.5)]
+TILE = 114     # output points per tile
+
+GRIDS = [(7, 2, 0, 0, 0.5), (63, 3, -2, 2, 0.999), (114, 5, 0, 1, 1.0), (115, 4, -2, 1, 0.7), (127, 9, 0, 2, 0.9),
+         (229, 6, -2, 3, 0.999), (300, 17, -2, 0, 0.3), (200, 33, 1, -1, 0.6), (513, 8, 0, 0, 0.5)]
 
 
 @pytest.mark.parametrize("grid", GRIDS)
@@ -64,7 +66,7 @@ def test_equals_three_launch_step_and_oracle(grid):
     u0 = W.random_state(nr, nth, seed=nr * 3 + nth, smooth=True)
     ref3, _, _ = run(prob, dt, u0, 3, "rk3")
     oref, _ = o.evolve(u0, dt, 3)
-    strips = -(-nr // 51)
+    strips = -(-nr // TILE)
     for wg in (0, strips, 2 * strips, strips * nth):
         got, inf, _ = run(prob, dt, u0, 3, "rk3_blocked", workgroups=wg)
         d = float(np.max(np.abs(got - ref3)))
