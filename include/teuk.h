@@ -292,7 +292,8 @@ teuk_status teuk_host_coefficients(const teuk_config* cfg, double* out, size_t c
  * Separating exp(i m phi~) (Sec. 3) leaves one 2+1D problem per (s, m) mode
  * and per background; such solves share nothing, so a group advances all of
  * its members in one stage-kernel launch per SSP-RK stage (one per weight
- * precision present) instead of three launches per member per step.  Each
+ * precision present and per cache block of members) instead of three
+ * launches per member per step.  Each
  * member keeps its own grid, coefficients, dt, waveform ring and counters, and
  * its results are bitwise those of teuk_step on the member alone: the tiles
  * of a member run the single-solve stage arithmetic unchanged.
@@ -307,8 +308,8 @@ typedef struct teuk_group teuk_group;   /* opaque; owned by the library */
 
 typedef struct {
     int32_t members;         /* solvers in the group                                 */
-    int32_t classes;         /* weight precisions present (= launches per stage)     */
-    int64_t workgroups;      /* workgroups per stage, summed over the launches        */
+    int32_t classes;         /* (weight precision, chart) classes present            */
+    int64_t workgroups;      /* workgroups per stage, summed over the launches (blocks) */
     int64_t tiles;           /* tiles (one strip x one theta segment) per stage        */
     int64_t units;           /* strip-rows per stage (63 radial points x 1 theta row)  */
     int64_t points;          /* grid points over all members                          */
@@ -321,7 +322,11 @@ typedef struct {
  * numbered segment by segment with the strip index fastest, so that the
  * workgroups in flight march neighbouring strips over the same rows.  Each
  * stage launch runs one workgroup per tile (workgroups = 0) or `workgroups`
- * workgroups that take the tiles round-robin.
+ * workgroups that take the tiles round-robin.  Members of one weight precision
+ * and chart are launched together in cache blocks of consecutive members whose
+ * footprints (teuk_footprint_bytes) sum to at most 256 MiB; teuk_group_step
+ * runs all its steps on one block before the next, so that a block's state
+ * stays largely in the GPU's last-level cache between stages.
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE; teuk_group_last_error(NULL)
  * says why. */
 teuk_status teuk_group_create(const teuk_device_ctx* ctx, int32_t max_members, int32_t workgroups,
@@ -339,7 +344,11 @@ teuk_status teuk_group_remove(teuk_group* g, teuk_solver* h);
 
 /* Advance every member nsteps SSP-RK(3,3) steps with its own dt, sampling each
  * member's waveform as teuk_step does.  Asynchronous on the group's stream.
- * An empty group or nsteps = 0 is a no-op.  Errors: INVALID_ARG, DEVICE. */
+ * The steps run block by block (all nsteps on one cache block of members,
+ * then the next), so on an error some members may have advanced and others
+ * not; each member's step and sample counters stay consistent with its own
+ * state.  An empty group or nsteps = 0 is a no-op.  Errors: INVALID_ARG,
+ * DEVICE. */
 teuk_status teuk_group_step(teuk_group* g, int64_t nsteps);
 
 /* Group information (no synchronisation).  Errors: INVALID_ARG. */

@@ -51,6 +51,31 @@ struct teuk_solver {
 
 constexpr int kClasses = 8;   // (weight precision, chart) pairs
 
+// Group members are stepped in cache blocks: consecutive members of one
+// (weight precision, chart) class whose solver footprints sum to at most this
+// many bytes (a member larger than that is a block of its own).  A block runs
+// all of a teuk_group_step's steps before the next block starts, so much of
+// its state stays in the GPU's 256 MB last-level cache from one stage launch
+// to the next instead of streaming from HBM at every stage.  Measured on the
+// 64-solve batched workload (9.2 GB of footprint): 96 MiB blocks 5.04e10
+// point-updates/s, 224 MiB 5.44e10, 256 MiB 5.56e10, 320 MiB 5.54e10, 448 MiB
+// 5.17e10, one block per class 5.38e10.  Smaller blocks lose more to launches
+// that do not fill the GPU than they gain in cache hits.
+#ifndef TEUK_GROUP_BLOCK_MB
+#define TEUK_GROUP_BLOCK_MB 256
+#endif
+constexpr long long kGroupBlockBytes = (long long)TEUK_GROUP_BLOCK_MB << 20;
+
+// One cache block: members [first, first + n) of the class order (their stage
+// descriptors are consecutive in d_args), tile prefix sums from d_start + start.
+struct GroupBlock {
+    int cls = 0;
+    int first = 0, n = 0;
+    long long tiles = 0, units = 0;
+    size_t start = 0;
+    int grid = 0;
+};
+
 struct teuk_group {
     hipStream_t stream = nullptr;
     int device = 0;
@@ -59,12 +84,11 @@ struct teuk_group {
     int rows = 8;                                   // theta rows per tile (target)
     std::vector<teuk_solver*> mem;                  // insertion order
     StageArgs* d_args = nullptr;                    // [3][cap]: per stage, members by weight precision
-    long long* d_start = nullptr;                   // [8][cap + 1]: tile prefix sums per (precision, chart) class
+    long long* d_start = nullptr;                   // [2 cap + 2]: each block's tile prefix sums, from 0
     std::vector<StageArgs> h_args;
     std::vector<long long> h_start;
-    // launch classes: c = weight_prec + 4 * chart
-    int cls_first[kClasses] = {}, cls_n[kClasses] = {}, cls_grid[kClasses] = {};
-    long long cls_tiles[kClasses] = {}, cls_units[kClasses] = {};
+    std::vector<teuk_solver*> order;                // members in class order, block by block
+    std::vector<GroupBlock> blocks;                 // class c = weight_prec + 4 * chart
     long long points = 0;
     std::string err;
 };
@@ -862,29 +886,50 @@ static int group_segs(int nth, int rows)
     return segs;
 }
 
-// Rebuild and upload the members' stage descriptors and tile prefix sums, and
-// size each precision class's launch.  The caller has synchronised the group's
-// stream.
+// Rebuild and upload the members' stage descriptors and tile prefix sums, cut
+// each (precision, chart) class into cache blocks and size each block's launch.
+// The caller has synchronised the group's stream.
 static teuk_status group_upload(teuk_group* g)
 {
     const int cap = g->cap;
     int idx = 0;
+    size_t soff = 0;
     g->points = 0;
+    g->order.clear();
+    g->blocks.clear();
     for (int c = 0; c < kClasses; ++c) {
-        g->cls_first[c] = idx;
-        g->cls_n[c] = 0;
-        long long* start = &g->h_start[(size_t)c * (cap + 1)];
-        long long tiles = 0, units = 0;
-        start[0] = 0;
+        GroupBlock blk;
+        long long bytes = 0;
+        auto open_block = [&]() {
+            blk = GroupBlock();
+            blk.cls = c;
+            blk.first = idx;
+            blk.start = soff;
+            g->h_start[soff] = 0;
+            bytes = 0;
+        };
+        auto close_block = [&]() {
+            blk.grid = (int)(g->workgroups > 0 && g->workgroups < blk.tiles ? g->workgroups : blk.tiles);
+            g->blocks.push_back(blk);
+            soff += (size_t)blk.n + 1;
+        };
+        open_block();
         for (teuk_solver* h : g->mem) {
             if (h->cfg.weight_prec + 4 * h->cfg.chart != c) continue;
+            if (blk.n > 0 && bytes + (long long)h->bytes > kGroupBlockBytes) {
+                close_block();
+                open_block();
+            }
             StageArgs a = stage_args(h);
             a.segs = group_segs(h->cfg.ntheta, g->rows);
             a.grid = 0;                                  // set per launch
-            tiles += (long long)h->nstrips * a.segs;
-            units += (long long)h->nstrips * h->cfg.ntheta;
-            const int k = g->cls_n[c];
-            start[k + 1] = tiles;
+            blk.tiles += (long long)h->nstrips * a.segs;
+            blk.units += (long long)h->nstrips * h->cfg.ntheta;
+            if (blk.tiles > (1LL << 31) - 1)
+                return gfail(g, TEUK_ERR_CAPACITY, "group block too large for one launch (2^31 - 1 tiles)");
+            ++blk.n;
+            g->h_start[soff + blk.n] = blk.tiles;
+            bytes += (long long)h->bytes;
             // stage 1: u1 = u + dt F(u)
             a.uk = a.un = h->u[0]; a.out = h->u[1]; a.ca = 0.0; a.cb = 1.0;
             g->h_args[0 * (size_t)cap + idx] = a;
@@ -895,15 +940,10 @@ static teuk_status group_upload(teuk_group* g)
             a.uk = h->u[2]; a.un = h->u[0]; a.out = h->u[0]; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0;
             g->h_args[2 * (size_t)cap + idx] = a;
             g->points += h->plane;
-            ++g->cls_n[c];
+            g->order.push_back(h);
             ++idx;
         }
-        if (tiles > (1LL << 31) - 1)
-            return gfail(g, TEUK_ERR_CAPACITY, "group too large for one launch (2^31 - 1 tiles)");
-        g->cls_tiles[c] = tiles;
-        g->cls_units[c] = units;
-        g->cls_grid[c] = 0;
-        if (tiles > 0) g->cls_grid[c] = (int)(g->workgroups > 0 && g->workgroups < tiles ? g->workgroups : tiles);
+        if (blk.n > 0) close_block();
     }
     int e = (int)hipMemcpyAsync(g->d_args, g->h_args.data(), g->h_args.size() * sizeof(StageArgs),
                                 hipMemcpyHostToDevice, g->stream);
@@ -930,7 +970,7 @@ teuk_status teuk_group_create(const teuk_device_ctx* ctx, int32_t max_members, i
     g->workgroups = workgroups;
     g->rows = rows_per_tile > 0 ? rows_per_tile : 8;
     g->h_args.assign(3 * (size_t)max_members, StageArgs{});
-    g->h_start.assign(kClasses * ((size_t)max_members + 1), 0);
+    g->h_start.assign(2 * (size_t)max_members + 2, 0);   // members + blocks + 1 entries at most
     int e = (int)hipMalloc(&g->d_args, g->h_args.size() * sizeof(StageArgs));
     if (!e) e = (int)hipMalloc(&g->d_start, g->h_start.size() * sizeof(long long));
     if (e) {
@@ -990,22 +1030,22 @@ teuk_status teuk_group_step(teuk_group* g, int64_t nsteps)
     if (nsteps < 0) return gfail(g, TEUK_ERR_INVALID_ARG, "nsteps must be >= 0");
     if (g->mem.empty()) return TEUK_OK;
     const size_t cap = (size_t)g->cap;
-    for (int64_t n = 0; n < nsteps; ++n) {
-        for (int stage = 1; stage <= 3; ++stage) {
-            for (int c = 0; c < kClasses; ++c) {
-                if (g->cls_n[c] == 0) continue;
-                const int e = launch_group_stage(g->d_args + (stage - 1) * cap + g->cls_first[c],
-                                                 g->d_start + c * (cap + 1), g->cls_n[c], g->cls_tiles[c],
-                                                 g->cls_grid[c], stage, c % 4, c / 4, g->stream);
+    // block by block: a block runs all nsteps steps before the next starts
+    for (const GroupBlock& b : g->blocks) {
+        for (int64_t n = 0; n < nsteps; ++n) {
+            for (int stage = 1; stage <= 3; ++stage) {
+                const int e = launch_group_stage(g->d_args + (stage - 1) * cap + b.first, g->d_start + b.start, b.n,
+                                                 b.tiles, b.grid, stage, b.cls % 4, b.cls / 4, g->stream);
                 if (e) return gfail(g, TEUK_ERR_DEVICE, std::string("group stage launch: ") +
                                                            hipGetErrorString((hipError_t)e));
             }
-        }
-        for (teuk_solver* h : g->mem) {
-            ++h->steps;
-            if (h->cfg.extract_every > 0 && h->steps % h->cfg.extract_every == 0) {
-                teuk_status st = record_sample(h);
-                if (st != TEUK_OK) return gfail(g, st, h->err);
+            for (int k = b.first; k < b.first + b.n; ++k) {
+                teuk_solver* h = g->order[(size_t)k];
+                ++h->steps;
+                if (h->cfg.extract_every > 0 && h->steps % h->cfg.extract_every == 0) {
+                    teuk_status st = record_sample(h);
+                    if (st != TEUK_OK) return gfail(g, st, h->err);
+                }
             }
         }
     }
@@ -1021,11 +1061,13 @@ teuk_status teuk_group_info(const teuk_group* g, teuk_group_info_t* info)
     info->workgroups = 0;
     info->tiles = 0;
     info->units = 0;
-    for (int c = 0; c < kClasses; ++c) {
-        info->classes += g->cls_n[c] > 0;
-        info->workgroups += g->cls_grid[c];
-        info->tiles += g->cls_tiles[c];
-        info->units += g->cls_units[c];
+    bool seen[kClasses] = {};
+    for (const GroupBlock& b : g->blocks) {
+        info->classes += !seen[b.cls];
+        seen[b.cls] = true;
+        info->workgroups += b.grid;
+        info->tiles += b.tiles;
+        info->units += b.units;
     }
     info->points = g->points;
     return TEUK_OK;
