@@ -369,8 +369,9 @@ class Solver:
 
 
 class Group:
-    """Independent solves advanced together (one launch per RK stage for all
-    members).  Members are ``Solver`` objects on the group's stream; the group
+    """Independent solves advanced together (one launch per RK stage for each
+    cache block of members, a block running all of a step() call's steps
+    before the next).  Members are ``Solver`` objects on the group's stream; the group
     keeps a reference to each so that their memory outlives membership."""
 
     def __init__(self, max_members: int, workgroups: int = 0, rows_per_tile: int = 0,

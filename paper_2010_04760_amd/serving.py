@@ -2,8 +2,8 @@
 
 Requests (one solve each: background, mode, grid, initial pulse, step count)
 arrive over time.  The server keeps the admitted solves resident in HBM as one
-group (the C ABI's group extension: one stage launch per SSP-RK stage for all
-members), admits waiting requests first-come first-served while their
+group (the C ABI's group extension: one stage launch per SSP-RK stage for each
+cache block of members), admits waiting requests first-come first-served while their
 footprint (teuk_footprint_bytes) fits the HBM budget, steps the group in
 chunks so that arrivals can join between chunks, and on completion copies the
 request's waveform out and frees its memory.  Every solve's arithmetic is the
