@@ -139,6 +139,35 @@ def test_member_against_oracle():
     assert err <= 1e-12
 
 
+def test_cache_blocks_bitwise():
+    """Members large enough that the group cuts them into several cache blocks
+    (footprints of about 100 MB against 256 MiB per block), in two precision
+    classes with different sampling intervals: every member, stepped by the
+    group in two calls, equals the same solve alone, bitwise."""
+    say("case group cache blocks")
+    spec = [(8192, 128, -2, 2, 0.999, "fp64", 2), (8192, 128, 0, 1, 0.7, "fp32", 3),
+            (8000, 130, -2, 0, 0.5, "fp64", 1), (8192, 120, 0, 3, 0.9, "fp32", 0),
+            (8100, 128, -2, 1, 1.0, "fp64", 4), (7000, 140, 0, 0, 0.6, "fp64", 2)]
+    members = [make(*sp, seed=70 + i) for i, sp in enumerate(spec)]
+    fp64_bytes = sum(T.teuk_footprint_bytes(sv.cfg) for (sv, _), sp in zip(members, spec) if sp[5] == "fp64")
+    assert fp64_bytes > 256 << 20          # the FP64 class spans more than one block
+    with T.Group(len(spec)) as g:
+        for sv, _ in members:
+            g.add(sv)
+        g.step(2)
+        g.step(3)
+        torch.cuda.synchronize()
+        got = [snapshot(sv) for sv, _ in members]
+    say("   FP64 class footprint", fp64_bytes >> 20, "MiB")
+    for (sv, u0), sp, gs in zip(members, spec, got):
+        sv.close()
+        alone, _ = make(*sp, seed=0)
+        alone.set_initial(u0)
+        alone.step(5)
+        assert_same(gs, snapshot(alone), ("member", sp))
+        alone.close()
+
+
 def test_batched_mix_full_size():
     """The 64-solve mix at full size, 2 steps in one group; four members (the
     largest, the smallest and two others) against the same solves alone."""
