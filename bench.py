@@ -617,7 +617,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one MI355X only: this build has no multi-GPU path "
+        print("bench.py measures one MI355X only: the library has no multi-GPU path "
               "(a single solve would shard into radial slabs; see the design notes).", file=sys.stderr)
         sys.exit(2)
 

@@ -73,7 +73,7 @@ typedef enum {
     TEUK_ERR_DEVICE = -3,         /* a HIP runtime call failed               */
     TEUK_ERR_STATE = -4,          /* call out of order (e.g. step before set_initial) */
     TEUK_ERR_NONFINITE = -5,      /* NaN or Inf found in the state or input   */
-    TEUK_ERR_UNSUPPORTED = -6,    /* valid request this build does not offer  */
+    TEUK_ERR_UNSUPPORTED = -6,    /* valid request the library does not offer */
     TEUK_ERR_CAPACITY = -7        /* output array smaller than the data       */
 } teuk_status;
 

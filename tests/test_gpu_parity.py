@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
 same seeded inputs.
 
-Bar (the benchmark spec: <= 1e-12 max relative error): max |g - o| / max |o| with the
+Bar (<= 1e-12 max relative error): max |g - o| / max |o| with the
 max taken over the whole state u = {Phi_R, Phi_I, pi_R, pi_I} <= 1e-12.  Each
 plane is also held to its own scale, max |g_p - o_p| / max |o_p| <= 5e-12: the
 centred theta second difference amplifies one-ulp differences between two
