@@ -168,6 +168,52 @@ def test_cache_blocks_bitwise():
         alone.close()
 
 
+def test_group_with_hyperboloidal_members():
+    """Members of both charts in one group (tortoise FP64 and FP32, hyperboloidal
+    FP64 and FP16, a = M with the grid starting on the horizon and a = 0.8 with
+    it inside): state, waveform, horizon samples and counters equal each solve
+    alone, bitwise."""
+    say("case group with chart-H members")
+
+    def make_h(nr, nth, a, x_min, weights, every, seed):
+        cfg = T.make_config(s=-2, m=0, a=a, nr=nr, ntheta=nth, x_min=x_min, x_max=19.5, chart="H", S=20.0,
+                            weight_prec=weights, x_extract=19.0, extract_every=every, max_samples=16)
+        sv = T.Solver(cfg)
+        u0 = W.random_state(nr, nth, seed=seed, smooth=True)
+        sv.set_initial(u0)
+        return sv, u0
+
+    spec_h = [(300, 12, 1.0, 20.0 / 21.0, "fp64", 2), (257, 9, 0.8, 1.2, "fp16", 3)]
+    spec_t = [(200, 17, -2, 1, 1.0, "fp64", 1), (513, 8, 0, 2, 0.7, "fp32", 2)]
+    hmem = [make_h(*sp, seed=90 + i) for i, sp in enumerate(spec_h)]
+    tmem = [make(*sp, seed=95 + i) for i, sp in enumerate(spec_t)]
+    with T.Group(4) as g:
+        for sv, _ in hmem + tmem:
+            g.add(sv)
+        assert g.info().classes == 4
+        g.step(4)
+        g.step(3)
+        torch.cuda.synchronize()
+        got_h = [(snapshot(sv), sv.horizon()) for sv, _ in hmem]
+        got_t = [snapshot(sv) for sv, _ in tmem]
+    for (sv, u0), sp, (gs, gh) in zip(hmem, spec_h, got_h):
+        sv.close()
+        alone, _ = make_h(*sp, seed=0)
+        alone.set_initial(u0)
+        alone.step(7)
+        assert_same(gs, snapshot(alone), ("chart H member", sp))
+        for x, y in zip(gh, alone.horizon()):
+            assert np.array_equal(x, y), ("horizon samples", sp)
+        alone.close()
+    for (sv, u0), sp, gs in zip(tmem, spec_t, got_t):
+        sv.close()
+        alone, _ = make(*sp, seed=0)
+        alone.set_initial(u0)
+        alone.step(7)
+        assert_same(gs, snapshot(alone), ("chart T member", sp))
+        alone.close()
+
+
 def test_batched_mix_full_size():
     """The 64-solve mix at full size, 2 steps in one group; four members (the
     largest, the smallest and two others) against the same solves alone."""
