@@ -54,15 +54,16 @@ def kernel_sha() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(weights: str):
-    """HBM bytes per stage launch from the committed rocprofv3 counter runs, or
+def measured_traffic(weights: str, key: str = "bytes_per_launch"):
+    """HBM bytes per launch from the committed rocprofv3 counter runs (per
+    stage launch, or with key "bytes_per_blocked_step" per blocked step), or
     None if they were taken on a different kernel source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     rec = json.load(open(TRAFFIC_FILE))
-    if rec.get("kernel_sha") != kernel_sha() or weights not in rec.get("bytes_per_launch", {}):
+    if rec.get("kernel_sha") != kernel_sha() or weights not in rec.get(key, {}):
         return None
-    return float(rec["bytes_per_launch"][weights])
+    return float(rec[key][weights])
 
 
 def log(msg: str):
@@ -202,14 +203,16 @@ def bench_single(args, torch, T, W):
         out["mixed_precision"] = mixed
     if weights == "fp64" and not args.no_blocked:
         # Temporal blocking: the same SSP-RK(3,3) step as one launch per step
-        # (u(1), u(2) in LDS; 64 B of HBM traffic per point-step).
+        # (u(1), u(2) in LDS; 64 B of HBM traffic per point-step; "traffic" is
+        # the measured bytes per step).
         secb, _, infob, waveb = run("fp64", integrator="rk3_blocked")
         out["blocked"] = {
             "steps": steps, "ms_per_step": secb / steps * 1e3, "value": pu / secb, "unit": "point-updates/s",
             "speedup_vs_three_launch": gpu_s / secb, "tiles": infob.workgroups,
             "waveform_rel_diff_vs_three_launch": float(np.max(np.abs(waveb - wave)) / np.max(np.abs(wave))),
             "hbm": {"bytes_per_point_step": 64, "achieved_GBs": 64.0 * wl.points * steps / secb / 1e9,
-                    "frac": 64.0 * wl.points * steps / secb / 1e9 / HBM_PEAK_GBS},
+                    "frac": 64.0 * wl.points * steps / secb / 1e9 / HBM_PEAK_GBS,
+                    "traffic": measured_traffic("fp64", "bytes_per_blocked_step")},
         }
     if weights == "fp64" and not args.no_rk104:
         # SSP-RK(10,4) (Sec. 3.2) over the same simulated time: its default step
