@@ -130,6 +130,19 @@ def solver_config(T, wl, weights, total_steps, workgroups=0, every=None, state="
                          state=state, integrator=integrator)
 
 
+def copy_probe(mib, torch):
+    """A plain device copy of `mib` MiB, three times: a kernel of known traffic
+    that calibrates the rocprofv3 FETCH_SIZE / WRITE_SIZE counters of the run."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy probe: {n * 8} bytes read and written per copy")
+    del src, dst
+
+
 # ----------------------------------------------------------------------------- C2: one solve
 def bench_single(args, torch, T, W):
     wl = W.C2
@@ -139,16 +152,6 @@ def bench_single(args, torch, T, W):
     u0 = W.gaussian_pulse(wl)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-
-    if args.copy_probe > 0:
-        n = args.copy_probe * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"copy probe: {n * 8} bytes read and written per copy")
-        del src, dst
 
     def run(wp, state="fp64", nsteps=None, nwarm=None, integrator="rk3", every=None):
         """Warm up, then time `steps` steps with HIP events on the solver's
@@ -629,6 +632,8 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe, torch)
     fn = {"C2": bench_single, "C3": bench_sweep, "C3H": bench_horizon, "C4": bench_batched,
           "C5": bench_serving}[args.workload]
     out = fn(args, torch, T, W)
