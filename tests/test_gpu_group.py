@@ -1,12 +1,14 @@
-"""GPU: the group extension (many independent solves, one launch per RK stage).
+"""GPU: the group extension (many independent solves, one launch per RK stage
+for each cache block of members).
 
 A member's arithmetic is the single-solve stage arithmetic, tile by tile, so a
 solve advanced inside a group must equal the same solve advanced alone bit for
 bit: state, waveform samples and counters.  Cases: a mixed group (ragged grids,
 different spins, Kerr parameters, weight precisions, sampling intervals and
-tile sizes), members joining and leaving mid-run, the batched workload mix at
-full size (several members checked), one member against the FP64 oracle, and
-the error paths."""
+tile sizes), members joining and leaving mid-run, members cut into several
+cache blocks, members of both charts, the batched workload mix at full size
+(several members checked), one member against the FP64 oracle, and the error
+paths."""
 import numpy as np
 import pytest
 import torch
