@@ -976,13 +976,14 @@ __global__ __launch_bounds__(kBThreads) void blocked_step_kernel(StageArgs A)
     }
     if (r1lo + 2 < nstage) load_row(r1lo + 2);
 
-    // Issue priority steps down from 3 to 0 at the quarters of the march, so
-    // that waves which started later keep pace with the older waves of their
-    // SIMD (see march_strip_t).  On C2 this took the step from 0.97x to 1.02x
-    // of the three-launch step; steps every three rows, reaching priority 0
-    // after a third of the march, gave no gain.
+    // Issue priority steps down from 3 to 0 at 1/2, 3/4 and 7/8 of the march,
+    // so that waves which started later keep pace with the older waves of
+    // their SIMD (see march_strip_t).  On C2 the steps took the blocked step
+    // from 0.97x to above 1.02x of the three-launch step; with two-wave tiles
+    // these late steps measured 0.8 % faster than steps at the quarters, and
+    // steps at the thirds (never reaching 0) 1.3 % slower.
     const int nit = k1 + 2 - r1lo;
-    const int q1 = (nit + 3) / 4, q2 = (nit + 1) / 2, q3 = (3 * nit + 3) / 4;
+    const int q1 = (nit + 1) / 2, q2 = (3 * nit + 3) / 4, q3 = (7 * nit + 7) / 8;
     for (int r = r1lo; r < k1 + 2; ++r) {
         const int it = r - r1lo;
         if (it == 0) __builtin_amdgcn_s_setprio(3);
