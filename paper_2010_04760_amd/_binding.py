@@ -2,13 +2,16 @@
 
 Every computation runs in the HIP library.  PyTorch supplies device memory
 (a workspace tensor the solver lives in) and streams; it is imported before
-the library is loaded so that both share one HIP runtime.  If libteuk.so has
-not been built, importing this module fails: there is no fallback.
+the library is loaded so that both share one HIP runtime.  If libteuk.so is
+not there, it is built from the sources beside this file first; if that build
+fails, importing this module fails: there is no fallback.
 """
 from __future__ import annotations
 
 import ctypes
+import importlib.util
 import os
+import sys
 
 import numpy as np
 import torch  # noqa: F401  (plumbing: device memory and streams; loads the HIP runtime first)
@@ -16,9 +19,21 @@ import torch  # noqa: F401  (plumbing: device memory and streams; loads the HIP 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libteuk.so")
 
+
+def _build_missing_library() -> None:
+    print(f"{LIB_PATH} not found: building it with hipcc (gfx950)", file=sys.stderr, flush=True)
+    spec = importlib.util.spec_from_file_location("_teuk_build", os.path.join(_HERE, "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    try:
+        mod.build(verbose=False)
+    except Exception as e:  # noqa: BLE001
+        raise ImportError(f"{LIB_PATH} is not built and building it failed: {e}") from e
+    print(f"built {LIB_PATH}", file=sys.stderr, flush=True)
+
+
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
-                      "python paper_2010_04760_amd/build.py")
+    _build_missing_library()
 
 _lib = ctypes.CDLL(LIB_PATH)
 

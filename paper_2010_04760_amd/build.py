@@ -1,9 +1,16 @@
-"""Build libteuk.so (HIP, gfx950) in the package directory with hipcc."""
+"""Build libteuk.so (HIP, gfx950) in the package directory with hipcc.
+
+This file imports nothing from the package, so it can be loaded by path (and
+run as a script) before the library exists.  Each translation unit is compiled
+to an object of its own, in parallel, and the objects are then linked; no unit
+launches a kernel defined in another, so no relocatable device code is needed.
+"""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -20,7 +27,6 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # code object v5 is understood by both the ROCm 7.2 toolchain and the
     # ROCm 7.0 runtime that ships inside the PyTorch wheel
     "-mcode-object-version=5",
@@ -31,23 +37,7 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False, extra_flags: list[str] | None = None) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    os.makedirs(BUILD_DIR, exist_ok=True)
-    objs = []
-    for s in GXX_SOURCES:
-        obj = os.path.join(BUILD_DIR, os.path.splitext(s)[0] + ".o")
-        gcmd = ["g++", *GXX_FLAGS, "-I", os.path.join(ROOT, "include"), "-c", os.path.join(CSRC, s), "-o", obj]
-        if verbose:
-            print(" ".join(gcmd), flush=True)
-        r = subprocess.run(gcmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            sys.stderr.write(r.stdout + r.stderr)
-            raise RuntimeError(f"g++ failed building {s}")
-        objs.append(obj)
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", *HIPCC_FLAGS, *(extra_flags or []), "-I", os.path.join(ROOT, "include"), *srcs, *["-Wl," + o for o in objs],
-           "-lquadmath", "-o", tmp]
+def _run(cmd: list[str], what: str, verbose: bool) -> None:
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -55,9 +45,31 @@ def build(verbose: bool = False, extra_flags: list[str] | None = None) -> str:
     msgs = [ln for ln in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in ln]
     if r.returncode != 0:
         sys.stderr.write("\n".join(msgs) + "\n")
-        raise RuntimeError("hipcc failed building libteuk.so")
+        raise RuntimeError(f"{what} failed (exit {r.returncode})")
     if verbose and msgs:
-        print("\n".join(msgs))
+        print("\n".join(msgs), flush=True)
+
+
+def build(verbose: bool = False, extra_flags: list[str] | None = None) -> str:
+    """Compile every source and link libteuk.so; returns its path.  Raises
+    RuntimeError (with the compiler's messages on stderr) if any step fails."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include")]
+    jobs = []
+    for s in GXX_SOURCES:
+        obj = os.path.join(BUILD_DIR, os.path.splitext(s)[0] + ".o")
+        jobs.append((["g++", *GXX_FLAGS, *inc, "-c", os.path.join(CSRC, s), "-o", obj], f"g++ {s}", obj))
+    for s in SOURCES:
+        obj = os.path.join(BUILD_DIR, os.path.splitext(s)[0] + ".hip.o")
+        jobs.append((["hipcc", *HIPCC_FLAGS, *(extra_flags or []), *inc, "-c", os.path.join(CSRC, s), "-o", obj],
+                     f"hipcc {s}", obj))
+    with ThreadPoolExecutor(max_workers=min(len(jobs), 8)) as ex:
+        for f in [ex.submit(_run, cmd, what, verbose) for cmd, what, _ in jobs]:
+            f.result()
+    tmp = LIB + ".tmp"
+    objs = [o for _, _, o in jobs]
+    _run(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-lquadmath", "-o", tmp],
+         "linking libteuk.so", verbose)
     os.replace(tmp, LIB)
     return LIB
 
