@@ -227,7 +227,10 @@ size_t teuk_footprint_bytes(const teuk_config* cfg);
  * DEVICE.  On error *out is NULL and teuk_last_error(NULL) says why. */
 teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk_solver** out);
 
-/* Set the state u^n (layout above; on_device != 0 means u is a device pointer
+/* Set the state u^n = {Phi_R, Phi_I, pi_R, pi_I} of the first-order system
+ * (eq. evln; pi = d_t Phi + b d_x Phi, Sec. 2.3) -- the initial data of the
+ * evolution, e.g. the real Gaussian packets times an angular profile of the
+ * runs of Sec. 4 (layout above; on_device != 0 means u is a device pointer
  * with that dense layout, else a host pointer), reset t and the step and
  * sample counters, and record the first waveform sample (t = 0).  The data
  * are copied; u is not retained.  Host input is checked for NaN/Inf
@@ -248,7 +251,12 @@ teuk_status teuk_set_initial(teuk_solver* h, const double* u, int32_t on_device)
 teuk_status teuk_step(teuk_solver* h, int64_t nsteps);
 
 /* Copy results to the host array out (capacity in doubles); *written receives
- * the number of doubles written (may be NULL).  Synchronises the stream and
+ * the number of doubles written (may be NULL).  The waveform is the field Phi
+ * at a fixed radius sampled in time, the series whose late-time decay (local
+ * power-law index t dPhi/dt / Phi) Sec. 4 studies; the horizon samples are Phi
+ * and d_rho Phi on the extremal horizon, the quantities of the horizon laws of
+ * Sec. 4 (Phi_H decaying as 1/tau while d_rho Phi_H tends to a constant, the
+ * Aretakis behaviour).  Synchronises the stream and
  * runs the non-finite guard on the state first (NONFINITE if it trips; the
  * data are still copied for inspection).
  *   TEUK_X_STATE     4*ntheta*nr doubles (twice that in double-double)

@@ -286,17 +286,23 @@ constexpr int kRing = 4;                                    // rows in the LDS r
 constexpr unsigned kPlaneBytes = kRowP * 8;                 // 576
 constexpr unsigned kSlotBytes = 4 * kPlaneBytes;            // 2304
 
-// One LDS-DMA dword per lane: LDS[m0 + 4 lane] = global[sbase + voff].
+// One LDS-DMA dword per lane: LDS[m0 + 4 lane] = global[sbase + voff].  The
+// LDS address reaches m0 through an operand constrained to that register, so
+// the compiler writes m0 itself and knows the instruction reads it.
 __device__ __forceinline__ void dma_dword(unsigned voff, const double* sbase, unsigned lds)
 {
-    asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dword %0, %1" : : "v"(voff), "s"(sbase), "s"(lds) : "memory");
+    asm volatile("global_load_lds_dword %0, %1" : : "v"(voff), "s"(sbase), "{m0}"(lds) : "memory");
 }
 
-// A double from global memory whose arrival is waited for explicitly.
+// A double from global memory whose arrival is waited for explicitly: the
+// register holds the value only after the vm_wait that takes it as an operand.
+// Until then no instruction may read, copy or reuse it; the compiler sees the
+// value as ready at once, so this is checked in the built assembly (every
+// wait names its operands in a comment for that check).
 __device__ __forceinline__ double ld_async(unsigned voff, const double* sbase)
 {
     double v;
-    asm volatile("global_load_dwordx2 %0, %1, %2" : "=v"(v) : "v"(voff), "s"(sbase) : "memory");
+    asm volatile("global_load_dwordx2 %0, %1, %2 ; async-load" : "=&v"(v) : "v"(voff), "s"(sbase) : "memory");
     return v;
 }
 
@@ -311,7 +317,7 @@ __device__ __forceinline__ void vm_wait()
 template <int N>
 __device__ __forceinline__ void vm_wait(double& a, double& b, double& c, double& d)
 {
-    asm volatile("s_waitcnt vmcnt(%4)" : "+v"(a), "+v"(b), "+v"(c), "+v"(d) : "n"(N) : "memory");
+    asm volatile("s_waitcnt vmcnt(%4) ; async-wait %0 %1 %2 %3" : "+v"(a), "+v"(b), "+v"(c), "+v"(d) : "n"(N) : "memory");
 }
 
 // One radial strip [j0, j0 + 63) marched over the theta rows [k0, k1), upward
