@@ -294,6 +294,33 @@ const char* teuk_last_error(const teuk_solver* h);
  * Errors: INVALID_ARG, CAPACITY. */
 teuk_status teuk_host_coefficients(const teuk_config* cfg, double* out, size_t capacity);
 
+/* Allocation-free stepping, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Advances the caller's device state u ([4][ntheta][nr] FP64
+ * planes, the layout above; read and written in place, not retained) by
+ * nsteps SSP-RK(3,3) steps of cfg, enqueued on `stream` (a hipStream_t, NULL
+ * for the null stream), with the same stage kernels and launch shapes as
+ * teuk_step: the result is bitwise that of teuk_create + teuk_set_initial +
+ * teuk_step with the same cfg.  It allocates nothing: the two stage buffers
+ * and the coefficient tables live in a fixed device array of the library
+ * (about 67 MiB, held by every GPU the library runs on until the process
+ * ends), so the grid is limited to nr <= 32768, ntheta <= 4096 and
+ * nr * ntheta <= 2^20 points.  The array keeps the last call's contents: the
+ * tables are rebuilt on the host and uploaded (a synchronising copy) only
+ * when s, m, M, a, nr, ntheta, x_min or x_max differ from the previous call
+ * on the device.  Under stream capture the tables of cfg must already be
+ * resident (an earlier call with the same cfg), else the call fails with
+ * STATE and enqueues nothing; the captured work is kernel launches only.
+ * Calls that overlap on one GPU (other threads or streams) share the array
+ * and race.  Tortoise chart, FP64 state, WENO5, FP64/FP32/FP16/BF16 weights;
+ * cfg->dt must be > 0 (no stability-bound reduction) and
+ * cfg->extract_every 0 (no waveform ring).
+ * Errors: INVALID_ARG (bad cfg, NULL u, nsteps < 0, dt <= 0, extract_every
+ * != 0, grid beyond the limits), UNSUPPORTED (other chart, state, integrator
+ * or scheme), STATE (capture without resident tables), DEVICE;
+ * teuk_last_error(NULL) says why. */
+teuk_status teuk_step_noalloc(const teuk_config* cfg, double* u, int64_t nsteps, void* stream);
+
 /* ------------------------------------------------------------------------
  * Group extension: many independent solves advanced together.
  *

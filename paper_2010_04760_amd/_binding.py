@@ -111,6 +111,8 @@ _lib.teuk_last_error.argtypes = [ctypes.c_void_p]
 _lib.teuk_last_error.restype = ctypes.c_char_p
 _lib.teuk_host_coefficients.argtypes = [_P(teuk_config), _dp, ctypes.c_size_t]
 _lib.teuk_host_coefficients.restype = ctypes.c_int
+_lib.teuk_step_noalloc.argtypes = [_P(teuk_config), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+_lib.teuk_step_noalloc.restype = ctypes.c_int
 
 
 class teuk_group_info_t(ctypes.Structure):
@@ -137,7 +139,8 @@ _lib.teuk_group_last_error.restype = ctypes.c_char_p
 EXPORTED = ["teuk_default_config", "teuk_footprint_bytes", "teuk_create", "teuk_set_initial", "teuk_step",
             "teuk_extract", "teuk_info", "teuk_check_finite", "teuk_destroy", "teuk_last_error",
             "teuk_host_coefficients", "teuk_group_create", "teuk_group_add", "teuk_group_remove",
-            "teuk_group_step", "teuk_group_info", "teuk_group_destroy", "teuk_group_last_error"]
+            "teuk_group_step", "teuk_group_info", "teuk_group_destroy", "teuk_group_last_error",
+            "teuk_step_noalloc"]
 
 
 class TeukError(RuntimeError):
@@ -223,6 +226,17 @@ def teuk_host_coefficients(cfg: teuk_config) -> np.ndarray:
     out = np.empty(TEUK_NCOEF * n * pv, dtype=np.float64)
     _check(_lib.teuk_host_coefficients(ctypes.byref(cfg), out.ctypes.data_as(_dp), out.size))
     return out.reshape((TEUK_NCOEF, cfg.ntheta, cfg.nr) + ((2,) if pv == 2 else ()))
+
+
+def teuk_step_noalloc(cfg: teuk_config, u: "torch.Tensor", nsteps: int, stream=None) -> None:
+    """Advance the contiguous float64 device tensor u ([4][ntheta][nr]) in place."""
+    if not (isinstance(u, torch.Tensor) and u.is_cuda and u.dtype == torch.float64 and u.is_contiguous()):
+        raise ValueError("u must be a contiguous float64 CUDA tensor")
+    if u.numel() != 4 * cfg.nr * cfg.ntheta:
+        raise ValueError(f"u holds {u.numel()} values, the grid needs {4 * cfg.nr * cfg.ntheta}")
+    s = stream if stream is not None else torch.cuda.current_stream(u.device)
+    _check(_lib.teuk_step_noalloc(ctypes.byref(cfg), ctypes.c_void_p(u.data_ptr()), int(nsteps),
+                                  ctypes.c_void_p(s.cuda_stream)))
 
 
 def teuk_group_create(ctx: teuk_device_ctx | None, max_members: int, workgroups: int = 0,

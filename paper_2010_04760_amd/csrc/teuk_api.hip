@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -1089,3 +1090,137 @@ const char* teuk_group_last_error(const teuk_group* g)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free stepping
+// teuk_step_noalloc keeps its device memory beyond the caller's state -- the
+// two SSP-RK stage buffers u(1), u(2) and the chart-T radial and polar
+// coefficient tables -- in one file-scope device array.  Every GPU the library
+// runs on holds its own copy of the array from module load until the process
+// ends.  Host code never passes the array's name to a kernel or a copy: it
+// takes the array's device address on each device once (hipGetSymbolAddress)
+// and uses that address.
+namespace {
+constexpr long long kNaMaxPoints = 1LL << 20;   // nr * ntheta
+constexpr int kNaMaxNr = 1 << 15;
+constexpr int kNaMaxNth = 1 << 12;
+constexpr size_t kNaStateBytes = (size_t)kNaMaxPoints * 4 * sizeof(double);
+constexpr size_t kNaOffU1 = 0;
+constexpr size_t kNaOffU2 = kNaStateBytes;
+constexpr size_t kNaOffR = 2 * kNaStateBytes;
+constexpr size_t kNaOffT = kNaOffR + (size_t)kNRT * kNaMaxNr * sizeof(double);
+constexpr size_t kNaBytes = kNaOffT + (size_t)kNTT * kNaMaxNth * sizeof(double);
+static_assert(kNaOffR % 256 == 0 && kNaOffT % 256 == 0, "scratch regions stay 256-byte aligned");
+constexpr int kNaMaxDevices = 64;
+
+// What the resident coefficient tables were built from.
+struct NaTableKey {
+    int32_t s, m, nr, ntheta;
+    double M, a, x_min, x_max;
+};
+
+struct NaDevice {
+    char* ptr = nullptr;          // device address of `scratch` on this device
+    bool tables = false;          // tables of `key` resident in the array
+    NaTableKey key{};
+};
+std::mutex g_na_mutex;
+NaDevice g_na[kNaMaxDevices];
+}  // namespace
+
+static __device__ __align__(256) char scratch[kNaBytes];
+
+extern "C" teuk_status teuk_step_noalloc(const teuk_config* cfg, double* u, int64_t nsteps, void* stream)
+{
+    std::string err;
+    if (!validate(cfg, err)) return fail(nullptr, TEUK_ERR_INVALID_ARG, err);
+    if (!u) return fail(nullptr, TEUK_ERR_INVALID_ARG, "u is NULL");
+    if (nsteps < 0) return fail(nullptr, TEUK_ERR_INVALID_ARG, "nsteps must be >= 0");
+    if (cfg->chart != TEUK_CHART_TORTOISE || cfg->state_prec != TEUK_S_FP64 || cfg->integrator != TEUK_RK_SSP33 ||
+        cfg->scheme != TEUK_SCHEME_WENO5 || cfg->weight_prec == TEUK_W_DD)
+        return fail(nullptr, TEUK_ERR_UNSUPPORTED,
+                    "teuk_step_noalloc: tortoise chart, FP64 state, SSP-RK(3,3), WENO5 only");
+    if (!(cfg->dt > 0.0)) return fail(nullptr, TEUK_ERR_INVALID_ARG, "teuk_step_noalloc needs dt > 0");
+    if (cfg->extract_every != 0) return fail(nullptr, TEUK_ERR_INVALID_ARG, "teuk_step_noalloc keeps no waveform: extract_every must be 0");
+    if (cfg->nr > kNaMaxNr || cfg->ntheta > kNaMaxNth || (long long)cfg->nr * cfg->ntheta > kNaMaxPoints)
+        return fail(nullptr, TEUK_ERR_INVALID_ARG,
+                    "teuk_step_noalloc: grid " + std::to_string(cfg->nr) + " x " + std::to_string(cfg->ntheta) +
+                        " exceeds its scratch limits (nr <= 32768, ntheta <= 4096, nr * ntheta <= 1048576)");
+    if (nsteps == 0) return TEUK_OK;
+    const hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    int e = (int)hipGetDevice(&dev);
+    if (e) return fail(nullptr, TEUK_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString((hipError_t)e));
+    if (dev < 0 || dev >= kNaMaxDevices) return fail(nullptr, TEUK_ERR_UNSUPPORTED, "device index beyond 63");
+    const NaTableKey key{cfg->s, cfg->m, cfg->nr, cfg->ntheta, cfg->M, cfg->a, cfg->x_min, cfg->x_max};
+    char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_na_mutex);
+        NaDevice& d = g_na[dev];
+        if (!d.ptr) {
+            void* p = nullptr;
+            e = (int)hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e || !p)
+                return fail(nullptr, TEUK_ERR_DEVICE,
+                            std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString((hipError_t)e));
+            d.ptr = (char*)p;
+        }
+        base = d.ptr;
+        if (!d.tables || std::memcmp(&d.key, &key, sizeof(key)) != 0) {
+            // A copy from host memory must not be recorded into a graph (its
+            // source is released on return), so a capturing call needs the
+            // tables of its configuration resident already.
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            e = (int)hipStreamIsCapturing(st, &cs);
+            if (e) return fail(nullptr, TEUK_ERR_DEVICE, std::string("hipStreamIsCapturing: ") + hipGetErrorString((hipError_t)e));
+            if (cs != hipStreamCaptureStatusNone)
+                return fail(nullptr, TEUK_ERR_STATE,
+                            "teuk_step_noalloc under stream capture: call it once outside capture with this "
+                            "configuration first, so that its coefficient tables are resident");
+            std::vector<double> rtab, ttab;
+            if (!build_tables(*cfg, rtab, ttab, err)) return fail(nullptr, TEUK_ERR_INVALID_ARG, err);
+            d.tables = false;
+            e = (int)hipMemcpyAsync(base + kNaOffR, rtab.data(), rtab.size() * sizeof(double), hipMemcpyHostToDevice, st);
+            if (!e) e = (int)hipMemcpyAsync(base + kNaOffT, ttab.data(), ttab.size() * sizeof(double), hipMemcpyHostToDevice, st);
+            if (!e) e = (int)hipStreamSynchronize(st);   // the host tables are released on return
+            if (e) return fail(nullptr, TEUK_ERR_DEVICE, std::string("table upload: ") + hipGetErrorString((hipError_t)e));
+            d.key = key;
+            d.tables = true;
+        }
+    }
+    const int nstrips = (cfg->nr + kStripPoints - 1) / kStripPoints;
+    const int segs1 = pick_segs(*cfg, nstrips, cfg->weight_prec, true);
+    const int segs23 = pick_segs(*cfg, nstrips, cfg->weight_prec, false);
+    if (segs1 <= 0 || segs23 <= 0) return fail(nullptr, TEUK_ERR_UNSUPPORTED, "occupancy query failed");
+    double* u1 = (double*)(base + kNaOffU1);
+    double* u2 = (double*)(base + kNaOffU2);
+    const double dx = (cfg->x_max - cfg->x_min) / (cfg->nr - 1);
+    const double dth = M_PI / cfg->ntheta;
+    StageArgs a;
+    a.rtab = (const double*)(base + kNaOffR);
+    a.ttab = (const double*)(base + kNaOffT);
+    a.ctab = nullptr;
+    a.plane = (long long)cfg->nr * cfg->ntheta;
+    a.nr = cfg->nr;
+    a.nth = cfg->ntheta;
+    a.nstrips = nstrips;
+    a.inv6dx = 1.0 / (6.0 * dx);
+    a.ih1 = 1.0 / (2.0 * dth);
+    a.ih2 = 1.0 / (dth * dth);
+    a.dt = cfg->dt;
+    a.out2 = nullptr;
+    a.ca2 = a.cb2 = 0.0;
+    a.inv_dx = 1.0 / dx;
+    a.ko_sigma = cfg->ko_sigma;
+    a.eps = cfg->weno_eps;
+    a.parity = ((cfg->m + cfg->s) % 2 != 0) ? -1.0 : 1.0;
+    for (int64_t n = 0; n < nsteps && !e; ++n) {
+        a.uk = u; a.un = u; a.out = u1; a.ca = 0.0; a.cb = 1.0; a.segs = segs1; a.grid = nstrips * segs1;
+        e = launch_stage(a, 1, cfg->weight_prec, cfg->chart, st);
+        if (!e) { a.uk = u1; a.un = u; a.out = u2; a.ca = 0.75; a.cb = 0.25; a.segs = segs23; a.grid = nstrips * segs23;
+                  e = launch_stage(a, 2, cfg->weight_prec, cfg->chart, st); }
+        if (!e) { a.uk = u2; a.un = u; a.out = u; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0;
+                  e = launch_stage(a, 3, cfg->weight_prec, cfg->chart, st); }
+    }
+    if (e) return fail(nullptr, TEUK_ERR_DEVICE, std::string("stage launch: ") + hipGetErrorString((hipError_t)e));
+    return TEUK_OK;
+}
