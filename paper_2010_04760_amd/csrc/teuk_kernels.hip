@@ -48,15 +48,12 @@ constexpr bool reads_un() { return kMode == kStageLater || kMode == kStageDual; 
 constexpr int kChartT = TEUK_CHART_TORTOISE;
 constexpr int kChartH = TEUK_CHART_HYPERBOLOIDAL;
 
-// 1/x to full FP64 precision: hardware estimate refined by two Newton steps.
+// 1/x from the hardware estimate refined by one Newton step.
 __device__ __forceinline__ double rcp64(double x)
 {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = __builtin_fma(-x, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-x, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    return r;
+    const double r = __builtin_amdgcn_rcp(x);
+    const double e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
 }
 
 // 1/sqrt(x), x > 0, to full FP64 precision: estimate plus two Newton steps.
@@ -116,9 +113,9 @@ struct Weno<TEUK_W_FP64> {
         const double e2 = 3.0 * v2 - 4.0 * v3 + v4;
         constexpr double c = 13.0 / 3.0;
         const double eps4 = 4.0 * eps;
-        double t0 = eps4 + ((c * d0) * d0 + e0 * e0);
-        double t1 = eps4 + ((c * d1) * d1 + e1 * e1);
-        double t2 = eps4 + ((c * d2) * d2 + e2 * e2);
+        double t0 = __builtin_fma(c * d0, d0, __builtin_fma(e0, e0, eps4));
+        double t1 = __builtin_fma(c * d1, d1, __builtin_fma(e1, e1, eps4));
+        double t2 = __builtin_fma(c * d2, d2, __builtin_fma(e2, e2, eps4));
         t0 *= t0;
         t1 *= t1;
         t2 *= t2;
