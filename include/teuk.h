@@ -250,6 +250,25 @@ teuk_status teuk_set_initial(teuk_solver* h, const double* u, int32_t on_device)
  * Errors: STATE (no initial data), INVALID_ARG (nsteps < 0), DEVICE. */
 teuk_status teuk_step(teuk_solver* h, int64_t nsteps);
 
+/* Graph mode (HIP graphs).  With chunk_steps > 0, teuk_step runs its steps as
+ * replays of one graph that holds chunk_steps steps -- every stage launch and
+ * waveform sample of them, exactly the launches of stepping one call at a
+ * time -- captured on first use, so that the host enqueues one graph launch
+ * per chunk instead of three or more kernel launches per step: nsteps / chunk
+ * replays, then the remaining nsteps % chunk steps launch by launch.  Results
+ * are bitwise those of graph mode off.  Samples reach the right ring slots on
+ * every replay because the sample kernel takes its slot from a device copy of
+ * the sample count.  The graph is recaptured only when the sampling phase
+ * (steps % extract_every) at the start of a replay run differs from the one
+ * it was captured at, so stepping in multiples of chunk_steps captures once.
+ * The captured work is kernel launches only (no memset or copy nodes).
+ * chunk_steps = 0 turns graph mode off (the default); at most 4096.
+ * Errors: INVALID_ARG (NULL, chunk out of range, chunk not a multiple of
+ * extract_every, odd chunk with TEUK_RK_SSP33_BLOCKED), UNSUPPORTED
+ * (double-double state).  teuk_step may then also return DEVICE from the
+ * capture or a replay. */
+teuk_status teuk_set_graph(teuk_solver* h, int32_t chunk_steps);
+
 /* Copy results to the host array out (capacity in doubles); *written receives
  * the number of doubles written (may be NULL).  The waveform is the field Phi
  * at a fixed radius sampled in time, the series whose late-time decay (local
@@ -385,6 +404,17 @@ teuk_status teuk_group_remove(teuk_group* g, teuk_solver* h);
  * state.  An empty group or nsteps = 0 is a no-op.  Errors: INVALID_ARG,
  * DEVICE. */
 teuk_status teuk_group_step(teuk_group* g, int64_t nsteps);
+
+/* Graph mode for the group (see teuk_set_graph): teuk_group_step runs, cache
+ * block by cache block, nsteps / chunk_steps replays of that block's graph of
+ * chunk_steps steps (its stage launches and its members' samples), then the
+ * remainder launch by launch.  Each block keeps its own graph, so a block still
+ * runs all of a call's steps before the next block starts.  Adding or removing
+ * a member drops the graphs; they are recaptured on the next step.  Every
+ * member's extract_every must divide chunk_steps (else teuk_group_step returns
+ * INVALID_ARG).  chunk_steps = 0 turns it off; at most 4096.
+ * Errors: INVALID_ARG. */
+teuk_status teuk_group_set_graph(teuk_group* g, int32_t chunk_steps);
 
 /* Group information (no synchronisation).  Errors: INVALID_ARG. */
 teuk_status teuk_group_info(const teuk_group* g, teuk_group_info_t* info);

@@ -111,6 +111,8 @@ _lib.teuk_last_error.argtypes = [ctypes.c_void_p]
 _lib.teuk_last_error.restype = ctypes.c_char_p
 _lib.teuk_host_coefficients.argtypes = [_P(teuk_config), _dp, ctypes.c_size_t]
 _lib.teuk_host_coefficients.restype = ctypes.c_int
+_lib.teuk_set_graph.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+_lib.teuk_set_graph.restype = ctypes.c_int
 _lib.teuk_step_noalloc.argtypes = [_P(teuk_config), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
 _lib.teuk_step_noalloc.restype = ctypes.c_int
 
@@ -129,6 +131,8 @@ _lib.teuk_group_remove.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
 _lib.teuk_group_remove.restype = ctypes.c_int
 _lib.teuk_group_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
 _lib.teuk_group_step.restype = ctypes.c_int
+_lib.teuk_group_set_graph.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+_lib.teuk_group_set_graph.restype = ctypes.c_int
 _lib.teuk_group_info.argtypes = [ctypes.c_void_p, _P(teuk_group_info_t)]
 _lib.teuk_group_info.restype = ctypes.c_int
 _lib.teuk_group_destroy.argtypes = [ctypes.c_void_p]
@@ -140,7 +144,7 @@ EXPORTED = ["teuk_default_config", "teuk_footprint_bytes", "teuk_create", "teuk_
             "teuk_extract", "teuk_info", "teuk_check_finite", "teuk_destroy", "teuk_last_error",
             "teuk_host_coefficients", "teuk_group_create", "teuk_group_add", "teuk_group_remove",
             "teuk_group_step", "teuk_group_info", "teuk_group_destroy", "teuk_group_last_error",
-            "teuk_step_noalloc"]
+            "teuk_step_noalloc", "teuk_set_graph", "teuk_group_set_graph"]
 
 
 class TeukError(RuntimeError):
@@ -201,6 +205,10 @@ def teuk_extract(h: int, what: int, capacity: int) -> np.ndarray:
     return out[: written.value]
 
 
+def teuk_set_graph(h: int, chunk_steps: int) -> None:
+    _check(_lib.teuk_set_graph(h, int(chunk_steps)), h)
+
+
 def teuk_info(h: int) -> teuk_info_t:
     info = teuk_info_t()
     _check(_lib.teuk_info(h, ctypes.byref(info)), h)
@@ -257,6 +265,10 @@ def teuk_group_remove(g: int, h: int) -> None:
 
 def teuk_group_step(g: int, nsteps: int) -> None:
     _gcheck(_lib.teuk_group_step(g, int(nsteps)), g)
+
+
+def teuk_group_set_graph(g: int, chunk_steps: int) -> None:
+    _gcheck(_lib.teuk_group_set_graph(g, int(chunk_steps)), g)
 
 
 def teuk_group_info(g: int) -> teuk_group_info_t:
@@ -340,6 +352,10 @@ class Solver:
     def step(self, nsteps: int):
         teuk_step(self.h, nsteps)
 
+    def set_graph(self, chunk_steps: int):
+        """Graph mode: step() replays a captured graph of chunk_steps steps (0: off)."""
+        teuk_set_graph(self.h, chunk_steps)
+
     def state(self) -> np.ndarray:
         n = int(np.prod(self.plane_shape))
         return teuk_extract(self.h, TEUK_X_STATE, n).reshape(self.plane_shape)
@@ -421,6 +437,10 @@ class Group:
 
     def step(self, nsteps: int):
         teuk_group_step(self.g, nsteps)
+
+    def set_graph(self, chunk_steps: int):
+        """Graph mode: each cache block replays a captured graph of chunk_steps steps (0: off)."""
+        teuk_group_set_graph(self.g, chunk_steps)
 
     def info(self) -> teuk_group_info_t:
         return teuk_group_info(self.g)

@@ -37,6 +37,7 @@ struct teuk_solver {
     double hw[4] = {0, 0, 0, 0}, hdw[4] = {0, 0, 0, 0};   // horizon value / derivative weights
     unsigned long long* cell = nullptr;             // dt-bound reduction cell
     int* flag = nullptr;                            // non-finite flag
+    unsigned long long* scount = nullptr;           // samples recorded (FP64 state; device copy of `samples`)
     double dx = 0, dth = 0, dt = 0, dt_bound = 0;
     int j_e = 0;
     int nstrips = 0;
@@ -47,10 +48,16 @@ struct teuk_solver {
     bool have_init = false;
     int device = 0;
     teuk_group* group = nullptr;                    // group holding this solver, if any
+    // graph mode: teuk_step replays a captured graph of graph_chunk steps
+    int graph_chunk = 0;                            // 0: off
+    hipStream_t cap_stream = nullptr;               // private stream the chunk is captured on
+    hipGraphExec_t gexec = nullptr;                 // the captured chunk, or null
+    long long graph_phase = -1;                     // steps % extract_every when it was captured
     std::string err;
 };
 
 constexpr int kClasses = 8;   // (weight precision, chart) pairs
+constexpr int kMaxGraphChunk = 4096;   // steps per captured graph
 
 // Group members are stepped in cache blocks: consecutive members of one
 // (weight precision, chart) class whose solver footprints sum to at most this
@@ -91,6 +98,11 @@ struct teuk_group {
     std::vector<teuk_solver*> order;                // members in class order, block by block
     std::vector<GroupBlock> blocks;                 // class c = weight_prec + 4 * chart
     long long points = 0;
+    // graph mode: each cache block replays a captured graph of graph_chunk steps
+    int graph_chunk = 0;                            // 0: off
+    hipStream_t cap_stream = nullptr;
+    std::vector<hipGraphExec_t> gexec;              // per block, or null
+    std::vector<std::vector<long long>> gphase;     // per block: its members' steps % extract_every at capture
     std::string err;
 };
 
@@ -230,9 +242,23 @@ teuk_status hip_fail(teuk_solver* h, int e, const char* what)
     return fail(h, TEUK_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString((hipError_t)e));
 }
 
+// Destroy the solver's captured graph (after the work already enqueued on its
+// stream, which may still be replaying it, has finished).
+void drop_graph(teuk_solver* h)
+{
+    if (h->gexec) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
+    h->graph_phase = -1;
+}
+
 void free_solver(teuk_solver* h)
 {
     if (!h) return;
+    drop_graph(h);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->owns && h->base) (void)hipFree(h->base);
     delete h;
 }
@@ -255,14 +281,18 @@ teuk_status run_guard(teuk_solver* h)
 teuk_status record_sample(teuk_solver* h)
 {
     if (h->cfg.extract_every <= 0) return TEUK_OK;
-    const long long slot = h->samples % h->cfg.max_samples;
-    double* dst = h->wave + (size_t)slot * h->cfg.ntheta * (h->dd ? 4 : 2);
-    int e = h->dd ? launch_dd_extract(h->u[0], h->plane, h->cfg.nr, h->cfg.ntheta, h->j_e, dst, h->stream)
-                  : launch_extract(h->u[0], h->plane, h->cfg.nr, h->cfg.ntheta, h->j_e, dst, h->stream);
-    if (!e && h->hwave)
-        e = launch_horizon(h->u[0], h->plane, h->cfg.nr, h->cfg.ntheta, h->j_h, h->hw, h->hdw,
-                           h->hwave + (size_t)slot * h->cfg.ntheta * 4, h->stream);
-    if (e) return hip_fail(h, e, "extract launch");
+    int e;
+    if (h->dd) {
+        const long long slot = h->samples % h->cfg.max_samples;
+        e = launch_dd_extract(h->u[0], h->plane, h->cfg.nr, h->cfg.ntheta, h->j_e,
+                              h->wave + (size_t)slot * h->cfg.ntheta * 4, h->stream);
+    } else {
+        // the slot is taken from the device copy of the sample count, so that a
+        // captured chunk of steps samples into the right slots on every replay
+        e = launch_sample(h->u[0], h->plane, h->cfg.nr, h->cfg.ntheta, h->j_e, h->wave, h->hwave, h->j_h, h->hw,
+                          h->hdw, h->cfg.max_samples, h->scount, h->stream);
+    }
+    if (e) return hip_fail(h, e, "sample launch");
     ++h->samples;
     return TEUK_OK;
 }
@@ -377,6 +407,7 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     if (chartH) (void)horizon_stencil(*cfg, &h->j_h, h->hw, h->hdw);
     h->cell = (unsigned long long*)p;
     h->flag = (int*)(p + 64);
+    h->scount = (unsigned long long*)(p + 128);
 
     h->plane = (long long)cfg->nr * cfg->ntheta;
     h->vals = 4 * h->plane * (dd ? 2 : 1);
@@ -475,6 +506,11 @@ teuk_status teuk_set_initial(teuk_solver* h, const double* u, int32_t on_device)
     }
     h->steps = 0;
     h->samples = 0;
+    if (!h->dd && h->cfg.extract_every > 0) {
+        static const unsigned long long kZero = 0;
+        e = (int)hipMemcpyAsync(h->scount, &kZero, sizeof(kZero), hipMemcpyHostToDevice, h->stream);
+        if (e) return hip_fail(h, e, "hipMemcpyAsync(sample count)");
+    }
     h->have_init = true;
     return record_sample(h);
 }
@@ -625,11 +661,9 @@ static int rk104_step(teuk_solver* h, StageArgs a)
     return run_stage(h, a, 2);
 }
 
-teuk_status teuk_step(teuk_solver* h, int64_t nsteps)
+// nsteps steps launch by launch on h->stream.
+static teuk_status step_eager(teuk_solver* h, int64_t nsteps)
 {
-    if (!h) return fail(nullptr, TEUK_ERR_INVALID_ARG, "solver is NULL");
-    if (nsteps < 0) return fail(h, TEUK_ERR_INVALID_ARG, "nsteps must be >= 0");
-    if (!h->have_init) return fail(h, TEUK_ERR_STATE, "teuk_step before teuk_set_initial");
     const teuk_config& c = h->cfg;
     if (h->dd) {
         for (int64_t n = 0; n < nsteps; ++n) {
@@ -694,6 +728,90 @@ teuk_status teuk_step(teuk_solver* h, int64_t nsteps)
             if (st != TEUK_OK) return st;
         }
     }
+    return TEUK_OK;
+}
+
+// Capture graph_chunk steps of h into a graph (on the solver's private
+// capture stream, with the host counters and buffer roles restored after) and
+// instantiate it; the captured launches are the ones step_eager enqueues.
+static teuk_status capture_chunk(teuk_solver* h)
+{
+    const long long every = h->cfg.extract_every;
+    const long long phase = every > 0 ? h->steps % every : 0;
+    if (h->gexec && h->graph_phase == phase) return TEUK_OK;
+    drop_graph(h);
+    int e = 0;
+    if (!h->cap_stream) {
+        e = (int)hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+        if (e) {
+            h->cap_stream = nullptr;
+            return hip_fail(h, e, "hipStreamCreateWithFlags");
+        }
+    }
+    const hipStream_t saved_stream = h->stream;
+    const long long saved_steps = h->steps, saved_samples = h->samples;
+    double* const saved_u[3] = {h->u[0], h->u[1], h->u[2]};
+    e = (int)hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e) return hip_fail(h, e, "hipStreamBeginCapture");
+    h->stream = h->cap_stream;
+    const teuk_status st = step_eager(h, h->graph_chunk);
+    h->stream = saved_stream;
+    hipGraph_t graph = nullptr;
+    e = (int)hipStreamEndCapture(h->cap_stream, &graph);
+    h->steps = saved_steps;
+    h->samples = saved_samples;
+    for (int i = 0; i < 3; ++i) h->u[i] = saved_u[i];
+    if (st != TEUK_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e || !graph) return hip_fail(h, e ? e : (int)hipErrorUnknown, "hipStreamEndCapture");
+    e = (int)hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e) {
+        h->gexec = nullptr;
+        return hip_fail(h, e, "hipGraphInstantiate");
+    }
+    h->graph_phase = phase;
+    return TEUK_OK;
+}
+
+teuk_status teuk_step(teuk_solver* h, int64_t nsteps)
+{
+    if (!h) return fail(nullptr, TEUK_ERR_INVALID_ARG, "solver is NULL");
+    if (nsteps < 0) return fail(h, TEUK_ERR_INVALID_ARG, "nsteps must be >= 0");
+    if (!h->have_init) return fail(h, TEUK_ERR_STATE, "teuk_step before teuk_set_initial");
+    const int64_t chunk = h->graph_chunk;
+    if (chunk > 0 && nsteps >= chunk) {
+        teuk_status st = capture_chunk(h);
+        if (st != TEUK_OK) return st;
+        const long long every = h->cfg.extract_every;
+        const long long per = every > 0 ? chunk / every : 0;   // chunk is a multiple of extract_every
+        for (int64_t q = nsteps / chunk; q > 0; --q) {
+            const int e = (int)hipGraphLaunch(h->gexec, h->stream);
+            if (e) return hip_fail(h, e, "hipGraphLaunch");
+            h->steps += chunk;
+            h->samples += per;
+        }
+        return step_eager(h, nsteps % chunk);
+    }
+    return step_eager(h, nsteps);
+}
+
+teuk_status teuk_set_graph(teuk_solver* h, int32_t chunk_steps)
+{
+    if (!h) return fail(nullptr, TEUK_ERR_INVALID_ARG, "solver is NULL");
+    if (chunk_steps < 0 || chunk_steps > kMaxGraphChunk)
+        return fail(h, TEUK_ERR_INVALID_ARG, "chunk_steps must be in [0, " + std::to_string(kMaxGraphChunk) + "]");
+    if (chunk_steps > 0) {
+        if (h->dd) return fail(h, TEUK_ERR_UNSUPPORTED, "graph mode: FP64 state only");
+        if (h->cfg.extract_every > 0 && chunk_steps % h->cfg.extract_every != 0)
+            return fail(h, TEUK_ERR_INVALID_ARG, "chunk_steps must be a multiple of extract_every");
+        if (h->cfg.integrator == TEUK_RK_SSP33_BLOCKED && chunk_steps % 2 != 0)
+            return fail(h, TEUK_ERR_INVALID_ARG, "the blocked step swaps two buffers per step: chunk_steps must be even");
+    }
+    drop_graph(h);
+    h->graph_chunk = chunk_steps;
     return TEUK_OK;
 }
 
@@ -890,8 +1008,11 @@ static int group_segs(int nth, int rows)
 // Rebuild and upload the members' stage descriptors and tile prefix sums, cut
 // each (precision, chart) class into cache blocks and size each block's launch.
 // The caller has synchronised the group's stream.
+static void drop_group_graphs(teuk_group* g);
+
 static teuk_status group_upload(teuk_group* g)
 {
+    drop_group_graphs(g);
     const int cap = g->cap;
     int idx = 0;
     size_t soff = 0;
@@ -952,6 +1073,8 @@ static teuk_status group_upload(teuk_group* g)
                                     hipMemcpyHostToDevice, g->stream);
     if (!e) e = (int)hipStreamSynchronize(g->stream);
     if (e) return gfail(g, TEUK_ERR_DEVICE, std::string("group upload: ") + hipGetErrorString((hipError_t)e));
+    g->gexec.assign(g->blocks.size(), nullptr);
+    g->gphase.assign(g->blocks.size(), std::vector<long long>());
     return TEUK_OK;
 }
 
@@ -1025,31 +1148,141 @@ teuk_status teuk_group_remove(teuk_group* g, teuk_solver* h)
     return group_upload(g);
 }
 
+// nsteps steps of cache block bi, launch by launch on `stream` (the members'
+// samples too).
+static teuk_status group_block_eager(teuk_group* g, size_t bi, int64_t nsteps, hipStream_t stream)
+{
+    const size_t cap = (size_t)g->cap;
+    const GroupBlock& b = g->blocks[bi];
+    for (int64_t n = 0; n < nsteps; ++n) {
+        for (int stage = 1; stage <= 3; ++stage) {
+            const int e = launch_group_stage(g->d_args + (stage - 1) * cap + b.first, g->d_start + b.start, b.n,
+                                             b.tiles, b.grid, stage, b.cls % 4, b.cls / 4, stream);
+            if (e) return gfail(g, TEUK_ERR_DEVICE, std::string("group stage launch: ") +
+                                                       hipGetErrorString((hipError_t)e));
+        }
+        for (int k = b.first; k < b.first + b.n; ++k) {
+            teuk_solver* h = g->order[(size_t)k];
+            ++h->steps;
+            if (h->cfg.extract_every > 0 && h->steps % h->cfg.extract_every == 0) {
+                const hipStream_t own = h->stream;
+                h->stream = stream;
+                teuk_status st = record_sample(h);
+                h->stream = own;
+                if (st != TEUK_OK) return gfail(g, st, h->err);
+            }
+        }
+    }
+    return TEUK_OK;
+}
+
+static void drop_group_graphs(teuk_group* g)
+{
+    bool any = false;
+    for (hipGraphExec_t x : g->gexec) any = any || x;
+    if (any) (void)hipStreamSynchronize(g->stream);
+    for (hipGraphExec_t& x : g->gexec)
+        if (x) {
+            (void)hipGraphExecDestroy(x);
+            x = nullptr;
+        }
+    g->gexec.assign(g->blocks.size(), nullptr);
+    g->gphase.assign(g->blocks.size(), std::vector<long long>());
+}
+
+// The graph of graph_chunk steps of block bi, captured for its members'
+// current sampling phases (recaptured when they differ).
+static teuk_status capture_block(teuk_group* g, size_t bi)
+{
+    const GroupBlock& b = g->blocks[bi];
+    const int64_t chunk = g->graph_chunk;
+    std::vector<long long> phase;
+    for (int k = b.first; k < b.first + b.n; ++k) {
+        const teuk_solver* h = g->order[(size_t)k];
+        const long long every = h->cfg.extract_every;
+        if (every > 0 && chunk % every != 0)
+            return gfail(g, TEUK_ERR_INVALID_ARG, "graph mode: chunk_steps must be a multiple of every member's extract_every");
+        phase.push_back(every > 0 ? h->steps % every : 0);
+    }
+    if (g->gexec[bi] && g->gphase[bi] == phase) return TEUK_OK;
+    int e = 0;
+    if (g->gexec[bi]) {
+        (void)hipStreamSynchronize(g->stream);
+        (void)hipGraphExecDestroy(g->gexec[bi]);
+        g->gexec[bi] = nullptr;
+    }
+    if (!g->cap_stream) {
+        e = (int)hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);
+        if (e) {
+            g->cap_stream = nullptr;
+            return gfail(g, TEUK_ERR_DEVICE, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString((hipError_t)e));
+        }
+    }
+    std::vector<std::pair<long long, long long>> saved;
+    for (int k = b.first; k < b.first + b.n; ++k) saved.emplace_back(g->order[(size_t)k]->steps, g->order[(size_t)k]->samples);
+    e = (int)hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e) return gfail(g, TEUK_ERR_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString((hipError_t)e));
+    const teuk_status st = group_block_eager(g, bi, chunk, g->cap_stream);
+    hipGraph_t graph = nullptr;
+    e = (int)hipStreamEndCapture(g->cap_stream, &graph);
+    for (int k = b.first; k < b.first + b.n; ++k) {
+        g->order[(size_t)k]->steps = saved[(size_t)(k - b.first)].first;
+        g->order[(size_t)k]->samples = saved[(size_t)(k - b.first)].second;
+    }
+    if (st != TEUK_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e || !graph)
+        return gfail(g, TEUK_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString((hipError_t)(e ? e : (int)hipErrorUnknown)));
+    e = (int)hipGraphInstantiate(&g->gexec[bi], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e) {
+        g->gexec[bi] = nullptr;
+        return gfail(g, TEUK_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString((hipError_t)e));
+    }
+    g->gphase[bi] = phase;
+    return TEUK_OK;
+}
+
 teuk_status teuk_group_step(teuk_group* g, int64_t nsteps)
 {
     if (!g) return gfail(nullptr, TEUK_ERR_INVALID_ARG, "group is NULL");
     if (nsteps < 0) return gfail(g, TEUK_ERR_INVALID_ARG, "nsteps must be >= 0");
     if (g->mem.empty()) return TEUK_OK;
-    const size_t cap = (size_t)g->cap;
+    const int64_t chunk = g->graph_chunk;
+    if (g->gexec.size() != g->blocks.size()) drop_group_graphs(g);
     // block by block: a block runs all nsteps steps before the next starts
-    for (const GroupBlock& b : g->blocks) {
-        for (int64_t n = 0; n < nsteps; ++n) {
-            for (int stage = 1; stage <= 3; ++stage) {
-                const int e = launch_group_stage(g->d_args + (stage - 1) * cap + b.first, g->d_start + b.start, b.n,
-                                                 b.tiles, b.grid, stage, b.cls % 4, b.cls / 4, g->stream);
-                if (e) return gfail(g, TEUK_ERR_DEVICE, std::string("group stage launch: ") +
-                                                           hipGetErrorString((hipError_t)e));
-            }
-            for (int k = b.first; k < b.first + b.n; ++k) {
-                teuk_solver* h = g->order[(size_t)k];
-                ++h->steps;
-                if (h->cfg.extract_every > 0 && h->steps % h->cfg.extract_every == 0) {
-                    teuk_status st = record_sample(h);
-                    if (st != TEUK_OK) return gfail(g, st, h->err);
+    for (size_t bi = 0; bi < g->blocks.size(); ++bi) {
+        int64_t left = nsteps;
+        if (chunk > 0 && nsteps >= chunk) {
+            teuk_status st = capture_block(g, bi);
+            if (st != TEUK_OK) return st;
+            const GroupBlock& b = g->blocks[bi];
+            for (int64_t q = nsteps / chunk; q > 0; --q) {
+                const int e = (int)hipGraphLaunch(g->gexec[bi], g->stream);
+                if (e) return gfail(g, TEUK_ERR_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString((hipError_t)e));
+                for (int k = b.first; k < b.first + b.n; ++k) {
+                    teuk_solver* h = g->order[(size_t)k];
+                    h->steps += chunk;
+                    if (h->cfg.extract_every > 0) h->samples += chunk / h->cfg.extract_every;
                 }
             }
+            left = nsteps % chunk;
         }
+        teuk_status st = group_block_eager(g, bi, left, g->stream);
+        if (st != TEUK_OK) return st;
     }
+    return TEUK_OK;
+}
+
+teuk_status teuk_group_set_graph(teuk_group* g, int32_t chunk_steps)
+{
+    if (!g) return gfail(nullptr, TEUK_ERR_INVALID_ARG, "group is NULL");
+    if (chunk_steps < 0 || chunk_steps > kMaxGraphChunk)
+        return gfail(g, TEUK_ERR_INVALID_ARG, "chunk_steps must be in [0, " + std::to_string(kMaxGraphChunk) + "]");
+    drop_group_graphs(g);
+    g->graph_chunk = chunk_steps;
     return TEUK_OK;
 }
 
@@ -1077,6 +1310,8 @@ teuk_status teuk_group_info(const teuk_group* g, teuk_group_info_t* info)
 void teuk_group_destroy(teuk_group* g)
 {
     if (!g) return;
+    drop_group_graphs(g);
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     (void)hipStreamSynchronize(g->stream);
     for (teuk_solver* h : g->mem) h->group = nullptr;
     if (g->d_args) (void)hipFree(g->d_args);

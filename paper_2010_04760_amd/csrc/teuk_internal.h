@@ -81,8 +81,6 @@ int launch_group_stage(const StageArgs* args, const long long* start, int nmem, 
 int launch_dt_bound(const double* rtab, const double* ttab, const double* ctab, int nr, int nth, double dx,
                     double dth, unsigned long long* cell, void* stream);
 int launch_guard(const double* u, long long n, int* flag, void* stream);
-int launch_extract(const double* u, long long plane, int nr, int nth, int j_e, double* wave_slot,
-                   void* stream);
 int launch_coef_dump(const double* rtab, const double* ttab, const double* ctab, int nr, int nth, double* out,
                      void* stream);
 // Temporal blocking: one whole SSP-RK(3,3) step (tortoise chart, FP64
@@ -101,9 +99,13 @@ int launch_cmp_stage(const StageArgs& a, int stage, int scheme, int chart, void*
 int launch_dd_stage(const DDStageArgs& a, int stage, int weight_prec, void* stream);
 int launch_dd_extract(const double* u, long long plane, int nr, int nth, int j_e, double* slot, void* stream);
 int launch_dd_normalise(double* u, long long n, void* stream);
-// Horizon sample: Phi and d_rho Phi from the nodes j0 .. j0+3 with value
-// weights w[4] and derivative weights dw[4] (divided by dx); slot is [nth][4].
-int launch_horizon(const double* u, long long plane, int nr, int nth, int j0, const double* w, const double* dw,
-                   double* slot, void* stream);
+// One ring sample of the FP64 state: the waveform [nth][2] at radial index j_e
+// and, if hwave is not null, the horizon values [nth][4] (Phi and d_rho Phi,
+// Re and Im, from the nodes j0 .. j0+3 with value weights w[4] and derivative
+// weights dw[4], the latter divided by dx),
+// into slot *counter % ring of the rings wave and hwave; then *counter += 1.
+// One workgroup; the counter is device memory.
+int launch_sample(const double* u, long long plane, int nr, int nth, int j_e, double* wave, double* hwave, int j0,
+                  const double* w, const double* dw, long long ring, unsigned long long* counter, void* stream);
 
 }  // namespace teuk

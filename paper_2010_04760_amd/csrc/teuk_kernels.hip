@@ -1134,43 +1134,51 @@ __global__ __launch_bounds__(256) void guard_kernel(const double* __restrict__ u
     if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
-// ---------------------------------------------------------------- waveform sample
-__global__ __launch_bounds__(256) void extract_kernel(const double* __restrict__ u, long long plane, int nr,
-                                                      int nth, int j_e, double* __restrict__ slot)
-{
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < nth) {
-        slot[2 * k] = u[(size_t)k * nr + j_e];
-        slot[2 * k + 1] = u[plane + (size_t)k * nr + j_e];
-    }
-}
-
-// ---------------------------------------------------------------- horizon sample
-// Phi and d_rho Phi on the horizon from the four nodes j0 .. j0 + 3 with
-// interpolation weights w (value) and dw (derivative, already divided by dx).
+// ---------------------------------------------------------------- horizon weights
+// Weights of the four nodes j0 .. j0 + 3 for the value (w) and the
+// rho-derivative (dw, already divided by dx) on the horizon.
 struct HorizonWeights {
     double w[4], dw[4];
 };
-__global__ __launch_bounds__(256) void horizon_kernel(const double* __restrict__ u, long long plane, int nr,
-                                                      int nth, int j0, HorizonWeights W,
-                                                      double* __restrict__ slot)
+
+// ---------------------------------------------------------------- ring sample
+// One waveform sample (and, in the hyperboloidal chart, one horizon sample)
+// into ring slot counter % ring, then counter + 1.  The count lives in device
+// memory, so the same launch recorded once into a graph writes each replay's
+// samples to the slots that stepping launch by launch would.  One workgroup
+// walks the theta rows.
+__global__ __launch_bounds__(256) void sample_kernel(const double* __restrict__ u, long long plane, int nr, int nth,
+                                                     int j_e, double* __restrict__ wave, double* __restrict__ hwave,
+                                                     int j0, HorizonWeights W, long long ring,
+                                                     unsigned long long* counter)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < nth) {
-        const double* pr = u + (size_t)k * nr + j0;
+    __shared__ unsigned long long c;
+    if (threadIdx.x == 0) c = *counter;
+    __syncthreads();
+    const long long slot = (long long)(c % (unsigned long long)ring);
+    double* w = wave + (size_t)slot * nth * 2;
+    double* hw = hwave ? hwave + (size_t)slot * nth * 4 : nullptr;
+    for (int k = threadIdx.x; k < nth; k += blockDim.x) {
+        const double* pr = u + (size_t)k * nr;
         const double* pi = pr + plane;
-        double vr = 0.0, vi = 0.0, dr = 0.0, di = 0.0;
-        for (int q = 0; q < 4; ++q) {
-            vr += W.w[q] * pr[q];
-            vi += W.w[q] * pi[q];
-            dr += W.dw[q] * pr[q];
-            di += W.dw[q] * pi[q];
+        w[2 * k] = pr[j_e];
+        w[2 * k + 1] = pi[j_e];
+        if (hw) {
+            double vr = 0.0, vi = 0.0, dr = 0.0, di = 0.0;
+            for (int q = 0; q < 4; ++q) {
+                vr += W.w[q] * pr[j0 + q];
+                vi += W.w[q] * pi[j0 + q];
+                dr += W.dw[q] * pr[j0 + q];
+                di += W.dw[q] * pi[j0 + q];
+            }
+            hw[4 * k] = vr;
+            hw[4 * k + 1] = vi;
+            hw[4 * k + 2] = dr;
+            hw[4 * k + 3] = di;
         }
-        slot[4 * k] = vr;
-        slot[4 * k + 1] = vi;
-        slot[4 * k + 2] = dr;
-        slot[4 * k + 3] = di;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) *counter = c + 1;
 }
 
 // ---------------------------------------------------------------- coefficient dump
@@ -1339,26 +1347,21 @@ int launch_guard(const double* u, long long n, int* flag, void* stream)
     return (int)hipGetLastError();
 }
 
-int launch_extract(const double* u, long long plane, int nr, int nth, int j_e, double* wave_slot, void* stream)
+int launch_sample(const double* u, long long plane, int nr, int nth, int j_e, double* wave, double* hwave, int j0,
+                  const double* w, const double* dw, long long ring, unsigned long long* counter, void* stream)
 {
-    (void)hipGetLastError();
-    hipLaunchKernelGGL(extract_kernel, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, (hipStream_t)stream, u,
-                       plane, nr, nth, j_e, wave_slot);
-    return (int)hipGetLastError();
-}
-
-int launch_horizon(const double* u, long long plane, int nr, int nth, int j0, const double* w, const double* dw,
-                   double* slot, void* stream)
-{
-    if (j0 < 0 || j0 + 3 > nr - 1) return (int)hipErrorInvalidValue;
-    HorizonWeights W;
-    for (int q = 0; q < 4; ++q) {
-        W.w[q] = w[q];
-        W.dw[q] = dw[q];
+    if (j_e < 0 || j_e >= nr || ring < 1) return (int)hipErrorInvalidValue;
+    HorizonWeights W{};
+    if (hwave) {
+        if (j0 < 0 || j0 + 3 > nr - 1) return (int)hipErrorInvalidValue;
+        for (int q = 0; q < 4; ++q) {
+            W.w[q] = w[q];
+            W.dw[q] = dw[q];
+        }
     }
     (void)hipGetLastError();
-    hipLaunchKernelGGL(horizon_kernel, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, (hipStream_t)stream, u,
-                       plane, nr, nth, j0, W, slot);
+    hipLaunchKernelGGL(sample_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, u, plane, nr, nth, j_e, wave,
+                       hwave, j0, W, ring, counter);
     return (int)hipGetLastError();
 }
 
