@@ -313,6 +313,43 @@ const char* teuk_last_error(const teuk_solver* h);
  * Errors: INVALID_ARG, CAPACITY. */
 teuk_status teuk_host_coefficients(const teuk_config* cfg, double* out, size_t capacity);
 
+/* ------------------------------------------------------------------------
+ * Launch-shape autotuner.
+ *
+ * A stage launch of a single solve runs nstrips x segs workgroups (radial
+ * strips of 63 points, 114 for the blocked step, each cut into segs theta
+ * segments that its workgroups march), with segs derived from a workgroup
+ * budget: cfg->workgroups, or by default the number of stage workgroups the
+ * GPU holds at once.  teuk_tune times the stage kernels of cfg for a set of
+ * budgets from 1/4 to 4 times that default (one per distinct segs), each the
+ * best of three runs of `steps` steps (0: chosen to take about 2 ms) on a
+ * scratch solver of the same grid, chart, precisions and integrator with zero
+ * data, and remembers the fastest budget for that launch class (device, chart,
+ * weight and state precision, integrator, scheme, nr, ntheta) for the rest of
+ * the process: a later teuk_create of that class with workgroups = 0 uses it
+ * (teuk_info reports the workgroups in use).  The tiling does not change any
+ * point's arithmetic, so results are bitwise independent of the choice.  The
+ * scratch solver is allocated and freed inside the call; the stream is a
+ * private one.  Errors: INVALID_ARG, UNSUPPORTED (double-double state), the
+ * errors of teuk_create and teuk_step, DEVICE; teuk_tune_last_error() says why. */
+typedef struct {
+    int32_t workgroups;          /* fastest budget (the value teuk_create will use)  */
+    int32_t segs;                /* theta segments per strip it gives               */
+    int32_t default_workgroups;  /* the untuned default budget                      */
+    int32_t default_segs;
+    int32_t candidates;          /* budgets timed                                   */
+    int32_t steps;               /* steps per timed run                             */
+    double us_per_step;          /* fastest, microseconds per step                   */
+    double us_per_step_default;  /* the default budget, microseconds per step        */
+} teuk_tune_info_t;
+teuk_status teuk_tune(const teuk_config* cfg, int32_t steps, teuk_tune_info_t* info);
+
+/* Forget every tuned budget of the process (later solvers use the defaults). */
+void teuk_tune_forget(void);
+
+/* Message of the calling thread's last failed teuk_tune.  Never NULL. */
+const char* teuk_tune_last_error(void);
+
 /* Allocation-free stepping, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  Advances the caller's device state u ([4][ntheta][nr] FP64
@@ -415,6 +452,24 @@ teuk_status teuk_group_step(teuk_group* g, int64_t nsteps);
  * INVALID_ARG).  chunk_steps = 0 turns it off; at most 4096.
  * Errors: INVALID_ARG. */
 teuk_status teuk_group_set_graph(teuk_group* g, int32_t chunk_steps);
+
+/* Tune the group's tile height and cache-block size on its current members.
+ * Times rows_per_tile in {4, 8, 16, 32, 64} by cache blocks of
+ * {128, 256, 384, 512} MiB of member footprint (and the group's current
+ * shape), each the best of two runs of `steps` steps (0: chosen to take about
+ * 20 ms) on clones of the members -- same grids, classes and step sizes,
+ * starting from the members' current states, no waveform rings -- so the
+ * members themselves do not advance; then applies the fastest shape to the
+ * group.  Results do not depend on the shape (bitwise).  The clones double
+ * the group's device footprint during the call.  Synchronises the group's
+ * stream.  Errors: INVALID_ARG, STATE (no members), OUT_OF_MEMORY, DEVICE. */
+typedef struct {
+    int32_t rows_per_tile, block_mib;                  /* the shape applied            */
+    int32_t default_rows_per_tile, default_block_mib;  /* the shape before the call    */
+    int32_t candidates, steps;                         /* shapes timed, steps per run  */
+    double us_per_step, us_per_step_default;           /* microseconds per group step  */
+} teuk_group_tune_info_t;
+teuk_status teuk_group_tune(teuk_group* g, int32_t steps, teuk_group_tune_info_t* info);
 
 /* Group information (no synchronisation).  Errors: INVALID_ARG. */
 teuk_status teuk_group_info(const teuk_group* g, teuk_group_info_t* info);

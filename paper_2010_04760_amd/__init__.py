@@ -6,4 +6,4 @@ functions, which carry the C names.
 """
 from ._binding import *  # noqa: F401,F403
 from ._binding import (EXPORTED, LIB_PATH, Group, Solver, TeukError, make_config, teuk_config,  # noqa: F401
-                       teuk_device_ctx, teuk_group_info_t, teuk_info_t)
+                       teuk_device_ctx, teuk_group_info_t, teuk_group_tune_info_t, teuk_info_t, teuk_tune_info_t)

@@ -111,6 +111,25 @@ _lib.teuk_last_error.argtypes = [ctypes.c_void_p]
 _lib.teuk_last_error.restype = ctypes.c_char_p
 _lib.teuk_host_coefficients.argtypes = [_P(teuk_config), _dp, ctypes.c_size_t]
 _lib.teuk_host_coefficients.restype = ctypes.c_int
+class teuk_tune_info_t(ctypes.Structure):
+    _fields_ = [("workgroups", ctypes.c_int32), ("segs", ctypes.c_int32), ("default_workgroups", ctypes.c_int32),
+                ("default_segs", ctypes.c_int32), ("candidates", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("us_per_step", ctypes.c_double), ("us_per_step_default", ctypes.c_double)]
+
+
+class teuk_group_tune_info_t(ctypes.Structure):
+    _fields_ = [("rows_per_tile", ctypes.c_int32), ("block_mib", ctypes.c_int32),
+                ("default_rows_per_tile", ctypes.c_int32), ("default_block_mib", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("us_per_step", ctypes.c_double), ("us_per_step_default", ctypes.c_double)]
+
+
+_lib.teuk_tune.argtypes = [_P(teuk_config), ctypes.c_int32, _P(teuk_tune_info_t)]
+_lib.teuk_tune.restype = ctypes.c_int
+_lib.teuk_tune_forget.argtypes = []
+_lib.teuk_tune_forget.restype = None
+_lib.teuk_tune_last_error.argtypes = []
+_lib.teuk_tune_last_error.restype = ctypes.c_char_p
 _lib.teuk_set_graph.argtypes = [ctypes.c_void_p, ctypes.c_int32]
 _lib.teuk_set_graph.restype = ctypes.c_int
 _lib.teuk_step_noalloc.argtypes = [_P(teuk_config), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
@@ -131,6 +150,8 @@ _lib.teuk_group_remove.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
 _lib.teuk_group_remove.restype = ctypes.c_int
 _lib.teuk_group_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
 _lib.teuk_group_step.restype = ctypes.c_int
+_lib.teuk_group_tune.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+_lib.teuk_group_tune.restype = ctypes.c_int
 _lib.teuk_group_set_graph.argtypes = [ctypes.c_void_p, ctypes.c_int32]
 _lib.teuk_group_set_graph.restype = ctypes.c_int
 _lib.teuk_group_info.argtypes = [ctypes.c_void_p, _P(teuk_group_info_t)]
@@ -144,7 +165,8 @@ EXPORTED = ["teuk_default_config", "teuk_footprint_bytes", "teuk_create", "teuk_
             "teuk_extract", "teuk_info", "teuk_check_finite", "teuk_destroy", "teuk_last_error",
             "teuk_host_coefficients", "teuk_group_create", "teuk_group_add", "teuk_group_remove",
             "teuk_group_step", "teuk_group_info", "teuk_group_destroy", "teuk_group_last_error",
-            "teuk_step_noalloc", "teuk_set_graph", "teuk_group_set_graph"]
+            "teuk_step_noalloc", "teuk_set_graph", "teuk_group_set_graph", "teuk_tune", "teuk_tune_forget",
+            "teuk_tune_last_error", "teuk_group_tune"]
 
 
 class TeukError(RuntimeError):
@@ -203,6 +225,22 @@ def teuk_extract(h: int, what: int, capacity: int) -> np.ndarray:
         raise TeukError(st, _lib.teuk_last_error(h).decode() + " (state copied for inspection)")
     _check(st, h)
     return out[: written.value]
+
+
+def teuk_tune(cfg: teuk_config, steps: int = 0) -> teuk_tune_info_t:
+    info = teuk_tune_info_t()
+    st = _lib.teuk_tune(ctypes.byref(cfg), int(steps), ctypes.byref(info))
+    if st != TEUK_OK:
+        raise TeukError(st, _lib.teuk_tune_last_error().decode())
+    return info
+
+
+def teuk_tune_forget() -> None:
+    _lib.teuk_tune_forget()
+
+
+def teuk_tune_last_error() -> str:
+    return _lib.teuk_tune_last_error().decode()
 
 
 def teuk_set_graph(h: int, chunk_steps: int) -> None:
@@ -265,6 +303,12 @@ def teuk_group_remove(g: int, h: int) -> None:
 
 def teuk_group_step(g: int, nsteps: int) -> None:
     _gcheck(_lib.teuk_group_step(g, int(nsteps)), g)
+
+
+def teuk_group_tune(g: int, steps: int = 0) -> teuk_group_tune_info_t:
+    info = teuk_group_tune_info_t()
+    _gcheck(_lib.teuk_group_tune(g, int(steps), ctypes.byref(info)), g)
+    return info
 
 
 def teuk_group_set_graph(g: int, chunk_steps: int) -> None:
@@ -441,6 +485,10 @@ class Group:
     def set_graph(self, chunk_steps: int):
         """Graph mode: each cache block replays a captured graph of chunk_steps steps (0: off)."""
         teuk_group_set_graph(self.g, chunk_steps)
+
+    def tune(self, steps: int = 0) -> teuk_group_tune_info_t:
+        """Time tile heights and cache-block sizes on clones of the members; apply the fastest."""
+        return teuk_group_tune(self.g, steps)
 
     def info(self) -> teuk_group_info_t:
         return teuk_group_info(self.g)

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libteuk.so")
-SOURCES = ["teuk_api.hip", "teuk_kernels.hip", "teuk_kernels_dd.hip", "teuk_kernels_cmp.hip", "teuk_background.cpp"]
+SOURCES = ["teuk_api.hip", "teuk_tune.hip", "teuk_kernels.hip", "teuk_kernels_dd.hip", "teuk_kernels_cmp.hip", "teuk_background.cpp"]
 # host-only sources that need the GNU C++ compiler (binary128 via libquadmath)
 GXX_SOURCES = ["teuk_background_dd.cpp"]
 GXX_FLAGS = ["-O2", "-std=gnu++17", "-fPIC", "-Wall", "-fno-fast-math"]

@@ -2,6 +2,7 @@
 // the SSP-RK(3,3) step loop, waveform ring buffer, guard and extraction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -90,6 +91,7 @@ struct teuk_group {
     int cap = 0;                                    // max members
     int workgroups = 0;                             // per stage launch; 0 = one per tile
     int rows = 8;                                   // theta rows per tile (target)
+    long long block_bytes = kGroupBlockBytes;       // cache-block size (member footprints)
     std::vector<teuk_solver*> mem;                  // insertion order
     StageArgs* d_args = nullptr;                    // [3][cap]: per stage, members by weight precision
     long long* d_start = nullptr;                   // [2 cap + 2]: each block's tile prefix sums, from 0
@@ -414,9 +416,13 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     h->dx = (cfg->x_max - cfg->x_min) / (cfg->nr - 1);
     h->dth = M_PI / cfg->ntheta;
     h->nstrips = (cfg->nr + kStripPoints - 1) / kStripPoints;
+    // the caller's workgroup budget, else the one teuk_tune found for this
+    // launch class on this device, else (0) all the GPU holds at once
+    teuk_config eff = *cfg;
+    if (eff.workgroups == 0) eff.workgroups = tuned_workgroups(*cfg);
     // (the double-double kernel runs one wave per strip and theta row)
-    h->segs[0] = dd ? 1 : pick_segs(*cfg, h->nstrips, cfg->weight_prec, true);
-    h->segs[1] = dd ? 1 : pick_segs(*cfg, h->nstrips, cfg->weight_prec, false);
+    h->segs[0] = dd ? 1 : pick_segs(eff, h->nstrips, cfg->weight_prec, true);
+    h->segs[1] = dd ? 1 : pick_segs(eff, h->nstrips, cfg->weight_prec, false);
     if (h->segs[0] <= 0 || h->segs[1] <= 0 || (long long)h->nstrips * h->segs[0] > (1LL << 31) - 1 ||
         (long long)h->nstrips * h->segs[1] > (1LL << 31) - 1) {
         free_solver(h);
@@ -424,7 +430,7 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     }
     if (cfg->integrator == TEUK_RK_SSP33_BLOCKED) {
         h->bstrips = (cfg->nr + kBlockedPoints - 1) / kBlockedPoints;
-        long long cap = cfg->workgroups > 0 ? cfg->workgroups : blocked_grid();
+        long long cap = eff.workgroups > 0 ? eff.workgroups : blocked_grid();
         long long segs = cap / h->bstrips;
         if (segs > cfg->ntheta) segs = cfg->ntheta;
         if (segs < 1) segs = 1;
@@ -1038,7 +1044,7 @@ static teuk_status group_upload(teuk_group* g)
         open_block();
         for (teuk_solver* h : g->mem) {
             if (h->cfg.weight_prec + 4 * h->cfg.chart != c) continue;
-            if (blk.n > 0 && bytes + (long long)h->bytes > kGroupBlockBytes) {
+            if (blk.n > 0 && bytes + (long long)h->bytes > g->block_bytes) {
                 close_block();
                 open_block();
             }
@@ -1286,6 +1292,135 @@ teuk_status teuk_group_set_graph(teuk_group* g, int32_t chunk_steps)
     return TEUK_OK;
 }
 
+// Microseconds per step of group t: the best of two timed runs of n steps
+// after two warm-up steps, on t's stream.
+static teuk_status time_group(teuk_group* t, int64_t n, double* us)
+{
+    teuk_status st = teuk_group_step(t, 2);
+    if (st != TEUK_OK) return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int e = (int)hipEventCreate(&e0);
+    if (!e) e = (int)hipEventCreate(&e1);
+    double best = 0.0;
+    for (int rep = 0; rep < 2 && !e && st == TEUK_OK; ++rep) {
+        e = (int)hipEventRecord(e0, t->stream);
+        if (!e) st = teuk_group_step(t, n);
+        if (!e && st == TEUK_OK) e = (int)hipEventRecord(e1, t->stream);
+        if (!e && st == TEUK_OK) e = (int)hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (!e && st == TEUK_OK) e = (int)hipEventElapsedTime(&ms, e0, e1);
+        const double v = 1e3 * (double)ms / (double)n;
+        if (!e && st == TEUK_OK && (rep == 0 || v < best)) best = v;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st != TEUK_OK) return st;
+    if (e) return gfail(t, TEUK_ERR_DEVICE, std::string("timing events: ") + hipGetErrorString((hipError_t)e));
+    *us = best;
+    return TEUK_OK;
+}
+
+teuk_status teuk_group_tune(teuk_group* g, int32_t steps, teuk_group_tune_info_t* out)
+{
+    if (!g) return gfail(nullptr, TEUK_ERR_INVALID_ARG, "group is NULL");
+    if (!out) return gfail(g, TEUK_ERR_INVALID_ARG, "out is NULL");
+    if (steps < 0) return gfail(g, TEUK_ERR_INVALID_ARG, "steps must be >= 0");
+    std::memset(out, 0, sizeof(*out));
+    if (g->mem.empty()) return gfail(g, TEUK_ERR_STATE, "the group has no members to tune on");
+    int e = (int)hipStreamSynchronize(g->stream);
+    if (e) return gfail(g, TEUK_ERR_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString((hipError_t)e));
+    hipStream_t ts = nullptr;
+    e = (int)hipStreamCreateWithFlags(&ts, hipStreamNonBlocking);
+    if (e) return gfail(g, TEUK_ERR_DEVICE, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString((hipError_t)e));
+    // clones of the members: same grids, classes and step sizes, no waveform
+    // ring, starting from the members' current states
+    std::vector<teuk_solver*> clones;
+    teuk_group* tg = nullptr;
+    teuk_status st = TEUK_OK;
+    std::string why;
+    for (teuk_solver* h : g->mem) {
+        teuk_config c = h->cfg;
+        c.extract_every = 0;
+        c.max_samples = 0;
+        c.dt = h->dt;
+        teuk_device_ctx ctx{ts, nullptr, 0};
+        teuk_solver* x = nullptr;
+        st = teuk_create(&c, &ctx, &x);
+        if (st != TEUK_OK) { why = std::string("clone: ") + teuk_last_error(nullptr); break; }
+        clones.push_back(x);
+        st = teuk_set_initial(x, h->u[0], 1);
+        if (st != TEUK_OK) { why = std::string("clone state: ") + x->err; break; }
+    }
+    if (st == TEUK_OK) {
+        teuk_device_ctx gctx{ts, nullptr, 0};
+        st = teuk_group_create(&gctx, (int32_t)clones.size(), g->workgroups, g->rows, &tg);
+        if (st != TEUK_OK) why = g_group_err;
+        for (size_t i = 0; i < clones.size() && st == TEUK_OK; ++i) {
+            st = teuk_group_add(tg, clones[i]);
+            if (st != TEUK_OK) why = tg->err;
+        }
+    }
+    const int rows_c[] = {4, 8, 16, 32, 64};
+    const long long mib_c[] = {128, 256, 384, 512};
+    int best_rows = g->rows;
+    long long best_bytes = g->block_bytes;
+    double best_us = 0.0, default_us = 0.0;
+    int cand = 0;
+    int64_t n = steps;
+    if (st == TEUK_OK && n == 0) {
+        // aim at about 20 ms per timed run
+        double us = 0.0;
+        st = time_group(tg, 1, &us);
+        if (st != TEUK_OK) why = tg->err;
+        n = (int64_t)std::min(200.0, std::max(2.0, 20000.0 / std::max(us, 1.0)));
+    }
+    auto try_shape = [&](int rows, long long bytes, double* us) {
+        tg->rows = rows;
+        tg->block_bytes = bytes;
+        teuk_status s2 = group_upload(tg);
+        if (s2 == TEUK_OK) s2 = time_group(tg, n, us);
+        if (s2 != TEUK_OK) why = tg->err;
+        return s2;
+    };
+    if (st == TEUK_OK) st = try_shape(g->rows, g->block_bytes, &default_us);
+    if (st == TEUK_OK) {
+        best_us = default_us;
+        cand = 1;
+    }
+    for (int r : rows_c) {
+        for (long long mb : mib_c) {
+            if (st != TEUK_OK) break;
+            if (r == g->rows && (mb << 20) == g->block_bytes) continue;
+            double us = 0.0;
+            st = try_shape(r, mb << 20, &us);
+            if (st != TEUK_OK) break;
+            ++cand;
+            if (us < best_us) {
+                best_us = us;
+                best_rows = r;
+                best_bytes = mb << 20;
+            }
+        }
+    }
+    if (tg) teuk_group_destroy(tg);
+    for (teuk_solver* x : clones) teuk_destroy(x);
+    (void)hipStreamDestroy(ts);
+    if (st != TEUK_OK) return gfail(g, st, "group tuning: " + why);
+    out->default_rows_per_tile = g->rows;
+    out->default_block_mib = (int32_t)(g->block_bytes >> 20);
+    g->rows = best_rows;
+    g->block_bytes = best_bytes;
+    st = group_upload(g);
+    if (st != TEUK_OK) return st;
+    out->rows_per_tile = best_rows;
+    out->block_mib = (int32_t)(best_bytes >> 20);
+    out->candidates = cand;
+    out->steps = (int32_t)n;
+    out->us_per_step = best_us;
+    out->us_per_step_default = default_us;
+    return TEUK_OK;
+}
+
 teuk_status teuk_group_info(const teuk_group* g, teuk_group_info_t* info)
 {
     if (!g) return gfail(nullptr, TEUK_ERR_INVALID_ARG, "group is NULL");
@@ -1423,8 +1558,10 @@ extern "C" teuk_status teuk_step_noalloc(const teuk_config* cfg, double* u, int6
         }
     }
     const int nstrips = (cfg->nr + kStripPoints - 1) / kStripPoints;
-    const int segs1 = pick_segs(*cfg, nstrips, cfg->weight_prec, true);
-    const int segs23 = pick_segs(*cfg, nstrips, cfg->weight_prec, false);
+    teuk_config eff = *cfg;
+    if (eff.workgroups == 0) eff.workgroups = tuned_workgroups(*cfg);
+    const int segs1 = pick_segs(eff, nstrips, cfg->weight_prec, true);
+    const int segs23 = pick_segs(eff, nstrips, cfg->weight_prec, false);
     if (segs1 <= 0 || segs23 <= 0) return fail(nullptr, TEUK_ERR_UNSUPPORTED, "occupancy query failed");
     double* u1 = (double*)(base + kNaOffU1);
     double* u2 = (double*)(base + kNaOffU2);

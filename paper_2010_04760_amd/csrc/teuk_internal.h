@@ -63,6 +63,10 @@ struct DDStageArgs {
     double dt, eps, parity;
 };
 
+// Workgroup budget that teuk_tune found fastest for c's launch class on the
+// current device, or 0 if it has not been tuned.
+int tuned_workgroups(const teuk_config& c);
+
 // Resident workgroup count of a stage-kernel instantiation on the current
 // device (0 if the weight precision is not built).  The launch uses
 // nstrips * segs workgroups with segs chosen from it.

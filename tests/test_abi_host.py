@@ -43,9 +43,15 @@ int main(void) {
   printf("teuk_config %zu\\n", sizeof(teuk_config));
   printf("teuk_device_ctx %zu\\n", sizeof(teuk_device_ctx));
   printf("teuk_info_t %zu\\n", sizeof(teuk_info_t));
+  printf("teuk_group_info_t %zu\\n", sizeof(teuk_group_info_t));
+  printf("teuk_tune_info_t %zu\\n", sizeof(teuk_tune_info_t));
+  printf("teuk_group_tune_info_t %zu\\n", sizeof(teuk_group_tune_info_t));
   F(teuk_config, M) F(teuk_config, a) F(teuk_config, x_extract) F(teuk_config, workgroups) F(teuk_config, S)
   F(teuk_config, state_prec) F(teuk_config, integrator) F(teuk_config, scheme) F(teuk_config, ko_sigma)
   F(teuk_info_t, samples) F(teuk_info_t, dt_bound) F(teuk_device_ctx, workspace_bytes)
+  F(teuk_group_info_t, workgroups) F(teuk_group_info_t, points)
+  F(teuk_tune_info_t, steps) F(teuk_tune_info_t, us_per_step) F(teuk_tune_info_t, us_per_step_default)
+  F(teuk_group_tune_info_t, steps) F(teuk_group_tune_info_t, us_per_step) F(teuk_group_tune_info_t, us_per_step_default)
   return 0; }
 """)
     exe = tmp_path / "probe"
@@ -55,6 +61,8 @@ int main(void) {
     assert int(out["teuk_config"]) == ctypes.sizeof(T.teuk_config)
     assert int(out["teuk_device_ctx"]) == ctypes.sizeof(T.teuk_device_ctx)
     assert int(out["teuk_info_t"]) == ctypes.sizeof(T.teuk_info_t)
+    for st in ("teuk_group_info_t", "teuk_tune_info_t", "teuk_group_tune_info_t"):
+        assert int(out[st]) == ctypes.sizeof(getattr(T, st)), st
     for key, val in out.items():
         if "." in key:
             s, f = key.split(".")
