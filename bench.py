@@ -70,14 +70,21 @@ def log(msg: str):
     print("# " + msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, u0, target_s: float):
-    """The FP64 oracle on the host cores, on the same grid and initial data."""
-    from oracle import solver as S
-    threads = min(os.cpu_count() or 1, 16)
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(S, o, u0, dt, points, target_s, threads):
+    """Point-updates/s of the oracle on `threads` OpenMP threads, timed over
+    whole steps until target_s seconds have passed."""
     S.set_threads(threads)
-    prob = S.Problem(wl.s, wl.m, wl.a, wl.nr, wl.nth, wl.x_min, wl.x_max)
-    o = S.TeukOracle(prob)
-    dt = o.dt_bound(0.5)
     u, _ = o.evolve(u0, dt, 1)                 # first call: thread start-up, page faults
     n, el, chunk = 0, 0.0, 1
     while el < target_s:
@@ -86,10 +93,28 @@ def cpu_baseline(wl, u0, target_s: float):
         dt_chunk = time.perf_counter() - t0
         n, el = n + chunk, el + dt_chunk
         chunk = max(1, min(64, int(0.25 * target_s / max(dt_chunk / chunk, 1e-4))))
-    return {"value": 3.0 * wl.points * n / el, "unit": "point-updates/s", "cores": S.num_threads(),
-            "kind": "oracle",
-            "sample": f"{wl.nr}x{wl.nth} grid ({wl.name.split(',')[0]}), {n} SSP-RK3 steps "
-                      f"({3 * wl.points * n:.3g} point-updates, {el:.1f} s) on {S.num_threads()} OpenMP threads"}
+    return 3.0 * points * n / el, n, el, S.num_threads()
+
+
+def cpu_baseline(wl, u0, target_s: float):
+    """The FP64 oracle on the host, on the same grid and initial data: one
+    thread, and every core the process may use (at most 16, the host share of
+    one GPU).  `value` is the all-cores rate."""
+    from oracle import solver as S
+    prob = S.Problem(wl.s, wl.m, wl.a, wl.nr, wl.nth, wl.x_min, wl.x_max)
+    o = S.TeukOracle(prob)
+    dt = o.dt_bound(0.5)
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    many = max(1, min(avail, 16))
+    r1, n1, e1, t1 = _oracle_rate(S, o, u0, dt, wl.points, 0.4 * target_s, 1)
+    rn, nn, en, tn = _oracle_rate(S, o, u0, dt, wl.points, 0.6 * target_s, many)
+    grid = f"{wl.nr}x{wl.nth} grid ({wl.name.split(':')[0]})"
+    return {"value": rn, "unit": "point-updates/s", "cores": tn, "kind": "oracle",
+            "sample": f"{grid}, {nn} SSP-RK3 steps ({3 * wl.points * nn:.3g} point-updates, {en:.1f} s) "
+                      f"on {tn} OpenMP threads; single thread: {n1} steps in {e1:.1f} s",
+            "single_thread": {"value": r1, "unit": "point-updates/s", "cores": t1},
+            "speedup_all_cores_vs_one": rn / r1,
+            "cpu": {"model": cpu_model(), "nproc": os.cpu_count(), "affinity": avail}}
 
 
 def roofline(points_per_launch: float, t_launch: float, traffic):
@@ -145,28 +170,31 @@ def copy_probe(mib, torch):
 
 # ----------------------------------------------------------------------------- C2: one solve
 def bench_single(args, torch, T, W):
-    wl = W.C2
-    steps = 20000 if args.steps is None else args.steps
+    c1 = args.workload == "C1"
+    wl = W.C1 if c1 else W.C2
+    steps = (wl.steps if c1 else 20000) if args.steps is None else args.steps
     warmup = 100 if args.warmup is None else args.warmup
     weights = args.weights or "fp64"
     u0 = W.gaussian_pulse(wl)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
 
-    def run(wp, state="fp64", nsteps=None, nwarm=None, integrator="rk3", every=None):
-        """Warm up, then time `steps` steps with HIP events on the solver's
+    def run(wp, state="fp64", nsteps=None, nwarm=None, integrator="rk3", every=None, graph=0):
+        """Warm up, then time `nsteps` steps with HIP events on the solver's
         stream.  Returns (seconds, wall seconds, info, waveform samples)."""
         nsteps = steps if nsteps is None else nsteps
         nwarm = warmup if nwarm is None else nwarm
         sv = T.Solver(solver_config(T, wl, wp, nwarm + nsteps, args.workgroups, state=state,
                                     integrator=integrator, every=every), stream=stream)
         sv.set_initial(u0)
-        log(f"{state}/{wp}: warmup {nwarm} steps")
+        log(f"{state}/{wp}/{integrator}{' graph ' + str(graph) if graph else ''}: warmup {nwarm} steps")
         sv.step(nwarm)
+        if graph:
+            sv.set_graph(graph)          # captured here, at the current sampling phase (untimed)
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
-        log(f"{state}/{wp}: timing {nsteps} steps")
+        log(f"{state}/{wp}/{integrator}: timing {nsteps} steps")
         w0 = time.perf_counter()
         ev0.record(stream)
         sv.step(nsteps)
@@ -180,7 +208,37 @@ def bench_single(args, torch, T, W):
         sv.close()
         return sec, wall, info, wave
 
-    gpu_s, wall, info, wave = run(weights)
+    # Launch shapes from the project's autotuner (it times stage-kernel
+    # workgroup budgets on a scratch solver of this grid; solvers created
+    # afterwards with workgroups = 0 use the winner).
+    tuned = {}
+    if not args.no_tune and args.workgroups == 0:
+        for integ in ("rk3", "rk3_blocked") if (weights == "fp64" and not args.no_blocked) else ("rk3",):
+            cfg = solver_config(T, wl, weights, 1, 0, every=0, integrator=integ)
+            log(f"autotuner: {integ}")
+            ti = T.teuk_tune(cfg, 0)
+            tuned[integ] = {"workgroups": ti.workgroups, "segs_per_strip": ti.segs, "candidates": ti.candidates,
+                            "us_per_step": ti.us_per_step, "default_workgroups": ti.default_workgroups,
+                            "default_segs_per_strip": ti.default_segs, "us_per_step_default": ti.us_per_step_default}
+
+    # Reduced-precision weights over the workload's full length (the waveform
+    # at x_e needs the pulse to have passed it), before the headline timing:
+    # speed and waveform error (relative L2 over every sample) against FP64.
+    mixed = None
+    if weights == "fp64" and not args.no_mixed:
+        full = wl.steps
+        sec64f, _, _, wave64f = run("fp64", nsteps=full, nwarm=0)
+        mixed = {"steps": full, "fp64": {"value": 3.0 * wl.points * full / sec64f, "seconds": sec64f}}
+        for wp in ("fp32", "fp16", "bf16"):
+            sec_w, _, _, wave_w = run(wp, nsteps=full, nwarm=0)
+            mixed[wp] = {"value": 3.0 * wl.points * full / sec_w, "seconds": sec_w,
+                         "speedup_vs_fp64": sec64f / sec_w,
+                         "waveform_rel_l2_vs_fp64": float(np.linalg.norm(wave_w - wave64f) / np.linalg.norm(wave64f))}
+        mixed["waveform"] = (f"{wave64f.shape[0]} samples x {wl.nth} rows at r* = {wl.x_e}, t = 0 .. "
+                             f"{full} steps; the FP64 run is the parity-tested path")
+
+    graph = args.graph if args.graph >= 0 else (50 if c1 else 10)
+    gpu_s, wall, info, wave = run(weights, graph=graph)
     pu = 3.0 * wl.points * steps
     # 3 stage launches per step; the sample kernel (one per 10 steps) is
     # included in the time and is < 0.5 % of it.
@@ -191,19 +249,26 @@ def bench_single(args, torch, T, W):
         "data": "synthetic",
         "config": {"workload": wl.name, "nr": wl.nr, "ntheta": wl.nth, "s": wl.s, "m": wl.m, "a": wl.a,
                    "weights": weights, "dt": info.dt, "workgroups": info.workgroups,
-                   "extract_every": wl.every, "seed": wl.seed},
-        "roofline": roofline(wl.points, gpu_s / (3 * steps), measured_traffic(weights)),
+                   "extract_every": wl.every, "seed": wl.seed, "graph_chunk_steps": graph,
+                   "launch_shape": "autotuned" if "rk3" in tuned else ("given" if args.workgroups else "default")},
+        "roofline": roofline(wl.points, gpu_s / (3 * steps), measured_traffic(weights) if not c1 else None),
         "wall_s": wall,
     }
-    if weights == "fp64" and not args.no_mixed:
-        # Mixed-precision weights on the same workload: speed and waveform
-        # error (relative L2 over all samples) against the FP64 run above.
-        mixed = {}
-        for wp in ("fp32", "fp16", "bf16"):
-            sec_w, _, _, wave_w = run(wp)
-            err = float(np.linalg.norm(wave_w - wave) / np.linalg.norm(wave))
-            mixed[wp] = {"value": pu / sec_w, "speedup_vs_fp64": gpu_s / sec_w, "waveform_rel_l2_vs_fp64": err}
+    if tuned:
+        out["autotuner"] = tuned
+    if mixed is not None:
         out["mixed_precision"] = mixed
+    if not args.no_graph_leg:
+        # the same steps with the other launch mode (graph replay vs one launch per stage)
+        other = 0 if graph else (50 if c1 else 10)   # a multiple of the waveform cadence (10 steps)
+        sec_o, _, _, wave_o = run(weights, graph=other)
+        out["graph"] = {"chunk_steps": other, "ms_per_step": sec_o / steps * 1e3, "value": pu / sec_o,
+                        "speedup_vs_headline": gpu_s / sec_o, "waveform_identical": bool(np.array_equal(wave_o, wave))}
+    if c1:
+        if not args.no_cpu_baseline:
+            log("cpu baseline (oracle)")
+            out["cpu_baseline"] = cpu_baseline(wl, u0, args.cpu_seconds)
+        return out
     if weights == "fp64" and not args.no_blocked:
         # Temporal blocking: the same SSP-RK(3,3) step as one launch per step
         # (u(1), u(2) in LDS; 64 B of HBM traffic per point-step; "traffic" is
@@ -506,11 +571,21 @@ def bench_batched(args, torch, T, W):
     g = T.Group(len(mix), workgroups=args.workgroups, rows_per_tile=args.rows_per_tile, stream=stream)
     for sv in members:
         g.add(sv)
+    tuned = None
+    if not args.no_tune and args.rows_per_tile == 0:
+        # tile height x cache-block size, timed on clones of the members
+        log("C4: group autotuner")
+        ti = g.tune(0)
+        tuned = {"rows_per_tile": ti.rows_per_tile, "block_mib": ti.block_mib, "candidates": ti.candidates,
+                 "us_per_step": ti.us_per_step, "default_rows_per_tile": ti.default_rows_per_tile,
+                 "default_block_mib": ti.default_block_mib, "us_per_step_default": ti.us_per_step_default}
+    graph = max(args.graph, 0)
     ginfo = g.info()
     log(f"C4: warmup {warmup} steps")
     g.step(warmup)
+    g.set_graph(graph)                   # captured here (untimed)
     torch.cuda.synchronize()
-    log(f"C4: timing {steps} steps")
+    log(f"C4: timing {steps} steps{' (graph chunk ' + str(graph) + ')' if graph else ''}")
     w0 = time.perf_counter()
     ev0.record(stream)
     g.step(steps)
@@ -518,6 +593,19 @@ def bench_batched(args, torch, T, W):
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     gpu_s = ev0.elapsed_time(ev1) / 1e3
+    other = None
+    if not args.no_graph_leg:
+        # the same number of steps in the other launch mode
+        og = 0 if graph else 10
+        g.set_graph(og)
+        torch.cuda.synchronize()
+        log(f"C4: timing {steps} steps, graph chunk {og}")
+        ev0.record(stream)
+        g.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        other = {"chunk_steps": og, "ms_per_step": ev0.elapsed_time(ev1) / steps,
+                 "speedup_vs_headline": gpu_s / (ev0.elapsed_time(ev1) / 1e3)}
     for sv in members:
         sv.check_finite()
     g.close()
@@ -533,12 +621,17 @@ def bench_batched(args, torch, T, W):
                                f"{points} points, {steps} steps",
                    "solves": len(mix), "points": points, "weights": weights, "seeds": "1000..1063",
                    "workgroups_per_stage": int(ginfo.workgroups), "tiles_per_stage": int(ginfo.tiles),
-                   "rows_per_tile": args.rows_per_tile or 8},
+                   "rows_per_tile": tuned["rows_per_tile"] if tuned else (args.rows_per_tile or 8),
+                   "block_mib": tuned["block_mib"] if tuned else 256, "graph_chunk_steps": graph},
         "roofline": roofline(points, gpu_s / (3 * steps), None),
         "alone_sequential": {"value": 3.0 * points * alone_steps / alone_s, "steps": alone_steps},
         "batching_speedup": (pu / gpu_s) / (3.0 * points * alone_steps / alone_s),
         "wall_s": wall,
     }
+    if tuned:
+        out["autotuner"] = tuned
+    if other:
+        out["graph"] = other
     if not args.no_cpu_baseline:
         # the oracle on the member nearest the mean size
         mean = points / len(mix)
@@ -565,7 +658,8 @@ def bench_serving(args, torch, T, W):
     budget = int(args.hbm_budget_gb * (1 << 30)) if args.hbm_budget_gb > 0 else None
     log(f"C5: {nreq} requests, offered load {load:.2f} x {cap_rate:.3g} pu/s = {rate:.3g} req/s")
     srv = serving.Server(max_members=nreq, hbm_budget=budget, chunk_steps=args.chunk_steps,
-                         workgroups=args.workgroups, rows_per_tile=args.rows_per_tile)
+                         workgroups=args.workgroups, rows_per_tile=args.rows_per_tile,
+                         graph_chunk=max(args.graph, 0))
     res = srv.run(reqs, arrivals, progress=log)
     lat = np.array([r.latency for r in res.done])
     queued = np.array([r.queued for r in res.done])
@@ -577,7 +671,8 @@ def bench_serving(args, torch, T, W):
         "dtype": f"f64 (weights {reqs[0].weights})", "data": "synthetic",
         "config": {"workload": f"C5: {nreq} Poisson requests, steps~U{{5000..50000}}, offered load {load}",
                    "requests": nreq, "offered_load": load, "capacity_rate": cap_rate, "arrival_rate": rate,
-                   "hbm_budget_bytes": res.budget, "chunk_steps": args.chunk_steps},
+                   "hbm_budget_bytes": res.budget, "chunk_steps": args.chunk_steps,
+                   "graph_chunk_steps": max(args.graph, 0)},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "max": float(lat.max()), "mean": float(lat.mean())},
         "queue_s": {"p50": float(np.percentile(queued, 50)), "p99": float(np.percentile(queued, 99))},
@@ -588,7 +683,7 @@ def bench_serving(args, torch, T, W):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C3H", "C4", "C5"])
+    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C3H", "C4", "C5"])
     ap.add_argument("--steps", type=int, default=None,
                     help="timed SSP-RK3 steps (C2: 20000, C3: 200000, C4: 2000)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (C2: 100, C4: 20)")
@@ -598,12 +693,19 @@ def main():
                     help="stage-kernel workgroups (C2, 0: all the GPU holds at once; C4/C5, 0: one per tile)")
     ap.add_argument("--rows-per-tile", type=int, default=0, help="C4/C5: theta rows per group tile (0: 8)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="C1/C2: skip the launch-shape autotuner")
+    ap.add_argument("--graph", type=int, default=-1,
+                    help="C1/C2/C4/C5: steps per captured HIP graph of the headline run (0: one launch per "
+                         "stage; default: 50 for C1, 10 for C2, 0 for C4/C5)")
+    ap.add_argument("--no-graph-leg", action="store_true",
+                    help="C1/C2/C4: skip the run in the other launch mode (graph vs launch by launch)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/FP16/BF16-weight runs")
     ap.add_argument("--no-rk104", action="store_true", help="C2: skip the SSP-RK(10,4) run")
     ap.add_argument("--no-blocked", action="store_true", help="C2: skip the temporally blocked run")
     ap.add_argument("--quad-steps", type=int, default=1000,
                     help="C2: steps of the double-double state runs (0: skip them)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="seconds of oracle time for the CPU baseline (40 %% on one thread, 60 %% on all cores)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before the solve, run a plain device copy of MIB MiB three times (a known-size "
                          "kernel that calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -623,8 +725,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one MI355X only: the library has no multi-GPU path "
-              "(a single solve would shard into radial slabs; see the design notes).", file=sys.stderr)
+        print("bench.py measures one MI355X only: the library has no multi-GPU path (a single solve would "
+              "shard into radial slabs exchanging a three-cell halo per stage, and batched solves would be "
+              "dealt out whole per GPU).", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -634,7 +737,7 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe > 0:
         copy_probe(args.copy_probe, torch)
-    fn = {"C2": bench_single, "C3": bench_sweep, "C3H": bench_horizon, "C4": bench_batched,
+    fn = {"C1": bench_single, "C2": bench_single, "C3": bench_sweep, "C3H": bench_horizon, "C4": bench_batched,
           "C5": bench_serving}[args.workload]
     out = fn(args, torch, T, W)
     print(json.dumps(out), flush=True)

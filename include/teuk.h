@@ -261,7 +261,9 @@ teuk_status teuk_step(teuk_solver* h, int64_t nsteps);
  * the sample count.  The graph is recaptured only when the sampling phase
  * (steps % extract_every) at the start of a replay run differs from the one
  * it was captured at, so stepping in multiples of chunk_steps captures once.
- * The captured work is kernel launches only (no memset or copy nodes).
+ * The captured work is kernel launches only (no memset or copy nodes).  A
+ * solver that has initial data captures its graph in this call, at its current
+ * sampling phase (otherwise at its first teuk_step of at least chunk_steps).
  * chunk_steps = 0 turns graph mode off (the default); at most 4096.
  * Errors: INVALID_ARG (NULL, chunk out of range, chunk not a multiple of
  * extract_every, odd chunk with TEUK_RK_SSP33_BLOCKED), UNSUPPORTED
@@ -323,8 +325,8 @@ teuk_status teuk_host_coefficients(const teuk_config* cfg, double* out, size_t c
  * GPU holds at once.  teuk_tune times the stage kernels of cfg for a set of
  * budgets from 1/4 to 4 times that default (one per distinct segs), each the
  * best of three runs of `steps` steps (0: chosen to take about 2 ms) on a
- * scratch solver of the same grid, chart, precisions and integrator with zero
- * data, and remembers the fastest budget for that launch class (device, chart,
+ * scratch solver of the same grid, chart, precisions and integrator with a
+ * smooth synthetic state of order one, and remembers the fastest budget for that launch class (device, chart,
  * weight and state precision, integrator, scheme, nr, ntheta) for the rest of
  * the process: a later teuk_create of that class with workgroups = 0 uses it
  * (teuk_info reports the workgroups in use).  The tiling does not change any
@@ -447,10 +449,11 @@ teuk_status teuk_group_step(teuk_group* g, int64_t nsteps);
  * chunk_steps steps (its stage launches and its members' samples), then the
  * remainder launch by launch.  Each block keeps its own graph, so a block still
  * runs all of a call's steps before the next block starts.  Adding or removing
- * a member drops the graphs; they are recaptured on the next step.  Every
+ * a member drops the graphs; they are recaptured on the next step.  This
+ * call captures every block's graph at once.  Every
  * member's extract_every must divide chunk_steps (else teuk_group_step returns
  * INVALID_ARG).  chunk_steps = 0 turns it off; at most 4096.
- * Errors: INVALID_ARG. */
+ * Errors: INVALID_ARG, DEVICE (capture). */
 teuk_status teuk_group_set_graph(teuk_group* g, int32_t chunk_steps);
 
 /* Tune the group's tile height and cache-block size on its current members.

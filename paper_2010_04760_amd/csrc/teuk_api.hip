@@ -818,6 +818,9 @@ teuk_status teuk_set_graph(teuk_solver* h, int32_t chunk_steps)
     }
     drop_graph(h);
     h->graph_chunk = chunk_steps;
+    // capture now, at the current sampling phase, so that the first replays
+    // do not pay for it
+    if (chunk_steps > 0 && h->have_init) return capture_chunk(h);
     return TEUK_OK;
 }
 
@@ -1289,6 +1292,11 @@ teuk_status teuk_group_set_graph(teuk_group* g, int32_t chunk_steps)
         return gfail(g, TEUK_ERR_INVALID_ARG, "chunk_steps must be in [0, " + std::to_string(kMaxGraphChunk) + "]");
     drop_group_graphs(g);
     g->graph_chunk = chunk_steps;
+    // capture every block now, at its members' current sampling phases
+    for (size_t bi = 0; chunk_steps > 0 && bi < g->blocks.size(); ++bi) {
+        teuk_status st = capture_block(g, bi);
+        if (st != TEUK_OK) return st;
+    }
     return TEUK_OK;
 }
 

@@ -5,14 +5,15 @@
 // step: strips of 114 points).  teuk_create derives segs from a workgroup
 // budget, by default the number of stage workgroups the GPU holds at once.
 // teuk_tune times the stage kernels of one configuration over a set of budgets
-// around that default, on a scratch solver of the same grid (zero data, no
-// waveform ring), and remembers the fastest budget per device and launch
+// around that default, on a scratch solver of the same grid (no
+// waveform ring, a smooth synthetic state), and remembers the fastest budget per device and launch
 // class; later solvers of that class created with workgroups = 0 use it.  Only
 // the tiling changes between candidates: every point runs the same arithmetic,
 // so the results do not depend on the choice.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -151,8 +152,15 @@ teuk_status teuk_tune(const teuk_config* cfg, int32_t steps, teuk_tune_info_t* o
     hipStream_t stream = nullptr;
     e = (int)hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
     if (e) return tfail(TEUK_ERR_DEVICE, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString((hipError_t)e));
-    const size_t vals = 4 * (size_t)cfg->nr * (size_t)cfg->ntheta;
-    std::vector<double> zeros(vals, 0.0);
+    // a smooth state of order one (not zeros: the FP64 units draw less power
+    // on zero data and the clock, which bounds these kernels, runs higher)
+    const size_t plane = (size_t)cfg->nr * (size_t)cfg->ntheta;
+    std::vector<double> zeros(4 * plane);
+    for (size_t p = 0; p < 4; ++p)
+        for (int k = 0; k < cfg->ntheta; ++k)
+            for (int j = 0; j < cfg->nr; ++j)
+                zeros[p * plane + (size_t)k * cfg->nr + j] =
+                    std::sin(0.37 * j + 0.11 * k + (double)p) * std::cos(0.013 * j - 0.7 * (double)p);
     teuk_config base = *cfg;
     teuk_status st = TEUK_OK;
     int n = steps;

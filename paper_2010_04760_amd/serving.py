@@ -129,10 +129,13 @@ class Server:
     max_members: most solves resident at once; hbm_budget: bytes of solver
     footprint allowed at once (default: 90 % of the free HBM when run starts);
     chunk_steps: steps between admission checks (a chunk ends early when a
-    resident request finishes)."""
+    resident request finishes); graph_chunk: steps per captured HIP graph of
+    the group (0: one launch per stage; it must be a multiple of every
+    request's waveform cadence)."""
 
     def __init__(self, max_members: int = 256, hbm_budget: Optional[int] = None, chunk_steps: int = 250,
-                 workgroups: int = 0, rows_per_tile: int = 0, keep_state: bool = False):
+                 workgroups: int = 0, rows_per_tile: int = 0, keep_state: bool = False, graph_chunk: int = 0):
+        self.graph_chunk = int(graph_chunk)
         self.max_members = max_members
         self.hbm_budget = hbm_budget
         self.chunk_steps = max(1, int(chunk_steps))
@@ -154,6 +157,8 @@ class Server:
         used = 0
         group = T.Group(self.max_members, workgroups=self.workgroups, rows_per_tile=self.rows_per_tile,
                         stream=stream)
+        if self.graph_chunk:
+            group.set_graph(self.graph_chunk)
         t0 = time.perf_counter()
         try:
             while pending or waiting or resident:

@@ -156,12 +156,18 @@ def test_graph_errors():
         with pytest.raises(T.TeukError) as ei:
             sv.set_graph(4)
         assert ei.value.status == T.TEUK_ERR_UNSUPPORTED
-    # a group member whose cadence does not divide the chunk is refused at step time
+    # a group member whose cadence does not divide the chunk is refused: at
+    # set_graph when it is already a member, at step time when it joins later
     g = T.Group(2)
     sv = T.Solver(_cfg(wl, extract_every=3, max_samples=4, x_extract=10.0))
     sv.set_initial(W.gaussian_pulse(wl))
     g.add(sv)
+    with pytest.raises(T.TeukError) as ei:
+        g.set_graph(8)
+    assert ei.value.status == T.TEUK_ERR_INVALID_ARG
+    g.remove(sv)
     g.set_graph(8)
+    g.add(sv)
     with pytest.raises(T.TeukError) as ei:
         g.step(8)
     assert ei.value.status == T.TEUK_ERR_INVALID_ARG
