@@ -108,7 +108,7 @@ enum { TEUK_S_FP64 = 0, TEUK_S_DD = 1 };
  *     q = 1/25 u^n + 9/25 (u(4) + dt/6 F(u(4))) over u^n, and the last is
  *     u^{n+1} = q + 3/5 (u(9) + dt/6 F(u(9))).  FP64 state, single solves only
  *     (UNSUPPORTED with TEUK_S_DD or in a group). */
-enum { TEUK_RK_SSP33 = 0, TEUK_RK_SSP104 = 1, TEUK_RK_SSP33_BLOCKED = 2 };
+enum { TEUK_RK_SSP33 = 0, TEUK_RK_SSP104 = 1, TEUK_RK_SSP33_BLOCKED = 2, TEUK_RK_SSP33_PIPELINED = 3 };
 /* TEUK_RK_SSP33_BLOCKED: SSP-RK(3,3), each step one launch that computes all
  * three stages of a tile (temporal blocking): u(1) and u(2) stay in LDS and
  * HBM sees one read of u^n and one write of u^{n+1} per point.  Tiles are 114
@@ -117,6 +117,17 @@ enum { TEUK_RK_SSP33 = 0, TEUK_RK_SSP104 = 1, TEUK_RK_SSP33_BLOCKED = 2 };
  * row and three points beyond (workgroups, when > 0, sets the tile count).
  * The result is the same arithmetic as TEUK_RK_SSP33, point by point.
  * Tortoise chart, FP64 state, WENO5 with FP64 weights, single solves. */
+/* TEUK_RK_SSP33_PIPELINED: SSP-RK(3,3), the steps between two waveform samples
+ * (at most 1000) in one persistent cooperative launch.  Each workgroup takes
+ * the tiles of the three-launch step (63-point strips by theta segments) of
+ * stage after stage in order, and a tile's stage waits only until the nine
+ * tiles around it have finished the previous stage (per-tile counters with
+ * agent-scope release and acquire), instead of the whole grid waiting at each
+ * launch boundary.  Bitwise the result of TEUK_RK_SSP33.  A dependency wait
+ * that exceeds two seconds (it cannot under the cooperative launch's
+ * residency guarantee) is reported as DEVICE by the next teuk_extract of the
+ * state or teuk_check_finite, never as a hang.  Tortoise chart, FP64 state,
+ * WENO5, any FP64/FP32/FP16/BF16 weights, single solves, no graph mode. */
 
 /* Radial scheme (Sec. 3.1).  WENO5 is the hot path; the other two are the
  * paper's comparison schemes, run by a separate FP64 stage kernel (FP64 state

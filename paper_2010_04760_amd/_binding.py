@@ -49,8 +49,9 @@ TEUK_ERR_CAPACITY = -7
 TEUK_CHART_TORTOISE, TEUK_CHART_HYPERBOLOIDAL = 0, 1
 TEUK_W_FP64, TEUK_W_FP32, TEUK_W_FP16, TEUK_W_BF16, TEUK_W_DD = 0, 1, 2, 3, 4
 TEUK_S_FP64, TEUK_S_DD = 0, 1
-TEUK_RK_SSP33, TEUK_RK_SSP104, TEUK_RK_SSP33_BLOCKED = 0, 1, 2
-INTEGRATOR = {"rk3": TEUK_RK_SSP33, "rk104": TEUK_RK_SSP104, "rk3_blocked": TEUK_RK_SSP33_BLOCKED}
+TEUK_RK_SSP33, TEUK_RK_SSP104, TEUK_RK_SSP33_BLOCKED, TEUK_RK_SSP33_PIPELINED = 0, 1, 2, 3
+INTEGRATOR = {"rk3": TEUK_RK_SSP33, "rk104": TEUK_RK_SSP104, "rk3_blocked": TEUK_RK_SSP33_BLOCKED,
+              "rk3_pipelined": TEUK_RK_SSP33_PIPELINED}
 TEUK_SCHEME_WENO5, TEUK_SCHEME_WENO3, TEUK_SCHEME_FD6KO8 = 0, 1, 2
 SCHEME = {"weno5": TEUK_SCHEME_WENO5, "weno3": TEUK_SCHEME_WENO3, "fd6ko8": TEUK_SCHEME_FD6KO8}
 TEUK_X_STATE, TEUK_X_WAVEFORM, TEUK_X_TIMES, TEUK_X_COEFFS, TEUK_X_RHS, TEUK_X_HORIZON = 0, 1, 2, 3, 4, 5

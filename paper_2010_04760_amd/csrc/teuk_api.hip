@@ -39,6 +39,9 @@ struct teuk_solver {
     unsigned long long* cell = nullptr;             // dt-bound reduction cell
     int* flag = nullptr;                            // non-finite flag
     unsigned long long* scount = nullptr;           // samples recorded (FP64 state; device copy of `samples`)
+    int* perr = nullptr;                            // pipelined step: a dependency wait timed out
+    long long* pdone = nullptr;                     // pipelined step: stages completed per tile
+    int pgrid = 0;                                  // pipelined step: workgroups per launch
     double dx = 0, dth = 0, dt = 0, dt_bound = 0;
     int j_e = 0;
     int nstrips = 0;
@@ -59,6 +62,7 @@ struct teuk_solver {
 
 constexpr int kClasses = 8;   // (weight precision, chart) pairs
 constexpr int kMaxGraphChunk = 4096;   // steps per captured graph
+constexpr long long kPipeSpinTicks = 200000000;   // 2 s of the 100 MHz real-time counter
 
 // Group members are stepped in cache blocks: consecutive members of one
 // (weight precision, chart) class whose solver footprints sum to at most this
@@ -116,7 +120,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t u, rtab, ttab, ctab, dtab, wave, hwave, cells, total;
+    size_t u, rtab, ttab, ctab, dtab, wave, hwave, pipe, cells, total;
 };
 
 Layout layout_of(const teuk_config& c)
@@ -134,8 +138,11 @@ Layout layout_of(const teuk_config& c)
     const size_t ns = c.extract_every > 0 ? (size_t)c.max_samples : 0;
     L.wave = align_up(ns * (size_t)c.ntheta * 2 * pv * sizeof(double));
     L.hwave = H ? align_up(ns * (size_t)c.ntheta * 4 * sizeof(double)) : 0;
+    // pipelined step: one stage counter per tile (at most one tile per strip and row)
+    const size_t nstrips = ((size_t)c.nr + kStripPoints - 1) / kStripPoints;
+    L.pipe = c.integrator == TEUK_RK_SSP33_PIPELINED ? align_up(nstrips * (size_t)c.ntheta * sizeof(long long)) : 0;
     L.cells = kAlign;
-    L.total = 3 * L.u + L.rtab + L.ttab + L.ctab + L.dtab + L.wave + L.hwave + L.cells;
+    L.total = 3 * L.u + L.rtab + L.ttab + L.ctab + L.dtab + L.wave + L.hwave + L.pipe + L.cells;
     return L;
 }
 
@@ -188,7 +195,7 @@ bool validate(const teuk_config* c, std::string& err)
     if ((long long)c->nr * c->ntheta > (1LL << 34)) { err = "nr * ntheta too large"; return false; }
     if (c->weight_prec < TEUK_W_FP64 || c->weight_prec > TEUK_W_DD) { err = "weight_prec must be a TEUK_W_* value"; return false; }
     if (c->state_prec != TEUK_S_FP64 && c->state_prec != TEUK_S_DD) { err = "state_prec must be a TEUK_S_* value"; return false; }
-    if (c->integrator < TEUK_RK_SSP33 || c->integrator > TEUK_RK_SSP33_BLOCKED) { err = "integrator must be a TEUK_RK_* value"; return false; }
+    if (c->integrator < TEUK_RK_SSP33 || c->integrator > TEUK_RK_SSP33_PIPELINED) { err = "integrator must be a TEUK_RK_* value"; return false; }
     if (c->scheme < TEUK_SCHEME_WENO5 || c->scheme > TEUK_SCHEME_FD6KO8) { err = "scheme must be a TEUK_SCHEME_* value"; return false; }
     if (c->reserved != 0) { err = "reserved must be 0"; return false; }
     if (!(c->ko_sigma >= 0.0) || !(c->ko_sigma <= 1.0)) { err = "ko_sigma must lie in [0, 1]"; return false; }
@@ -276,6 +283,12 @@ teuk_status run_guard(teuk_solver* h)
     if (e) return hip_fail(h, e, "hipMemcpyAsync(flag)");
     e = (int)hipStreamSynchronize(h->stream);
     if (e) return hip_fail(h, e, "hipStreamSynchronize");
+    if (h->pdone) {
+        int pe = 0;
+        e = (int)hipMemcpy(&pe, h->perr, sizeof(int), hipMemcpyDeviceToHost);
+        if (e) return hip_fail(h, e, "hipMemcpy(pipeline flag)");
+        if (pe) return fail(h, TEUK_ERR_DEVICE, "pipelined step: a wait for neighbouring tiles timed out");
+    }
     if (f) return fail(h, TEUK_ERR_NONFINITE, "non-finite value (NaN or Inf) in the state");
     return TEUK_OK;
 }
@@ -359,6 +372,9 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
         (chartH || dd || cfg->scheme != TEUK_SCHEME_WENO5 || cfg->weight_prec != TEUK_W_FP64))
         return fail(nullptr, TEUK_ERR_UNSUPPORTED,
                     "temporal blocking: tortoise chart, FP64 state, WENO5 with FP64 weights only");
+    if (cfg->integrator == TEUK_RK_SSP33_PIPELINED &&
+        (chartH || dd || cfg->scheme != TEUK_SCHEME_WENO5 || cfg->weight_prec == TEUK_W_DD))
+        return fail(nullptr, TEUK_ERR_UNSUPPORTED, "pipelined steps: tortoise chart, FP64 state, WENO5 only");
     std::vector<double> rtab, ttab, ctab, dtab;
     DDScalars ddk{};
     if (chartH ? !build_tables_H(*cfg, ctab, err) : !build_tables(*cfg, rtab, ttab, err))
@@ -406,10 +422,12 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     h->ddk = ddk;
     h->wave = (double*)p; p += L.wave;
     h->hwave = L.hwave ? (double*)p : nullptr; p += L.hwave;
+    h->pdone = L.pipe ? (long long*)p : nullptr; p += L.pipe;
     if (chartH) (void)horizon_stencil(*cfg, &h->j_h, h->hw, h->hdw);
     h->cell = (unsigned long long*)p;
     h->flag = (int*)(p + 64);
     h->scount = (unsigned long long*)(p + 128);
+    h->perr = (int*)(p + 192);
 
     h->plane = (long long)cfg->nr * cfg->ntheta;
     h->vals = 4 * h->plane * (dd ? 2 : 1);
@@ -427,6 +445,16 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
         (long long)h->nstrips * h->segs[1] > (1LL << 31) - 1) {
         free_solver(h);
         return fail(nullptr, TEUK_ERR_UNSUPPORTED, "weight precision not built (or occupancy query failed)");
+    }
+    if (cfg->integrator == TEUK_RK_SSP33_PIPELINED) {
+        // every stage runs the later-stage tiling; all workgroups resident at once
+        const long long tiles = (long long)h->nstrips * h->segs[1];
+        const long long cap = pipe_grid(cfg->weight_prec);
+        h->pgrid = (int)(cap < tiles ? cap : tiles);
+        if (cap <= 0 || tiles > (1LL << 31) - 1) {
+            free_solver(h);
+            return fail(nullptr, TEUK_ERR_UNSUPPORTED, "pipelined steps: occupancy query failed");
+        }
     }
     if (cfg->integrator == TEUK_RK_SSP33_BLOCKED) {
         h->bstrips = (cfg->nr + kBlockedPoints - 1) / kBlockedPoints;
@@ -453,6 +481,7 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     if (!e && dd)
         e = (int)hipMemcpyAsync(h->dtab, dtab.data(), dtab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
     if (!e) e = (int)hipMemsetAsync(h->cell, 0, sizeof(unsigned long long), h->stream);
+    if (!e) e = (int)hipMemsetAsync(h->perr, 0, sizeof(int), h->stream);
     if (!e) e = launch_dt_bound(h->rtab, h->ttab, h->ctab, cfg->nr, cfg->ntheta, h->dx, h->dth, h->cell, h->stream);
     unsigned long long bits = 0;
     if (!e) e = (int)hipMemcpyAsync(&bits, h->cell, sizeof(bits), hipMemcpyDeviceToHost, h->stream);
@@ -512,6 +541,10 @@ teuk_status teuk_set_initial(teuk_solver* h, const double* u, int32_t on_device)
     }
     h->steps = 0;
     h->samples = 0;
+    if (h->pdone) {
+        e = (int)hipMemsetAsync(h->pdone, 0, (size_t)h->nstrips * h->segs[1] * sizeof(long long), h->stream);
+        if (e) return hip_fail(h, e, "hipMemsetAsync(stage counters)");
+    }
     if (!h->dd && h->cfg.extract_every > 0) {
         static const unsigned long long kZero = 0;
         e = (int)hipMemcpyAsync(h->scount, &kZero, sizeof(kZero), hipMemcpyHostToDevice, h->stream);
@@ -594,6 +627,7 @@ static StageArgs stage_args(const teuk_solver* h)
     a.ko_sigma = c.ko_sigma;
     a.eps = c.weno_eps;
     a.parity = ((c.m + c.s) % 2 != 0) ? -1.0 : 1.0;
+    a.flip = 0;
     a.uk = a.un = h->u[0];
     a.out = h->u[1];
     return a;
@@ -705,6 +739,32 @@ static teuk_status step_eager(teuk_solver* h, int64_t nsteps)
         }
         return TEUK_OK;
     }
+    if (c.integrator == TEUK_RK_SSP33_PIPELINED) {
+        StageArgs st[3];
+        a.segs = h->segs[1];
+        a.grid = h->pgrid;
+        st[0] = a; st[0].uk = h->u[0]; st[0].un = h->u[0]; st[0].out = h->u[1]; st[0].ca = 0.0; st[0].cb = 1.0;
+        st[1] = a; st[1].uk = h->u[1]; st[1].un = h->u[0]; st[1].out = h->u[2]; st[1].ca = 0.75; st[1].cb = 0.25;
+        st[2] = a; st[2].uk = h->u[2]; st[2].un = h->u[0]; st[2].out = h->u[0]; st[2].ca = 1.0 / 3.0; st[2].cb = 2.0 / 3.0;
+        for (int64_t left = nsteps; left > 0;) {
+            // up to the next waveform sample, at most 1000 steps per launch
+            int64_t k = left < 1000 ? left : 1000;
+            if (c.extract_every > 0) {
+                const int64_t to_sample = c.extract_every - h->steps % c.extract_every;
+                if (k > to_sample) k = to_sample;
+            }
+            const int e = launch_pipe(st, h->pdone, h->perr, 3 * h->steps, (int)k, h->pgrid, kPipeSpinTicks,
+                                      c.weight_prec, h->stream);
+            if (e) return hip_fail(h, e, "pipelined launch");
+            h->steps += k;
+            left -= k;
+            if (c.extract_every > 0 && h->steps % c.extract_every == 0) {
+                teuk_status st2 = record_sample(h);
+                if (st2 != TEUK_OK) return st2;
+            }
+        }
+        return TEUK_OK;
+    }
     if (c.integrator == TEUK_RK_SSP104) {
         for (int64_t n = 0; n < nsteps; ++n) {
             const int e = rk104_step(h, a);
@@ -718,15 +778,22 @@ static teuk_status step_eager(teuk_solver* h, int64_t nsteps)
         return TEUK_OK;
     }
     for (int64_t n = 0; n < nsteps; ++n) {
+        // Consecutive launches march their theta segments in opposite
+        // directions (flip alternates with the launch count 3 steps + stage),
+        // so that a stage starts on the rows the previous one wrote last,
+        // which are still in the XCD's L2.  The arithmetic of every point is
+        // the same either way.
+        const int flip = (int)(h->steps & 1);
         // u1 = u + dt F(u)
         a.uk = h->u[0]; a.un = h->u[0]; a.out = h->u[1]; a.ca = 0.0; a.cb = 1.0; a.segs = h->segs[0]; a.grid = h->nstrips * h->segs[0];
+        a.flip = flip;
         int e = run_stage(h, a, 1);
         // u2 = 3/4 u + 1/4 (u1 + dt F(u1))
         if (!e) { a.uk = h->u[1]; a.un = h->u[0]; a.out = h->u[2]; a.ca = 0.75; a.cb = 0.25; a.segs = h->segs[1]; a.grid = h->nstrips * h->segs[1];
-                  e = run_stage(h, a, 2); }
+                  a.flip = flip ^ 1; e = run_stage(h, a, 2); }
         // u = 1/3 u + 2/3 (u2 + dt F(u2)), in place (u^n is read only at the own point)
         if (!e) { a.uk = h->u[2]; a.un = h->u[0]; a.out = h->u[0]; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0; a.segs = h->segs[1]; a.grid = h->nstrips * h->segs[1];
-                  e = run_stage(h, a, 3); }
+                  a.flip = flip; e = run_stage(h, a, 3); }
         if (e) return hip_fail(h, e, "stage launch");
         ++h->steps;
         if (c.extract_every > 0 && h->steps % c.extract_every == 0) {
@@ -811,6 +878,8 @@ teuk_status teuk_set_graph(teuk_solver* h, int32_t chunk_steps)
         return fail(h, TEUK_ERR_INVALID_ARG, "chunk_steps must be in [0, " + std::to_string(kMaxGraphChunk) + "]");
     if (chunk_steps > 0) {
         if (h->dd) return fail(h, TEUK_ERR_UNSUPPORTED, "graph mode: FP64 state only");
+        if (h->cfg.integrator == TEUK_RK_SSP33_PIPELINED)
+            return fail(h, TEUK_ERR_UNSUPPORTED, "graph mode: the pipelined step is one cooperative launch already");
         if (h->cfg.extract_every > 0 && chunk_steps % h->cfg.extract_every != 0)
             return fail(h, TEUK_ERR_INVALID_ARG, "chunk_steps must be a multiple of extract_every");
         if (h->cfg.integrator == TEUK_RK_SSP33_BLOCKED && chunk_steps % 2 != 0)
@@ -917,7 +986,9 @@ teuk_status teuk_info(teuk_solver* h, teuk_info_t* info)
     info->steps = h->steps;
     info->samples = h->samples;
     info->j_extract = h->j_e;
-    info->workgroups = h->cfg.integrator == TEUK_RK_SSP33_BLOCKED ? h->bstrips * h->bsegs : h->nstrips * h->segs[1];
+    info->workgroups = h->cfg.integrator == TEUK_RK_SSP33_BLOCKED     ? h->bstrips * h->bsegs
+                       : h->cfg.integrator == TEUK_RK_SSP33_PIPELINED ? h->pgrid
+                                                                      : h->nstrips * h->segs[1];
     info->dt_bound = h->dt_bound;
     return TEUK_OK;
 }
@@ -1594,12 +1665,13 @@ extern "C" teuk_status teuk_step_noalloc(const teuk_config* cfg, double* u, int6
     a.eps = cfg->weno_eps;
     a.parity = ((cfg->m + cfg->s) % 2 != 0) ? -1.0 : 1.0;
     for (int64_t n = 0; n < nsteps && !e; ++n) {
-        a.uk = u; a.un = u; a.out = u1; a.ca = 0.0; a.cb = 1.0; a.segs = segs1; a.grid = nstrips * segs1;
+        // consecutive launches march their segments in opposite directions (see teuk_step)
+        a.uk = u; a.un = u; a.out = u1; a.ca = 0.0; a.cb = 1.0; a.segs = segs1; a.grid = nstrips * segs1; a.flip = (int)(n & 1);
         e = launch_stage(a, 1, cfg->weight_prec, cfg->chart, st);
         if (!e) { a.uk = u1; a.un = u; a.out = u2; a.ca = 0.75; a.cb = 0.25; a.segs = segs23; a.grid = nstrips * segs23;
-                  e = launch_stage(a, 2, cfg->weight_prec, cfg->chart, st); }
+                  a.flip ^= 1; e = launch_stage(a, 2, cfg->weight_prec, cfg->chart, st); }
         if (!e) { a.uk = u2; a.un = u; a.out = u; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0;
-                  e = launch_stage(a, 3, cfg->weight_prec, cfg->chart, st); }
+                  a.flip ^= 1; e = launch_stage(a, 3, cfg->weight_prec, cfg->chart, st); }
     }
     if (e) return fail(nullptr, TEUK_ERR_DEVICE, std::string("stage launch: ") + hipGetErrorString((hipError_t)e));
     return TEUK_OK;

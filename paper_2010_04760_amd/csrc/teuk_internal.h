@@ -46,6 +46,7 @@ struct StageArgs {
     double inv_dx;         // 1 / dx (comparison schemes)
     double ko_sigma;       // Kreiss-Oliger sigma (TEUK_SCHEME_FD6KO8)
     double eps, parity;    // WENO epsilon, (-1)^(m+s)
+    int flip;              // 1: odd theta segments march upward and even ones downward
 };
 
 // Arguments of one stage of the double-double state path (tortoise chart).
@@ -94,6 +95,16 @@ int launch_coef_dump(const double* rtab, const double* ttab, const double* ctab,
 constexpr int kBlockedPoints = 114;
 int blocked_grid();
 int launch_blocked_step(const StageArgs& a, int weight_prec, void* stream);
+// Pipelined steps (tortoise chart, FP64 state, WENO5): nsteps SSP-RK(3,3)
+// steps in one cooperative launch of `grid` workgroups (at most pipe_grid(),
+// the resident count, and at most the tile count st[0].nstrips * st[0].segs);
+// st[0..2] are the three stages' arguments (equal tiling), done[] the per-tile
+// stage counters (absolute since the state was set, s0 of them done before
+// this launch), *err is set if a dependency wait exceeds spin_ticks of the
+// 100 MHz real-time counter.
+int pipe_grid(int weight_prec);
+int launch_pipe(const StageArgs st[3], long long* done, int* err, long long s0, int nsteps, int grid,
+                long long spin_ticks, int weight_prec, void* stream);
 // Comparison schemes (TEUK_SCHEME_WENO3 / TEUK_SCHEME_FD6KO8, FP64): one stage,
 // same stage codes as launch_stage.
 int launch_cmp_stage(const StageArgs& a, int stage, int scheme, int chart, void* stream);

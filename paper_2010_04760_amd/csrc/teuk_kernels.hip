@@ -317,6 +317,52 @@ __device__ __forceinline__ void vm_wait(double& a, double& b, double& c, double&
     asm volatile("s_waitcnt vmcnt(%4) ; async-wait %0 %1 %2 %3" : "+v"(a), "+v"(b), "+v"(c), "+v"(d) : "n"(N) : "memory");
 }
 
+// Agent-coherent forms of the row traffic (the sc1 cache policy that the
+// compiler gives agent-scope atomics: not served from a non-coherent cache
+// line, and stores written through), for the pipelined step, whose workgroups
+// on any CU or XCD exchange tiles without cache write-back or invalidation.
+// With kCoh false they are the plain forms above.
+template <bool kCoh>
+__device__ __forceinline__ double ldb_c(const double* base, unsigned off)
+{
+    if constexpr (kCoh) {
+        const unsigned long long* q =
+            reinterpret_cast<const unsigned long long*>(reinterpret_cast<const char*>(base) + off);
+        return __longlong_as_double((long long)__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    } else {
+        return ldb(base, off);
+    }
+}
+template <bool kCoh>
+__device__ __forceinline__ void stb_c(double* base, unsigned off, double v)
+{
+    if constexpr (kCoh) {
+        unsigned long long* q = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(base) + off);
+        __hip_atomic_store(q, (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        stb(base, off, v);
+    }
+}
+template <bool kCoh>
+__device__ __forceinline__ void dma_dword_c(unsigned voff, const double* sbase, unsigned lds)
+{
+    if constexpr (kCoh)
+        asm volatile("global_load_lds_dword %0, %1 sc1" : : "v"(voff), "s"(sbase), "{m0}"(lds) : "memory");
+    else
+        dma_dword(voff, sbase, lds);
+}
+template <bool kCoh>
+__device__ __forceinline__ double ld_async_c(unsigned voff, const double* sbase)
+{
+    if constexpr (kCoh) {
+        double v;
+        asm volatile("global_load_dwordx2 %0, %1, %2 sc1 ; async-load" : "=&v"(v) : "v"(voff), "s"(sbase) : "memory");
+        return v;
+    } else {
+        return ld_async(voff, sbase);
+    }
+}
+
 // One radial strip [j0, j0 + 63) marched over the theta rows [k0, k1), upward
 // (dir = +1, from k0) or downward (dir = -1, from k1 - 1).  Rows are staged in
 // a two-row LDS ring: while row k is computed from LDS, the loads of row
@@ -562,7 +608,7 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
 //         i.e. vmcnt <= (12 + it) at i = 0 and vmcnt <= 2 it for i >= 1,
 //         it = loads per iteration (16 later stages, 12 otherwise);
 //     before the stores: u^n of row i has landed, vmcnt <= 12.
-template <int WP, int kMode, bool kLevel>
+template <int WP, int kMode, bool kLevel, bool kCoh = false>
 __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, int strip, int k0, int k1, int dir)
 {
     const int l = threadIdx.x;
@@ -597,11 +643,11 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
     {
         const int kb = first - dir;
         if (kb >= 0 && kb < nth) {
-            bhR = ldb(ukp[0] + (size_t)kb * nr, oc);
-            bhI = ldb(ukp[1] + (size_t)kb * nr, oc);
+            bhR = ldb_c<kCoh>(ukp[0] + (size_t)kb * nr, oc);
+            bhI = ldb_c<kCoh>(ukp[1] + (size_t)kb * nr, oc);
         } else {
-            bhR = A.parity * ldb(ukp[0] + (size_t)first * nr, oc);
-            bhI = A.parity * ldb(ukp[1] + (size_t)first * nr, oc);
+            bhR = A.parity * ldb_c<kCoh>(ukp[0] + (size_t)first * nr, oc);
+            bhI = A.parity * ldb_c<kCoh>(ukp[1] + (size_t)first * nr, oc);
         }
     }
     const int ahead_last = first + dir * n;
@@ -618,9 +664,9 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const double* base = ukp[p] + row;
-            dma_dword(o0, base, slot + p * kPlaneBytes);
-            dma_dword(o1, base, slot + p * kPlaneBytes + 256u);
-            if (l < 10) dma_dword(o2, base, slot + p * kPlaneBytes + 512u);
+            dma_dword_c<kCoh>(o0, base, slot + p * kPlaneBytes);
+            dma_dword_c<kCoh>(o1, base, slot + p * kPlaneBytes + 256u);
+            if (l < 10) dma_dword_c<kCoh>(o2, base, slot + p * kPlaneBytes + 512u);
         }
     };
     issue_row(0);
@@ -651,10 +697,10 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
         const double th = tt[kTh * nth + k];
         double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
         if (reads_un<kMode>()) {
-            n0 = ld_async(oc, unp[0] + row);
-            n1 = ld_async(oc, unp[1] + row);
-            n2 = ld_async(oc, unp[2] + row);
-            n3 = ld_async(oc, unp[3] + row);
+            n0 = ld_async_c<kCoh>(oc, unp[0] + row);
+            n1 = ld_async_c<kCoh>(oc, unp[1] + row);
+            n2 = ld_async_c<kCoh>(oc, unp[2] + row);
+            n3 = ld_async_c<kCoh>(oc, unp[3] + row);
         }
         issue_row(i + 3);
         constexpr int it = reads_un<kMode>() ? 16 : 12;
@@ -700,31 +746,31 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
             const double FpiI = c.b * dPiI - (c.m3r * dPhI + c.m3i * dPhR) + (c.btr * piI + c.bti * piR) +
                                 c.ath * d2I + c.bth * d1I + (c.cr * phI + c.ci * phR);
             if (kMode == kRhsOnly) {
-                stb(outp[0] + row, oc, FphR);
-                stb(outp[1] + row, oc, FphI);
-                stb(outp[2] + row, oc, FpiR);
-                stb(outp[3] + row, oc, FpiI);
+                stb_c<kCoh>(outp[0] + row, oc, FphR);
+                stb_c<kCoh>(outp[1] + row, oc, FphI);
+                stb_c<kCoh>(outp[2] + row, oc, FpiR);
+                stb_c<kCoh>(outp[3] + row, oc, FpiI);
             } else if (kMode == kStageFirst) {
-                stb(outp[0] + row, oc, phR + A.dt * FphR);
-                stb(outp[1] + row, oc, phI + A.dt * FphI);
-                stb(outp[2] + row, oc, piR + A.dt * FpiR);
-                stb(outp[3] + row, oc, piI + A.dt * FpiI);
+                stb_c<kCoh>(outp[0] + row, oc, phR + A.dt * FphR);
+                stb_c<kCoh>(outp[1] + row, oc, phI + A.dt * FphI);
+                stb_c<kCoh>(outp[2] + row, oc, piR + A.dt * FpiR);
+                stb_c<kCoh>(outp[3] + row, oc, piI + A.dt * FpiI);
             } else if (kMode == kStageLater) {
-                stb(outp[0] + row, oc, A.ca * n0 + A.cb * (phR + A.dt * FphR));
-                stb(outp[1] + row, oc, A.ca * n1 + A.cb * (phI + A.dt * FphI));
-                stb(outp[2] + row, oc, A.ca * n2 + A.cb * (piR + A.dt * FpiR));
-                stb(outp[3] + row, oc, A.ca * n3 + A.cb * (piI + A.dt * FpiI));
+                stb_c<kCoh>(outp[0] + row, oc, A.ca * n0 + A.cb * (phR + A.dt * FphR));
+                stb_c<kCoh>(outp[1] + row, oc, A.ca * n1 + A.cb * (phI + A.dt * FphI));
+                stb_c<kCoh>(outp[2] + row, oc, A.ca * n2 + A.cb * (piR + A.dt * FpiR));
+                stb_c<kCoh>(outp[3] + row, oc, A.ca * n3 + A.cb * (piI + A.dt * FpiI));
             } else {
                 const double v0 = phR + A.dt * FphR, v1 = phI + A.dt * FphI;
                 const double v2 = piR + A.dt * FpiR, v3 = piI + A.dt * FpiI;
-                stb(outp[0] + row, oc, A.ca * n0 + A.cb * v0);
-                stb(outp[1] + row, oc, A.ca * n1 + A.cb * v1);
-                stb(outp[2] + row, oc, A.ca * n2 + A.cb * v2);
-                stb(outp[3] + row, oc, A.ca * n3 + A.cb * v3);
-                stb(A.out2 + row, oc, A.ca2 * n0 + A.cb2 * v0);
-                stb(A.out2 + P + row, oc, A.ca2 * n1 + A.cb2 * v1);
-                stb(A.out2 + 2 * P + row, oc, A.ca2 * n2 + A.cb2 * v2);
-                stb(A.out2 + 3 * P + row, oc, A.ca2 * n3 + A.cb2 * v3);
+                stb_c<kCoh>(outp[0] + row, oc, A.ca * n0 + A.cb * v0);
+                stb_c<kCoh>(outp[1] + row, oc, A.ca * n1 + A.cb * v1);
+                stb_c<kCoh>(outp[2] + row, oc, A.ca * n2 + A.cb * v2);
+                stb_c<kCoh>(outp[3] + row, oc, A.ca * n3 + A.cb * v3);
+                stb_c<kCoh>(A.out2 + row, oc, A.ca2 * n0 + A.cb2 * v0);
+                stb_c<kCoh>(A.out2 + P + row, oc, A.ca2 * n1 + A.cb2 * v1);
+                stb_c<kCoh>(A.out2 + 2 * P + row, oc, A.ca2 * n2 + A.cb2 * v2);
+                stb_c<kCoh>(A.out2 + 3 * P + row, oc, A.ca2 * n3 + A.cb2 * v3);
             }
         }
         bhR = phR;
@@ -745,11 +791,11 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
 // staging ring (chart H).
 constexpr unsigned kLdsBytes = kRing * kSlotBytes;   // 9216 >= 2 * 4 * kRow * 8
 
-template <int WP, int kMode, int kChart, bool kLevel = false>
+template <int WP, int kMode, int kChart, bool kLevel = false, bool kCoh = false>
 __device__ __forceinline__ void march(const StageArgs& A, char* lds, int strip, int k0, int k1, int dir)
 {
     if constexpr (kChart == kChartT)
-        march_strip_t<WP, kMode, kLevel>(A, lds, strip, k0, k1, dir);
+        march_strip_t<WP, kMode, kLevel, kCoh>(A, lds, strip, k0, k1, dir);
     else
         march_strip<WP, kMode, kChart>(A, reinterpret_cast<double (*)[4][kRow]>(lds), strip, k0, k1, dir);
 }
@@ -761,7 +807,7 @@ __device__ __forceinline__ void run_tile(const StageArgs& A, char* lds, int rank
     const int seg = rank - strip * A.segs;
     const int k0 = (int)((long long)A.nth * seg / A.segs);
     const int k1 = (int)((long long)A.nth * (seg + 1) / A.segs);
-    if (k1 > k0) march<WP, kMode, kChart, true>(A, lds, strip, k0, k1, (seg & 1) ? -1 : 1);
+    if (k1 > k0) march<WP, kMode, kChart, true>(A, lds, strip, k0, k1, ((seg ^ A.flip) & 1) ? -1 : 1);
 }
 
 // Ranks are dealt so that each XCD (which receives every eighth workgroup id)
@@ -814,7 +860,102 @@ __global__ __launch_bounds__(kWave) void group_stage_kernel(const StageArgs* __r
         const int strip = local - seg * A.nstrips;
         const int k0 = (int)((long long)A.nth * seg / A.segs);
         const int k1 = (int)((long long)A.nth * (seg + 1) / A.segs);
-        if (k1 > k0) march<WP, kMode, kChart>(A, lds, strip, k0, k1, (seg & 1) ? -1 : 1);
+        if (k1 > k0) march<WP, kMode, kChart>(A, lds, strip, k0, k1, ((seg ^ A.flip) & 1) ? -1 : 1);
+    }
+}
+
+// ---------------------------------------------------------------- pipelined steps
+// Several SSP-RK(3,3) steps in one cooperative launch (tortoise chart).  The
+// work items are the tiles of every stage of every step -- tile (strip,
+// segment) of stage S, the tiles of the single-solve stage launch -- numbered
+// stage by stage, and workgroup w takes items w, w + G, w + 2G, ... in order.
+// A tile's stage S reads the stage S-1 results of its own tile and of the
+// tiles around it (the radial halo from the neighbouring strips, the theta row
+// across a segment boundary, and the corners of both), so it waits for those
+// nine tiles only, not for the whole grid: waves drift apart, and the memory
+// traffic of some overlaps the arithmetic of others across stage boundaries,
+// where stage-by-stage launches drain and refill the GPU three times a step.
+// Every other hazard (a stage overwriting values that a neighbour's earlier
+// stage still reads: u(1) by the next step's stage 1, u^n by stage 3 in place)
+// is ordered through these waits by induction, because a neighbour's stage
+// S-1 itself waited for the stage S-2 of its own neighbours.
+// Progress: the earliest unfinished item waits only on earlier items, which
+// have finished, and its workgroup has finished its own earlier items, so it is
+// working on that item; this needs every workgroup resident at once, which the
+// cooperative launch guarantees.
+// Counters: done[tile] = stages the tile has completed since the state was set
+// (absolute, so launches need no reset).  The tiles' rows are read and written
+// with agent-coherent accesses (the sc1 forms of the row loads, LDS-DMA loads
+// and stores), so no cache needs writing back or invalidating: a workgroup
+// waits for its stores to complete and then writes its tile's count; a reader
+// polls the neighbours' counts with agent-scope loads and issues its coherent
+// loads only after seeing them.
+// A wait longer than spin_ticks of the 100 MHz real-time counter sets *err and
+// goes on, so a fault of this scheme shows up as an error, never as a hang.
+struct PipeArgs {
+    StageArgs st[3];       // stage 1, 2, 3 arguments (segs, nstrips equal in all three)
+    long long* done;       // [nstrips * segs] stages completed per tile
+    int* err;              // set to 1 by a wait that timed out
+    long long s0;          // stages completed before this launch (3 x steps)
+    int nsteps;            // steps in this launch
+    int tiles;             // nstrips * segs
+    long long spin_ticks;  // wait limit
+};
+
+__device__ __forceinline__ void pipe_wait(const PipeArgs& P, int strip, int seg, long long need)
+{
+    const int l = threadIdx.x;
+    const int nstrips = P.st[0].nstrips, segs = P.st[0].segs;
+    const long long* c = nullptr;
+    if (l < 9) {
+        const int s2 = strip + l / 3 - 1, g2 = seg + l % 3 - 1;
+        if (s2 >= 0 && s2 < nstrips && g2 >= 0 && g2 < segs) c = P.done + (size_t)s2 * segs + g2;
+    }
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+        const bool ok = !c || __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+        if (__all(ok)) break;
+        // after one timed-out wait anywhere, no wait blocks any more
+        const int failed = __hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (failed) break;
+        if ((long long)(__builtin_amdgcn_s_memrealtime() - t0) > P.spin_ticks) {
+            if (l == 0) __hip_atomic_store(P.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    // the tile's loads are issued after the counts were seen (the loop exit
+    // depends on them) and are coherent loads, so they see the neighbours'
+    // completed stores; this keeps the compiler from hoisting them
+    asm volatile("" ::: "memory");
+}
+
+template <int WP>
+__global__ __launch_bounds__(kWave) void pipe_kernel(PipeArgs P)
+{
+    __shared__ __attribute__((aligned(16))) char lds[kLdsBytes];
+    const long long items = 3LL * P.nsteps * P.tiles;
+    const int segs = P.st[0].segs;
+    for (long long it = blockIdx.x; it < items; it += gridDim.x) {
+        const long long S = it / P.tiles;
+        const int r = (int)(it - S * P.tiles);
+        const int strip = r / segs, seg = r - strip * segs;
+        const long long need = P.s0 + S;
+        if (need > 0) pipe_wait(P, strip, seg, need);
+        const int stage = (int)(S % 3);
+        StageArgs A = P.st[stage];
+        A.flip = (int)(need & 1);
+        const int k0 = (int)((long long)A.nth * seg / segs);
+        const int k1 = (int)((long long)A.nth * (seg + 1) / segs);
+        const int dir = ((seg ^ A.flip) & 1) ? -1 : 1;
+        if (k1 > k0) {
+            if (stage == 0) march<WP, kStageFirst, kChartT, false, true>(A, lds, strip, k0, k1, dir);
+            else march<WP, kStageLater, kChartT, false, true>(A, lds, strip, k0, k1, dir);
+        }
+        // publish: every coherent store of the tile has completed before the count is written
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        if (threadIdx.x == 0)
+            __hip_atomic_store(P.done + r, need + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -1238,6 +1379,45 @@ int stage_grid(int weight_prec, bool first, int chart)
 #undef TEUK_OCC
     if (e != hipSuccess || per_cu < 1) return 0;
     return cus * per_cu;
+}
+
+int pipe_grid(int weight_prec)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (weight_prec == TEUK_W_FP64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pipe_kernel<TEUK_W_FP64>, kWave, 0);
+    if (weight_prec == TEUK_W_FP32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pipe_kernel<TEUK_W_FP32>, kWave, 0);
+    if (weight_prec == TEUK_W_FP16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pipe_kernel<TEUK_W_FP16>, kWave, 0);
+    if (weight_prec == TEUK_W_BF16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pipe_kernel<TEUK_W_BF16>, kWave, 0);
+    if (e != hipSuccess || per_cu < 1) return 0;
+    return cus * per_cu;
+}
+
+int launch_pipe(const StageArgs st[3], long long* done, int* err, long long s0, int nsteps, int grid,
+                long long spin_ticks, int weight_prec, void* stream)
+{
+    PipeArgs P;
+    for (int i = 0; i < 3; ++i) P.st[i] = st[i];
+    P.done = done;
+    P.err = err;
+    P.s0 = s0;
+    P.nsteps = nsteps;
+    P.tiles = st[0].nstrips * st[0].segs;
+    P.spin_ticks = spin_ticks;
+    if (grid < 1 || grid > P.tiles || nsteps < 1) return (int)hipErrorInvalidValue;
+    void* args[] = {&P};
+    const void* fn = nullptr;
+    if (weight_prec == TEUK_W_FP64) fn = (const void*)pipe_kernel<TEUK_W_FP64>;
+    if (weight_prec == TEUK_W_FP32) fn = (const void*)pipe_kernel<TEUK_W_FP32>;
+    if (weight_prec == TEUK_W_FP16) fn = (const void*)pipe_kernel<TEUK_W_FP16>;
+    if (weight_prec == TEUK_W_BF16) fn = (const void*)pipe_kernel<TEUK_W_BF16>;
+    if (!fn) return (int)hipErrorInvalidValue;
+    (void)hipGetLastError();
+    const hipError_t e = hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(kWave), args, 0, (hipStream_t)stream);
+    if (e != hipSuccess) return (int)e;
+    return (int)hipGetLastError();
 }
 
 int launch_stage(const StageArgs& a, int stage, int weight_prec, int chart, void* stream)

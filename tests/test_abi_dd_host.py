@@ -56,8 +56,10 @@ def test_dd_validation():
     assert T.teuk_footprint_bytes(T.make_config(**base, weight_prec="dd")) == 0
     assert T.teuk_footprint_bytes(T.make_config(**base, state=2)) == 0
     c = T.make_config(**base)
-    c.integrator = 3
+    c.integrator = 4                          # one past TEUK_RK_SSP33_PIPELINED
     assert T.teuk_footprint_bytes(c) == 0
+    c.integrator = 3                          # the pipelined step is valid; its footprint adds the tile counters
+    assert T.teuk_footprint_bytes(c) > T.teuk_footprint_bytes(T.make_config(**base))
     with pytest.raises(T.TeukError) as ei:
         T.teuk_create(T.make_config(**base, state="dd", weight_prec="dd", integrator="rk104"))
     assert ei.value.status == T.TEUK_ERR_UNSUPPORTED
