@@ -226,7 +226,7 @@ def bench_single(args, torch, T, W):
     # speed and waveform error (relative L2 over every sample) against FP64.
     mixed = None
     if weights == "fp64" and not args.no_mixed:
-        full = wl.steps
+        full = wl.steps if args.mixed_steps <= 0 else args.mixed_steps
         sec64f, _, _, wave64f = run("fp64", nsteps=full, nwarm=0)
         mixed = {"steps": full, "fp64": {"value": 3.0 * wl.points * full / sec64f, "seconds": sec64f}}
         for wp in ("fp32", "fp16", "bf16"):
@@ -264,6 +264,14 @@ def bench_single(args, torch, T, W):
         sec_o, _, _, wave_o = run(weights, graph=other)
         out["graph"] = {"chunk_steps": other, "ms_per_step": sec_o / steps * 1e3, "value": pu / sec_o,
                         "speedup_vs_headline": gpu_s / sec_o, "waveform_identical": bool(np.array_equal(wave_o, wave))}
+    if weights == "fp64" and not args.no_pipelined:
+        # the same steps in one cooperative launch per waveform interval (tiles
+        # wait for their neighbours' previous stage only)
+        secp, _, infop, wavep = run("fp64", integrator="rk3_pipelined")
+        out["pipelined"] = {"steps": steps, "ms_per_step": secp / steps * 1e3, "value": pu / secp,
+                            "speedup_vs_headline": gpu_s / secp, "workgroups": infop.workgroups,
+                            "waveform_identical": bool(np.array_equal(wavep, wave)),
+                            "launches": "one per waveform interval (every %d steps)" % wl.every}
     if c1:
         if not args.no_cpu_baseline:
             log("cpu baseline (oracle)")
@@ -700,8 +708,12 @@ def main():
     ap.add_argument("--no-graph-leg", action="store_true",
                     help="C1/C2/C4: skip the run in the other launch mode (graph vs launch by launch)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/FP16/BF16-weight runs")
+    ap.add_argument("--mixed-steps", type=int, default=0,
+                    help="C1/C2: steps of each weight-precision run (0: the workload's full length, which the "
+                         "waveform comparison needs; fewer for profiling)")
     ap.add_argument("--no-rk104", action="store_true", help="C2: skip the SSP-RK(10,4) run")
     ap.add_argument("--no-blocked", action="store_true", help="C2: skip the temporally blocked run")
+    ap.add_argument("--no-pipelined", action="store_true", help="C1/C2: skip the pipelined-step run")
     ap.add_argument("--quad-steps", type=int, default=1000,
                     help="C2: steps of the double-double state runs (0: skip them)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
