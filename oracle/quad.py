@@ -227,6 +227,7 @@ class TeukOracleQ:
         alone, its edges taken as grid ends (ghosts by the usual rules), so
         that values away from the block's edges equal the full grid's."""
         assert prob.chart == "T", "the binary128 oracle covers the tortoise chart"
+        assert prob.theta_order == 2, "the binary128 oracle takes second-order theta differences"
         assert weights in ("quad", "fp64")
         self.prob = prob
         self.weights = weights

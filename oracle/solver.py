@@ -55,7 +55,8 @@ class _OracleTeuk(ctypes.Structure):
                 ("dth", ctypes.c_double), ("dth_lo", ctypes.c_double), ("eps", ctypes.c_double),
                 ("parity", ctypes.c_double), ("wmode", ctypes.c_int), ("scheme", ctypes.c_int),
                 ("ko_sigma", ctypes.c_double)] + [
-                (n, ctypes.c_void_p) for n in ("lam1", "lam2", "m3r", "m3i", "btr", "bti", "cr", "ci", "ath", "bth")]
+                (n, ctypes.c_void_p) for n in ("lam1", "lam2", "m3r", "m3i", "btr", "bti", "cr", "ci", "ath", "bth")] + [
+                ("theta_order", ctypes.c_int)]
 
 
 RHS_FN = ctypes.CFUNCTYPE(None, _dp, _dp, ctypes.c_void_p)
@@ -241,6 +242,7 @@ class Problem:
     S: float = 20.0
     scheme: str = "weno5"        # radial scheme: "weno5", "weno3" or "fd6ko8" (Sec. 3.1)
     ko_sigma: float = 0.01       # Kreiss-Oliger sigma (fd6ko8)
+    theta_order: int = 2         # order of the centred theta differences: 2 or 4 (Sec. 3.1 leaves it open)
 
     @property
     def dx(self):
@@ -262,10 +264,28 @@ class Problem:
         return -1.0 if (self.m + self.s) % 2 else 1.0
 
 
+def theta_symbol_maxima(order):
+    """(max |dth^2 D2 symbol|, max |dth D1 symbol|) over the wavenumbers.
+
+    Second order: D2 -> (2 cos xi - 2), D1 -> i sin xi: (4, 1).  Fourth order:
+    D2 -> (32 cos xi - 2 cos 2xi - 30)/12, largest at xi = pi: 16/3; D1 ->
+    i (8 sin xi - sin 2xi)/6, whose derivative 8 cos xi - 2 cos 2xi vanishes
+    at cos xi = 1 - sqrt(3/2), where it equals sin xi (4 - cos xi)/3.
+    """
+    if order == 4:
+        c = 1.0 - np.sqrt(1.5)
+        return 16.0 / 3.0, float(np.sqrt(1.0 - c * c) * (4.0 - c) / 3.0)
+    return 4.0, 1.0
+
+
 class TeukOracle:
     """Chart-T oracle for one Problem: coefficient tables plus the C solver."""
 
     def __init__(self, prob: Problem):
+        if prob.theta_order not in (2, 4):
+            raise ValueError("theta_order must be 2 or 4")
+        if prob.nth < prob.theta_order // 2:
+            raise ValueError("fourth-order theta differences need nth >= 2")
         self.prob = prob
         x = prob.x()
         th = prob.theta()
@@ -292,19 +312,23 @@ class TeukOracle:
         self._s = _OracleTeuk(prob.nr, prob.nth, prob.dx, 0.0, prob.dth, 0.0, prob.eps, prob.parity(), 0,
                               SCHEMES[prob.scheme], prob.ko_sigma,
                               *[self.tab[n].ctypes.data for n in ("lam1", "lam2", "m3r", "m3i", "btr",
-                                                                  "bti", "cr", "ci", "ath", "bth")])
+                                                                  "bti", "cr", "ci", "ath", "bth")],
+                              prob.theta_order)
 
     # a8: stability bound (reading of the SSP framework of Sec. 3.2)
     def dt_bound(self, cfl=0.5):
-        """dt = cfl / max_points( max(|lam1|,|lam2|)/dx + sqrt(4 Ath/dth^2 + |Bth|/dth + |C|) ).
+        """dt = cfl / max_points( max(|lam1|,|lam2|)/dx + sqrt(c2 Ath/dth^2 + c1 |Bth|/dth + |C|) ).
 
         The square root bounds the frequency of the theta part (Gershgorin on
         the centred theta operator acting through the Phi-pi coupling); the
-        first term is the radial upwind speed over dx.
+        first term is the radial upwind speed over dx.  c2 and c1 are the
+        largest moduli of the Fourier symbols of dth^2 D2 and dth D1 (see
+        theta_symbol_maxima).
         """
         p, t = self.prob, self.tab
+        c2, c1 = theta_symbol_maxima(p.theta_order)
         lam = np.maximum(np.abs(t["lam1"]), np.abs(t["lam2"]))
-        om = np.sqrt(4.0 * t["ath"] / p.dth**2 + np.abs(t["bth"]) / p.dth + np.hypot(t["cr"], t["ci"]))
+        om = np.sqrt(c2 * t["ath"] / p.dth**2 + c1 * np.abs(t["bth"]) / p.dth + np.hypot(t["cr"], t["ci"]))
         return cfl / float(np.max(lam / p.dx + om))
 
     def rhs(self, u):

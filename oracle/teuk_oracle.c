@@ -21,12 +21,21 @@
  *   - each real plane of u = {Phi_R, Phi_I, pi_R, pi_I} differentiated by the
  *     WENO side that matches the sign of its wave speed (Sec. 3.1.2: positive
  *     speed -> f^+ treatment, negative -> f^-);
- *   - second-order centred differences in theta (Sec. 3.1);
+ *   - centred differences in theta (Sec. 3.1; the paper does not state their
+ *     order): second order by default,
+ *       D1 u = (u_{k+1} - u_{k-1}) / (2 dth),
+ *       D2 u = (u_{k+1} - 2 u_k + u_{k-1}) / dth^2,
+ *     or, with theta_order = 4, the fourth-order centred stencils
+ *       D1 u = (-u_{k+2} + 8 u_{k+1} - 8 u_{k-1} + u_{k-2}) / (12 dth),
+ *       D2 u = (-u_{k+2} + 16 u_{k+1} - 30 u_k + 16 u_{k-1} - u_{k-2}) / (12 dth^2);
  *   - the right-hand side of eq. evln, -(M d_x u + L u + A u), written with
  *     complex 2x2 blocks;
  *   - SSP-RK(3,3) in the Shu-Osher form of Sec. 3.2.
  * Ghost values: three cells per radial side copied from the end point, and in
- * theta one cell per pole equal to (-1)^(m+s) times the mirrored cell.
+ * theta (-1)^(m+s) times the cell mirrored across the pole: on the
+ * cell-centred grid theta_k = (k + 1/2) dth, row -1 - g mirrors row g and row
+ * nth + g mirrors row nth - 1 - g (one such row per pole at second order, two
+ * at fourth).
  *
  * Radial schemes (Sec. 3.1): WENO5 (scheme 0, above), the third-order WENO of
  * Sec. 3.1.2 (scheme 1: two candidate stencils, IS_1 = (f_j - f_{j-1})^2,
@@ -399,6 +408,7 @@ typedef struct {
     const real *btr, *bti;           /* B~t */
     const real *cr, *ci;             /* C~ */
     const real *ath, *bth;           /* A~thth, B~th */
+    int theta_order;                 /* 4: fourth-order theta differences; else second */
 } oracle_teuk;
 
 /* Copy row k of a plane into p[0 .. nr+7] with four end-point copies per side
@@ -413,11 +423,13 @@ static void pad_row(const real* plane, long nr, long k, real* p)
     memcpy(p + 4, row, (size_t)nr * sizeof(real));
 }
 
-/* theta neighbour of (k, j) in a plane, with the pole ghosts. */
+/* Row k (possibly a ghost row beyond a pole) of a plane at radial index j:
+ * rows -1, -2 mirror rows 0, 1 and rows nth, nth + 1 mirror rows nth - 1,
+ * nth - 2, each times the parity (-1)^(m+s). */
 static real theta_nb(const real* plane, long nr, long nth, long k, long j, real parity)
 {
-    if (k < 0) return parity * plane[0 * nr + j];
-    if (k >= nth) return parity * plane[(nth - 1) * nr + j];
+    if (k < 0) return parity * plane[(-1 - k) * nr + j];
+    if (k >= nth) return parity * plane[(2 * nth - 1 - k) * nr + j];
     return plane[k * nr + j];
 }
 
@@ -427,7 +439,9 @@ void FN(oracle_teuk_rhs)(const oracle_teuk* P, const real* u, real* F)
     const long nr = P->nr, nth = P->nth, N = nr * nth;
     const real *PhR = u, *PhI = u + N, *PiR = u + 2 * N, *PiI = u + 3 * N;
     const real dx = pair(P->dx, P->dx_lo), dth = pair(P->dth, P->dth_lo), par = R(P->parity);
+    const int th4 = P->theta_order == 4;
     const real ih1 = R(1) / (R(2) * dth), ih2 = R(1) / (dth * dth);
+    const real ih1_4 = R(1) / (R(12) * dth), ih2_4 = R(1) / (R(12) * dth * dth);
     const double eps = P->eps;
     const int wm = P->wmode, sc = P->scheme;
     const real sig = R(P->ko_sigma);
@@ -448,14 +462,28 @@ void FN(oracle_teuk_rhs)(const oracle_teuk* P, const real* u, real* F)
             const real dPhI = radial_d(pPhI, j, l1, dx, eps, wm, sc);
             const real dPiR = radial_d(pPiR, j, l2, dx, eps, wm, sc);
             const real dPiI = radial_d(pPiI, j, l2, dx, eps, wm, sc);
-            /* theta derivatives of Phi (second-order centred) */
+            /* theta derivatives of Phi (centred, second or fourth order) */
             const real phRm = theta_nb(PhR, nr, nth, k - 1, j, par);
             const real phRp = theta_nb(PhR, nr, nth, k + 1, j, par);
             const real phIm = theta_nb(PhI, nr, nth, k - 1, j, par);
             const real phIp = theta_nb(PhI, nr, nth, k + 1, j, par);
             const real phR = PhR[i], phI = PhI[i], piR = PiR[i], piI = PiI[i];
-            const real d1R = (phRp - phRm) * ih1, d1I = (phIp - phIm) * ih1;
-            const real d2R = (phRp - R(2) * phR + phRm) * ih2, d2I = (phIp - R(2) * phI + phIm) * ih2;
+            real d1R, d1I, d2R, d2I;
+            if (th4) {
+                const real phRmm = theta_nb(PhR, nr, nth, k - 2, j, par);
+                const real phRpp = theta_nb(PhR, nr, nth, k + 2, j, par);
+                const real phImm = theta_nb(PhI, nr, nth, k - 2, j, par);
+                const real phIpp = theta_nb(PhI, nr, nth, k + 2, j, par);
+                d1R = (-phRpp + R(8) * phRp - R(8) * phRm + phRmm) * ih1_4;
+                d1I = (-phIpp + R(8) * phIp - R(8) * phIm + phImm) * ih1_4;
+                d2R = (-phRpp + R(16) * phRp - R(30) * phR + R(16) * phRm - phRmm) * ih2_4;
+                d2I = (-phIpp + R(16) * phIp - R(30) * phI + R(16) * phIm - phImm) * ih2_4;
+            } else {
+                d1R = (phRp - phRm) * ih1;
+                d1I = (phIp - phIm) * ih1;
+                d2R = (phRp - R(2) * phR + phRm) * ih2;
+                d2I = (phIp - R(2) * phI + phIm) * ih2;
+            }
             /* complex products m3 dPhi, B~t pi, C~ Phi */
             const real mdR = P->m3r[i] * dPhR - P->m3i[i] * dPhI;
             const real mdI = P->m3r[i] * dPhI + P->m3i[i] * dPhR;
