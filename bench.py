@@ -147,12 +147,13 @@ def dd_roofline(points_per_launch: float, t_launch: float, variant: str):
             "valu_issue_frac": instrs * points_per_launch / t_launch / VALU_ISSUE_PER_S}
 
 
-def solver_config(T, wl, weights, total_steps, workgroups=0, every=None, state="fp64", integrator="rk3"):
+def solver_config(T, wl, weights, total_steps, workgroups=0, every=None, state="fp64", integrator="rk3",
+                  theta_order=2):
     every = wl.every if every is None else every
     return T.make_config(s=wl.s, m=wl.m, a=wl.a, nr=wl.nr, ntheta=wl.nth, x_min=wl.x_min, x_max=wl.x_max,
                          M=wl.M, dt=0.0, cfl=0.5, weight_prec=weights, x_extract=wl.x_e, extract_every=every,
                          max_samples=total_steps // every + 1 if every > 0 else 0, workgroups=workgroups,
-                         state=state, integrator=integrator)
+                         state=state, integrator=integrator, theta_order=theta_order)
 
 
 def copy_probe(mib, torch):
@@ -179,13 +180,13 @@ def bench_single(args, torch, T, W):
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
 
-    def run(wp, state="fp64", nsteps=None, nwarm=None, integrator="rk3", every=None, graph=0):
+    def run(wp, state="fp64", nsteps=None, nwarm=None, integrator="rk3", every=None, graph=0, theta_order=2):
         """Warm up, then time `nsteps` steps with HIP events on the solver's
         stream.  Returns (seconds, wall seconds, info, waveform samples)."""
         nsteps = steps if nsteps is None else nsteps
         nwarm = warmup if nwarm is None else nwarm
         sv = T.Solver(solver_config(T, wl, wp, nwarm + nsteps, args.workgroups, state=state,
-                                    integrator=integrator, every=every), stream=stream)
+                                    integrator=integrator, every=every, theta_order=theta_order), stream=stream)
         sv.set_initial(u0)
         log(f"{state}/{wp}/{integrator}{' graph ' + str(graph) if graph else ''}: warmup {nwarm} steps")
         sv.step(nwarm)
@@ -220,6 +221,11 @@ def bench_single(args, torch, T, W):
             tuned[integ] = {"workgroups": ti.workgroups, "segs_per_strip": ti.segs, "candidates": ti.candidates,
                             "us_per_step": ti.us_per_step, "default_workgroups": ti.default_workgroups,
                             "default_segs_per_strip": ti.default_segs, "us_per_step_default": ti.us_per_step_default}
+        if not args.no_theta4:
+            log("autotuner: rk3, fourth-order theta differences")
+            ti = T.teuk_tune(solver_config(T, wl, weights, 1, 0, every=0, theta_order=4), 0)
+            tuned["rk3_theta4"] = {"workgroups": ti.workgroups, "segs_per_strip": ti.segs,
+                                   "us_per_step": ti.us_per_step, "us_per_step_default": ti.us_per_step_default}
 
     # Reduced-precision weights over the workload's full length (the waveform
     # at x_e needs the pulse to have passed it), before the headline timing:
@@ -264,6 +270,14 @@ def bench_single(args, torch, T, W):
         sec_o, _, _, wave_o = run(weights, graph=other)
         out["graph"] = {"chunk_steps": other, "ms_per_step": sec_o / steps * 1e3, "value": pu / sec_o,
                         "speedup_vs_headline": gpu_s / sec_o, "waveform_identical": bool(np.array_equal(wave_o, wave))}
+    if not args.no_theta4:
+        # the same workload with fourth-order theta differences (two rows
+        # ahead and behind; the same HBM traffic per point, a smaller dt)
+        sec4, _, info4, _ = run(weights, graph=graph, theta_order=4)
+        out["theta4"] = {"steps": steps, "dt": info4.dt, "ms_per_step": sec4 / steps * 1e3, "value": pu / sec4,
+                         "speed_vs_second_order": gpu_s / sec4,
+                         "simulated_time_per_s_vs_second_order": (info4.dt / sec4) / (info.dt / gpu_s),
+                         "hbm_frac": roofline(wl.points, sec4 / (3 * steps), None)["frac"]}
     if weights == "fp64" and not args.no_pipelined:
         # the same steps in one cooperative launch per waveform interval (tiles
         # wait for their neighbours' previous stage only)
@@ -714,6 +728,8 @@ def main():
     ap.add_argument("--no-rk104", action="store_true", help="C2: skip the SSP-RK(10,4) run")
     ap.add_argument("--no-blocked", action="store_true", help="C2: skip the temporally blocked run")
     ap.add_argument("--no-pipelined", action="store_true", help="C1/C2: skip the pipelined-step run")
+    ap.add_argument("--no-theta4", action="store_true",
+                    help="C1/C2: skip the run with fourth-order theta differences")
     ap.add_argument("--quad-steps", type=int, default=1000,
                     help="C2: steps of the double-double state runs (0: skip them)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,

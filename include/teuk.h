@@ -14,7 +14,9 @@
  * x = r_* (Sec. 2.2) and Psi = exp(i m phi~) r^-(2s+1) Phi, so that Phi is O(1)
  * at large r.  The radial derivative is fifth-order WENO of Jiang and Shu
  * (Sec. 3.1.2), upwinded per row by the sign of its speed (+b for the Phi rows,
- * -b for the pi rows); theta derivatives are second-order centred (Sec. 3.1);
+ * -b for the pi rows); theta derivatives are centred (Sec. 3.1, which leaves
+ * their order open): second order by default, fourth order on request
+ * (teuk_config.theta_order);
  * time stepping is SSP-RK(3,3) in Shu-Osher form (Sec. 3.2).  The WENO
  * smoothness indicators and weights may be computed in reduced precision with
  * the weights summing to one in FP64 (Sec. 3.1.3); candidate fluxes, flux
@@ -33,8 +35,10 @@
  *
  * Grid: x_j = x_min + j (x_max - x_min)/(nr - 1), j = 0..nr-1;
  *       theta_k = (k + 1/2) pi / ntheta, k = 0..ntheta-1 (no node on a pole).
- * Boundaries: three ghost cells per radial side equal to the end value; one
- *       ghost row per pole equal to (-1)^(m+s) times the mirrored row.
+ * Boundaries: three ghost cells per radial side equal to the end value; in
+ *       theta, ghost rows beyond each pole equal to (-1)^(m+s) times the row
+ *       mirrored across it (row -1 - g mirrors row g, row ntheta + g mirrors
+ *       row ntheta - 1 - g): one per pole at second order, two at fourth.
  * State layout (host arrays across this ABI): four FP64 planes
  *       [4][ntheta][nr] in the order Phi_R, Phi_I, pi_R, pi_I, radial index
  *       fastest, densely packed.  With TEUK_S_DD every value is a (hi, lo)
@@ -180,7 +184,13 @@ typedef struct {
     int32_t state_prec;      /* TEUK_S_*                                              */
     int32_t integrator;      /* TEUK_RK_*                                             */
     int32_t scheme;          /* TEUK_SCHEME_*                                         */
-    int32_t reserved;        /* must be 0                                             */
+    int32_t theta_order;     /* order of the centred theta differences (Sec. 3.1):
+                                0 or 2: D1 = (u+ - u-)/(2 dth), D2 = (u+ - 2u + u-)/dth^2;
+                                4: D1 = (-u++ + 8u+ - 8u- + u--)/(12 dth),
+                                   D2 = (-u++ + 16u+ - 30u + 16u- - u--)/(12 dth^2)
+                                (tortoise chart, FP64 state, WENO5, TEUK_RK_SSP33 or
+                                TEUK_RK_SSP104; any weight precision; groups and graph
+                                mode too; else UNSUPPORTED)                             */
     double M;                /* black-hole mass (> 0)                                  */
     double a;                /* spin, 0 <= a <= M                                      */
     double x_min, x_max;     /* radial range of x (r_* or rho; x_min < x_max)          */
@@ -216,7 +226,7 @@ typedef struct {
 } teuk_info_t;
 
 /* Fill cfg with defaults: ABI version, M = 1, chart T, FP64 state and weights,
- * SSP-RK(3,3), WENO5 (ko_sigma 0.01 for FD6), cfl 0.5,
+ * SSP-RK(3,3), WENO5 (ko_sigma 0.01 for FD6), second-order theta differences, cfl 0.5,
  * eps 1e-6, dt from the bound, no waveform.  Sizes and ranges must still be set. */
 void teuk_default_config(teuk_config* cfg);
 
@@ -229,7 +239,10 @@ size_t teuk_footprint_bytes(const teuk_config* cfg);
  * background r(x), Delta(x) and the radial / polar coefficient tables on the
  * host in FP64 (Sec. 2.1-2.3), upload them, and compute the stability bound by
  * a device max-reduction over every grid point (Sec. 3.2, dt <= C dt_FE):
- *     dt_bound = 1 / max( b/dx + sqrt(4 A~thth/dtheta^2 + |B~th|/dtheta + |C~|) ).
+ *     dt_bound = 1 / max( b/dx + sqrt(c2 A~thth/dtheta^2 + c1 |B~th|/dtheta + |C~|) ),
+ * c2 and c1 the largest moduli of the Fourier symbols of dtheta^2 D2 and
+ * dtheta D1: (4, 1) at second order, (16/3, 1.3722...) at fourth, the latter
+ * sin(xi) (4 - cos xi)/3 at cos xi = 1 - sqrt(3/2).
  * If cfg->dt <= 0 the step is cfl * C * dt_bound (C = 1 for SSP-RK(3,3), 6 for
  * SSP-RK(10,4)).  ctx may be NULL.  On success
  * *out owns its device buffers (or lives in ctx->workspace, which the caller

@@ -71,7 +71,7 @@ class teuk_config(ctypes.Structure):
                 ("weight_prec", ctypes.c_int32), ("extract_every", ctypes.c_int32),
                 ("max_samples", ctypes.c_int32), ("workgroups", ctypes.c_int32),
                 ("state_prec", ctypes.c_int32), ("integrator", ctypes.c_int32),
-                ("scheme", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("scheme", ctypes.c_int32), ("theta_order", ctypes.c_int32),
                 ("M", ctypes.c_double), ("a", ctypes.c_double), ("x_min", ctypes.c_double),
                 ("x_max", ctypes.c_double), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("weno_eps", ctypes.c_double), ("x_extract", ctypes.c_double), ("S", ctypes.c_double),
@@ -335,7 +335,8 @@ def make_config(*, s: int, m: int, a: float, nr: int, ntheta: int, x_min: float,
                 M: float = 1.0, dt: float = 0.0, cfl: float = 0.5, weno_eps: float = 1e-6,
                 weight_prec="fp64", x_extract: float | None = None, extract_every: int = 0,
                 max_samples: int = 0, workgroups: int = 0, chart="T", S: float = 20.0,
-                state="fp64", integrator="rk3", scheme="weno5", ko_sigma: float = 0.01) -> teuk_config:
+                state="fp64", integrator="rk3", scheme="weno5", ko_sigma: float = 0.01,
+                theta_order: int = 2) -> teuk_config:
     c = teuk_default_config()
     c.s, c.m, c.a, c.M = int(s), int(m), float(a), float(M)
     c.nr, c.ntheta = int(nr), int(ntheta)
@@ -351,6 +352,7 @@ def make_config(*, s: int, m: int, a: float, nr: int, ntheta: int, x_min: float,
     c.integrator = INTEGRATOR[integrator] if isinstance(integrator, str) else int(integrator)
     c.scheme = SCHEME[scheme] if isinstance(scheme, str) else int(scheme)
     c.ko_sigma = float(ko_sigma)
+    c.theta_order = int(theta_order)
     return c
 
 

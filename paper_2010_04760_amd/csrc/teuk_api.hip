@@ -60,7 +60,7 @@ struct teuk_solver {
     std::string err;
 };
 
-constexpr int kClasses = 8;   // (weight precision, chart) pairs
+constexpr int kClasses = 12;  // (weight precision, launch class) pairs: 4 x (T, H, T with 4th-order theta)
 constexpr int kMaxGraphChunk = 4096;   // steps per captured graph
 constexpr long long kPipeSpinTicks = 200000000;   // 2 s of the 100 MHz real-time counter
 
@@ -197,7 +197,7 @@ bool validate(const teuk_config* c, std::string& err)
     if (c->state_prec != TEUK_S_FP64 && c->state_prec != TEUK_S_DD) { err = "state_prec must be a TEUK_S_* value"; return false; }
     if (c->integrator < TEUK_RK_SSP33 || c->integrator > TEUK_RK_SSP33_PIPELINED) { err = "integrator must be a TEUK_RK_* value"; return false; }
     if (c->scheme < TEUK_SCHEME_WENO5 || c->scheme > TEUK_SCHEME_FD6KO8) { err = "scheme must be a TEUK_SCHEME_* value"; return false; }
-    if (c->reserved != 0) { err = "reserved must be 0"; return false; }
+    if (c->theta_order != 0 && c->theta_order != 2 && c->theta_order != 4) { err = "theta_order must be 0, 2 or 4"; return false; }
     if (!(c->ko_sigma >= 0.0) || !(c->ko_sigma <= 1.0)) { err = "ko_sigma must lie in [0, 1]"; return false; }
     if (c->weight_prec == TEUK_W_DD && c->state_prec != TEUK_S_DD) { err = "TEUK_W_DD weights need the TEUK_S_DD state"; return false; }
     if (!(c->M > 0.0) || !std::isfinite(c->M)) { err = "M must be positive and finite"; return false; }
@@ -231,7 +231,7 @@ bool validate(const teuk_config* c, std::string& err)
 // one so that neighbouring segments pair up, and at most one per theta row.
 int pick_segs(const teuk_config& c, int nstrips, int weight_prec, bool first)
 {
-    long long cap = c.workgroups > 0 ? c.workgroups : stage_grid(weight_prec, first, c.chart);
+    long long cap = c.workgroups > 0 ? c.workgroups : stage_grid(weight_prec, first, kernel_chart(c));
     if (cap <= 0) return 0;
     long long segs = cap / nstrips;
     if (segs > c.ntheta) segs = c.ntheta;
@@ -344,6 +344,7 @@ void teuk_default_config(teuk_config* c)
     c->weno_eps = 1e-6;
     c->S = 20.0;
     c->ko_sigma = 0.01;
+    c->theta_order = 2;
 }
 
 size_t teuk_footprint_bytes(const teuk_config* cfg)
@@ -375,6 +376,12 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     if (cfg->integrator == TEUK_RK_SSP33_PIPELINED &&
         (chartH || dd || cfg->scheme != TEUK_SCHEME_WENO5 || cfg->weight_prec == TEUK_W_DD))
         return fail(nullptr, TEUK_ERR_UNSUPPORTED, "pipelined steps: tortoise chart, FP64 state, WENO5 only");
+    if (cfg->theta_order == 4 &&
+        (chartH || dd || cfg->scheme != TEUK_SCHEME_WENO5 ||
+         (cfg->integrator != TEUK_RK_SSP33 && cfg->integrator != TEUK_RK_SSP104)))
+        return fail(nullptr, TEUK_ERR_UNSUPPORTED,
+                    "fourth-order theta differences: tortoise chart, FP64 state, WENO5, "
+                    "SSP-RK(3,3) or SSP-RK(10,4) stepped stage by stage");
     std::vector<double> rtab, ttab, ctab, dtab;
     DDScalars ddk{};
     if (chartH ? !build_tables_H(*cfg, ctab, err) : !build_tables(*cfg, rtab, ttab, err))
@@ -482,7 +489,8 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
         e = (int)hipMemcpyAsync(h->dtab, dtab.data(), dtab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
     if (!e) e = (int)hipMemsetAsync(h->cell, 0, sizeof(unsigned long long), h->stream);
     if (!e) e = (int)hipMemsetAsync(h->perr, 0, sizeof(int), h->stream);
-    if (!e) e = launch_dt_bound(h->rtab, h->ttab, h->ctab, cfg->nr, cfg->ntheta, h->dx, h->dth, h->cell, h->stream);
+    if (!e) e = launch_dt_bound(h->rtab, h->ttab, h->ctab, cfg->nr, cfg->ntheta, h->dx, h->dth, cfg->theta_order,
+                                h->cell, h->stream);
     unsigned long long bits = 0;
     if (!e) e = (int)hipMemcpyAsync(&bits, h->cell, sizeof(bits), hipMemcpyDeviceToHost, h->stream);
     if (!e) e = (int)hipStreamSynchronize(h->stream);
@@ -616,8 +624,7 @@ static StageArgs stage_args(const teuk_solver* h)
     a.segs = h->segs[0];
     a.grid = h->nstrips * h->segs[0];
     a.inv6dx = 1.0 / (6.0 * h->dx);
-    a.ih1 = 1.0 / (2.0 * h->dth);
-    a.ih2 = 1.0 / (h->dth * h->dth);
+    theta_scales(c.theta_order, h->dth, &a.ih1, &a.ih2);
     a.dt = h->dt;
     a.ca = 0.0;
     a.cb = 1.0;
@@ -638,7 +645,7 @@ static int run_stage(const teuk_solver* h, const StageArgs& a, int stage)
 {
     const teuk_config& c = h->cfg;
     if (c.scheme != TEUK_SCHEME_WENO5) return launch_cmp_stage(a, stage, c.scheme, c.chart, h->stream);
-    return launch_stage(a, stage, c.weight_prec, c.chart, h->stream);
+    return launch_stage(a, stage, c.weight_prec, kernel_chart(c), h->stream);
 }
 
 // One SSP-RK(10,4) step (Sec. 3.2) in the three state buffers U = u^n,
@@ -1117,7 +1124,7 @@ static teuk_status group_upload(teuk_group* g)
         };
         open_block();
         for (teuk_solver* h : g->mem) {
-            if (h->cfg.weight_prec + 4 * h->cfg.chart != c) continue;
+            if (h->cfg.weight_prec + 4 * kernel_chart(h->cfg) != c) continue;
             if (blk.n > 0 && bytes + (long long)h->bytes > g->block_bytes) {
                 close_block();
                 open_block();
@@ -1655,8 +1662,7 @@ extern "C" teuk_status teuk_step_noalloc(const teuk_config* cfg, double* u, int6
     a.nth = cfg->ntheta;
     a.nstrips = nstrips;
     a.inv6dx = 1.0 / (6.0 * dx);
-    a.ih1 = 1.0 / (2.0 * dth);
-    a.ih2 = 1.0 / (dth * dth);
+    theta_scales(cfg->theta_order, dth, &a.ih1, &a.ih2);
     a.dt = cfg->dt;
     a.out2 = nullptr;
     a.ca2 = a.cb2 = 0.0;
@@ -1664,14 +1670,15 @@ extern "C" teuk_status teuk_step_noalloc(const teuk_config* cfg, double* u, int6
     a.ko_sigma = cfg->ko_sigma;
     a.eps = cfg->weno_eps;
     a.parity = ((cfg->m + cfg->s) % 2 != 0) ? -1.0 : 1.0;
+    const int kchart = kernel_chart(*cfg);
     for (int64_t n = 0; n < nsteps && !e; ++n) {
         // consecutive launches march their segments in opposite directions (see teuk_step)
         a.uk = u; a.un = u; a.out = u1; a.ca = 0.0; a.cb = 1.0; a.segs = segs1; a.grid = nstrips * segs1; a.flip = (int)(n & 1);
-        e = launch_stage(a, 1, cfg->weight_prec, cfg->chart, st);
+        e = launch_stage(a, 1, cfg->weight_prec, kchart, st);
         if (!e) { a.uk = u1; a.un = u; a.out = u2; a.ca = 0.75; a.cb = 0.25; a.segs = segs23; a.grid = nstrips * segs23;
-                  a.flip ^= 1; e = launch_stage(a, 2, cfg->weight_prec, cfg->chart, st); }
+                  a.flip ^= 1; e = launch_stage(a, 2, cfg->weight_prec, kchart, st); }
         if (!e) { a.uk = u2; a.un = u; a.out = u; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0;
-                  a.flip ^= 1; e = launch_stage(a, 3, cfg->weight_prec, cfg->chart, st); }
+                  a.flip ^= 1; e = launch_stage(a, 3, cfg->weight_prec, kchart, st); }
     }
     if (e) return fail(nullptr, TEUK_ERR_DEVICE, std::string("stage launch: ") + hipGetErrorString((hipError_t)e));
     return TEUK_OK;

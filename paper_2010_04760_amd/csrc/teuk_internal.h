@@ -21,6 +21,23 @@ bool build_tables(const teuk_config& c, std::vector<double>& rtab, std::vector<d
 // validated TEUK_CHART_HYPERBOLOIDAL configuration.
 bool build_tables_H(const teuk_config& c, std::vector<double>& ctab, std::string& err);
 
+// Launch class of the stage kernels: the chart (TEUK_CHART_*), with the
+// tortoise chart at fourth-order theta differences a class of its own.
+constexpr int kChartTortoise4 = 2;
+inline int kernel_chart(const teuk_config& c)
+{
+    return (c.chart == TEUK_CHART_TORTOISE && c.theta_order == 4) ? kChartTortoise4 : c.chart;
+}
+
+// Scales of the centred theta differences as the stage kernels take them:
+// 1/(2 dth) and 1/dth^2 at second order, 1/(12 dth) and 1/(12 dth^2) at fourth.
+inline void theta_scales(int theta_order, double dth, double* ih1, double* ih2)
+{
+    const double d = theta_order == 4 ? 12.0 : 1.0;
+    *ih1 = 1.0 / ((theta_order == 4 ? 12.0 : 2.0) * dth);
+    *ih2 = 1.0 / (d * dth * dth);
+}
+
 // Points per radial strip of one stage workgroup (one wave of 64 lanes computes
 // 64 interface fluxes and 63 point updates).
 constexpr int kStripPoints = 63;
@@ -39,7 +56,7 @@ struct StageArgs {
     int segs;              // theta segments per strip (grid = nstrips * segs)
     int grid;              // workgroups launched
     double inv6dx;         // 1 / (6 dx): candidate fluxes are carried times 6
-    double ih1, ih2;       // 1/(2 dtheta), 1/dtheta^2
+    double ih1, ih2;       // theta-difference scales (theta_scales)
     double dt, ca, cb;     // out = ca un + cb (uk + dt F)
     double* out2;          // dual stage: second output ca2 un + cb2 (uk + dt F); may alias un
     double ca2, cb2;
@@ -83,8 +100,10 @@ int launch_stage(const StageArgs& a, int stage, int weight_prec, int chart, void
 // each), tiles = start[nmem].
 int launch_group_stage(const StageArgs* args, const long long* start, int nmem, long long tiles, int grid,
                        int stage, int weight_prec, int chart, void* stream);
+// Stability-bound reduction; theta_order picks the Fourier-symbol maxima of
+// the theta differences.
 int launch_dt_bound(const double* rtab, const double* ttab, const double* ctab, int nr, int nth, double dx,
-                    double dth, unsigned long long* cell, void* stream);
+                    double dth, int theta_order, unsigned long long* cell, void* stream);
 int launch_guard(const double* u, long long n, int* flag, void* stream);
 int launch_coef_dump(const double* rtab, const double* ttab, const double* ctab, int nr, int nth, double* out,
                      void* stream);

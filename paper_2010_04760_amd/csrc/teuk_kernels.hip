@@ -47,6 +47,9 @@ constexpr bool reads_un() { return kMode == kStageLater || kMode == kStageDual; 
 // Radial chart (TEUK_CHART_*).
 constexpr int kChartT = TEUK_CHART_TORTOISE;
 constexpr int kChartH = TEUK_CHART_HYPERBOLOIDAL;
+// The tortoise chart with fourth-order theta differences (a launch class of
+// its own; the ABI's chart field stays TEUK_CHART_TORTOISE).
+constexpr int kChartT4 = kChartTortoise4;
 
 // 1/x from the hardware estimate refined by one Newton step.
 __device__ __forceinline__ double rcp64(double x)
@@ -608,7 +611,14 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
 //         i.e. vmcnt <= (12 + it) at i = 0 and vmcnt <= 2 it for i >= 1,
 //         it = loads per iteration (16 later stages, 12 otherwise);
 //     before the stores: u^n of row i has landed, vmcnt <= 12.
-template <int WP, int kMode, bool kLevel, bool kCoh = false>
+// kTh4 (fourth-order theta differences) also reads Phi on row i + 2, so it
+// waits for everything up to row i + 2 (vmcnt <= it at every i), keeps the
+// two rows behind in registers, and stages up to two rows past the segment.
+// Beyond a pole, ghost row -1 - g is parity x row g (and row nth + g is
+// parity x row nth - 1 - g): the ahead rows then come from the rows already
+// at hand (row k + 2 dir mirrors k + dir when only it is a ghost, and k - dir
+// when both are).
+template <int WP, int kMode, bool kLevel, bool kCoh = false, bool kTh4 = false>
 __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, int strip, int k0, int k1, int dir)
 {
     const int l = threadIdx.x;
@@ -639,19 +649,27 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
 
     const int n = k1 - k0;
     const int first = dir > 0 ? k0 : k1 - 1;
-    double bhR, bhI;
-    {
-        const int kb = first - dir;
-        if (kb >= 0 && kb < nth) {
-            bhR = ldb_c<kCoh>(ukp[0] + (size_t)kb * nr, oc);
-            bhI = ldb_c<kCoh>(ukp[1] + (size_t)kb * nr, oc);
-        } else {
-            bhR = A.parity * ldb_c<kCoh>(ukp[0] + (size_t)first * nr, oc);
-            bhI = A.parity * ldb_c<kCoh>(ukp[1] + (size_t)first * nr, oc);
+    // Phi on the rows behind (k - dir, and k - 2 dir for kTh4), pole ghosts mirrored
+    auto behind = [&](int kb, double& vR, double& vI) {
+        const bool ghost = kb < 0 || kb >= nth;
+        const int km = kb < 0 ? -1 - kb : (kb >= nth ? 2 * nth - 1 - kb : kb);
+        vR = ldb_c<kCoh>(ukp[0] + (size_t)km * nr, oc);
+        vI = ldb_c<kCoh>(ukp[1] + (size_t)km * nr, oc);
+        if (ghost) {
+            vR *= A.parity;
+            vI *= A.parity;
         }
-    }
+    };
+    double bhR, bhI, bh2R = 0.0, bh2I = 0.0;
+    behind(first - dir, bhR, bhI);
+    if constexpr (kTh4) behind(first - 2 * dir, bh2R, bh2I);
+    // rows staged: the segment's n rows and the rows past it that lie in the grid
     const int ahead_last = first + dir * n;
-    const int nst = (ahead_last >= 0 && ahead_last < nth) ? n + 1 : n;
+    int nst = (ahead_last >= 0 && ahead_last < nth) ? n + 1 : n;
+    if constexpr (kTh4) {
+        const int ahead2 = ahead_last + dir;
+        if (nst > n && ahead2 >= 0 && ahead2 < nth) ++nst;
+    }
 
     // 12 DMA operations: march row i into its slot, or, where the march has no
     // row i, the first dword of each plane (one cache line, read by every lane)
@@ -704,7 +722,8 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
         }
         issue_row(i + 3);
         constexpr int it = reads_un<kMode>() ? 16 : 12;
-        if (i == 0) vm_wait<12 + it>();
+        if constexpr (kTh4) vm_wait<it>();
+        else if (i == 0) vm_wait<12 + it>();
         else vm_wait<2 * it>();
         const int b = i & (kRing - 1), bn = (i + 1) & (kRing - 1);
 
@@ -722,6 +741,20 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
             ahR = A.parity * phR;
             ahI = A.parity * phI;
         }
+        double ah2R = 0.0, ah2I = 0.0;   // Phi on row k + 2 dir (kTh4)
+        if constexpr (kTh4) {
+            if (i + 2 < nst) {
+                const int bn2 = (i + 2) & (kRing - 1);
+                ah2R = sr[bn2][0][l + 3];
+                ah2I = sr[bn2][1][l + 3];
+            } else if (i + 1 < nst) {
+                ah2R = A.parity * ahR;
+                ah2I = A.parity * ahI;
+            } else {
+                ah2R = A.parity * bhR;
+                ah2I = A.parity * bhI;
+            }
+        }
         const double fR1 = __shfl_down(fR, 1);
         const double fI1 = __shfl_down(fI, 1);
         const double gR1 = __shfl_down(gR, 1);
@@ -736,9 +769,21 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
             const PointCoef c = point_coef(rt, sn2, cs, cot, th, rsq64(sigma2(rt, sn2)));
             const double upR = dir > 0 ? ahR : bhR, upI = dir > 0 ? ahI : bhI;
             const double dnR = dir > 0 ? bhR : ahR, dnI = dir > 0 ? bhI : ahI;
-            const double d1R = (upR - dnR) * A.ih1, d1I = (upI - dnI) * A.ih1;
-            const double d2R = (upR - 2.0 * phR + dnR) * A.ih2;
-            const double d2I = (upI - 2.0 * phI + dnI) * A.ih2;
+            double d1R, d1I, d2R, d2I;
+            if constexpr (kTh4) {
+                // ih1 = 1/(12 dtheta), ih2 = 1/(12 dtheta^2)
+                const double up2R = dir > 0 ? ah2R : bh2R, up2I = dir > 0 ? ah2I : bh2I;
+                const double dn2R = dir > 0 ? bh2R : ah2R, dn2I = dir > 0 ? bh2I : ah2I;
+                d1R = (8.0 * (upR - dnR) - (up2R - dn2R)) * A.ih1;
+                d1I = (8.0 * (upI - dnI) - (up2I - dn2I)) * A.ih1;
+                d2R = (16.0 * (upR + dnR) - 30.0 * phR - (up2R + dn2R)) * A.ih2;
+                d2I = (16.0 * (upI + dnI) - 30.0 * phI - (up2I + dn2I)) * A.ih2;
+            } else {
+                d1R = (upR - dnR) * A.ih1;
+                d1I = (upI - dnI) * A.ih1;
+                d2R = (upR - 2.0 * phR + dnR) * A.ih2;
+                d2I = (upI - 2.0 * phI + dnI) * A.ih2;
+            }
             const double FphR = piR - c.b * dPhR;
             const double FphI = piI - c.b * dPhI;
             const double FpiR = c.b * dPiR - (c.m3r * dPhR - c.m3i * dPhI) + (c.btr * piR - c.bti * piI) +
@@ -773,6 +818,10 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
                 stb_c<kCoh>(A.out2 + 3 * P + row, oc, A.ca2 * n3 + A.cb2 * v3);
             }
         }
+        if constexpr (kTh4) {
+            bh2R = bhR;
+            bh2I = bhI;
+        }
         bhR = phR;
         bhI = phI;
     }
@@ -794,8 +843,8 @@ constexpr unsigned kLdsBytes = kRing * kSlotBytes;   // 9216 >= 2 * 4 * kRow * 8
 template <int WP, int kMode, int kChart, bool kLevel = false, bool kCoh = false>
 __device__ __forceinline__ void march(const StageArgs& A, char* lds, int strip, int k0, int k1, int dir)
 {
-    if constexpr (kChart == kChartT)
-        march_strip_t<WP, kMode, kLevel, kCoh>(A, lds, strip, k0, k1, dir);
+    if constexpr (kChart == kChartT || kChart == kChartT4)
+        march_strip_t<WP, kMode, kLevel, kCoh, kChart == kChartT4>(A, lds, strip, k0, k1, dir);
     else
         march_strip<WP, kMode, kChart>(A, reinterpret_cast<double (*)[4][kRow]>(lds), strip, k0, k1, dir);
 }
@@ -1227,7 +1276,8 @@ __global__ __launch_bounds__(kBThreads) void blocked_step_kernel(StageArgs A)
 __global__ __launch_bounds__(256) void dt_bound_kernel(const double* __restrict__ rtab,
                                                        const double* __restrict__ ttab,
                                                        const double* __restrict__ ctab, int nr, int nth,
-                                                       double idx, double idth, unsigned long long* cell)
+                                                       double idx, double idth, double c2, double c1,
+                                                       unsigned long long* cell)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long n = (long long)nr * nth;
@@ -1253,7 +1303,7 @@ __global__ __launch_bounds__(256) void dt_bound_kernel(const double* __restrict_
             cr = c.cr;
             ci = c.ci;
         }
-        val = lam * idx + sqrt(4.0 * ath * idth * idth + fabs(bth) * idth + hypot(cr, ci));
+        val = lam * idx + sqrt(c2 * ath * idth * idth + c1 * fabs(bth) * idth + hypot(cr, ci));
     }
     for (int off = 32; off > 0; off >>= 1) val = fmax(val, __shfl_xor(val, off));
     __shared__ double sm[4];
@@ -1376,6 +1426,10 @@ int stage_grid(int weight_prec, bool first, int chart)
     TEUK_OCC(TEUK_W_FP32, kChartH)
     TEUK_OCC(TEUK_W_FP16, kChartH)
     TEUK_OCC(TEUK_W_BF16, kChartH)
+    TEUK_OCC(TEUK_W_FP64, kChartT4)
+    TEUK_OCC(TEUK_W_FP32, kChartT4)
+    TEUK_OCC(TEUK_W_FP16, kChartT4)
+    TEUK_OCC(TEUK_W_BF16, kChartT4)
 #undef TEUK_OCC
     if (e != hipSuccess || per_cu < 1) return 0;
     return cus * per_cu;
@@ -1446,6 +1500,10 @@ int launch_stage(const StageArgs& a, int stage, int weight_prec, int chart, void
     TEUK_LAUNCH(TEUK_W_FP32, kChartH)
     TEUK_LAUNCH(TEUK_W_FP16, kChartH)
     TEUK_LAUNCH(TEUK_W_BF16, kChartH)
+    TEUK_LAUNCH(TEUK_W_FP64, kChartT4)
+    TEUK_LAUNCH(TEUK_W_FP32, kChartT4)
+    TEUK_LAUNCH(TEUK_W_FP16, kChartT4)
+    TEUK_LAUNCH(TEUK_W_BF16, kChartT4)
 #undef TEUK_LAUNCH
     if (!done) return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();
@@ -1501,19 +1559,34 @@ int launch_group_stage(const StageArgs* args, const long long* start, int nmem, 
     TEUK_GLAUNCH(TEUK_W_FP32, kChartH)
     TEUK_GLAUNCH(TEUK_W_FP16, kChartH)
     TEUK_GLAUNCH(TEUK_W_BF16, kChartH)
+    TEUK_GLAUNCH(TEUK_W_FP64, kChartT4)
+    TEUK_GLAUNCH(TEUK_W_FP32, kChartT4)
+    TEUK_GLAUNCH(TEUK_W_FP16, kChartT4)
+    TEUK_GLAUNCH(TEUK_W_BF16, kChartT4)
 #undef TEUK_GLAUNCH
     if (!done) return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();
 }
 
 int launch_dt_bound(const double* rtab, const double* ttab, const double* ctab, int nr, int nth, double dx,
-                    double dth, unsigned long long* cell, void* stream)
+                    double dth, int theta_order, unsigned long long* cell, void* stream)
 {
+    // Largest moduli of the Fourier symbols of dth^2 D2 and dth D1.  Second
+    // order: |2 cos xi - 2| <= 4 and |sin xi| <= 1.  Fourth order:
+    // |(32 cos xi - 2 cos 2xi - 30)/12| <= 16/3 (at xi = pi), and
+    // (8 sin xi - sin 2xi)/6 peaks where 8 cos xi = 2 cos 2xi, i.e. at
+    // cos xi = 1 - sqrt(3/2), with the value sin xi (4 - cos xi)/3.
+    double c2 = 4.0, c1 = 1.0;
+    if (theta_order == 4) {
+        const double cx = 1.0 - std::sqrt(1.5);
+        c2 = 16.0 / 3.0;
+        c1 = std::sqrt(1.0 - cx * cx) * (4.0 - cx) / 3.0;
+    }
     (void)hipGetLastError();
     const long long n = (long long)nr * nth;
     const unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(dt_bound_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, rtab, ttab, ctab, nr, nth,
-                       1.0 / dx, 1.0 / dth, cell);
+                       1.0 / dx, 1.0 / dth, c2, c1, cell);
     return (int)hipGetLastError();
 }
 

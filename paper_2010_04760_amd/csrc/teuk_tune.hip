@@ -25,8 +25,8 @@
 
 namespace {
 
-// What a tuned budget applies to: device, chart, weight and state precision,
-// integrator, scheme and grid.
+// What a tuned budget applies to: device, launch class (chart and theta
+// order), weight and state precision, integrator, scheme and grid.
 typedef std::tuple<int, int, int, int, int, int, int, int> TuneKey;
 
 std::mutex g_tune_mutex;
@@ -35,7 +35,8 @@ thread_local std::string g_tune_err;
 
 TuneKey key_of(const teuk_config& c, int device)
 {
-    return TuneKey(device, c.chart, c.weight_prec, c.state_prec, c.integrator, c.scheme, c.nr, c.ntheta);
+    return TuneKey(device, teuk::kernel_chart(c), c.weight_prec, c.state_prec, c.integrator, c.scheme, c.nr,
+                   c.ntheta);
 }
 
 // Theta segments per strip that a workgroup budget gives (the rule of
@@ -133,7 +134,7 @@ teuk_status teuk_tune(const teuk_config* cfg, int32_t steps, teuk_tune_info_t* o
     const bool blocked = cfg->integrator == TEUK_RK_SSP33_BLOCKED;
     const int strip = blocked ? teuk::kBlockedPoints : teuk::kStripPoints;
     const int nstrips = (cfg->nr + strip - 1) / strip;
-    const long long resident = blocked ? teuk::blocked_grid() : teuk::stage_grid(cfg->weight_prec, false, cfg->chart);
+    const long long resident = blocked ? teuk::blocked_grid() : teuk::stage_grid(cfg->weight_prec, false, teuk::kernel_chart(*cfg));
     if (resident <= 0) return tfail(TEUK_ERR_UNSUPPORTED, "occupancy query failed");
 
     // candidate budgets around the resident count, one per distinct segment count

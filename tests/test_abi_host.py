@@ -153,7 +153,8 @@ def test_footprint_and_validation():
     assert fp >= 3 * 4 * 512 * 32 * 8
     bad = []
     for field, val in [("a", 1.5), ("nr", 6), ("ntheta", 1), ("weight_prec", 7), ("abi_version", 99),
-                       ("chart", 3), ("weno_eps", 0.0), ("M", -1.0), ("s", 3)]:
+                       ("chart", 3), ("weno_eps", 0.0), ("M", -1.0), ("s", 3), ("theta_order", 3),
+                       ("theta_order", 6)]:
         c = T.make_config(s=0, m=0, a=0.5, nr=512, ntheta=32, x_min=-64, x_max=64)
         setattr(c, field, val)
         bad.append(c)
@@ -170,6 +171,14 @@ def test_footprint_and_validation():
             T.teuk_host_coefficients(c)
         assert ei.value.status == T.TEUK_ERR_INVALID_ARG
         assert T.teuk_last_error(None)
+
+
+def test_theta_order_field():
+    d = T.teuk_default_config()
+    assert d.theta_order == 2
+    for order in (0, 2, 4):
+        c = T.make_config(s=-2, m=2, a=0.9, nr=512, ntheta=32, x_min=-64, x_max=64, theta_order=order)
+        assert T.teuk_footprint_bytes(c) > 0, order
 
 
 def test_capacity_error():

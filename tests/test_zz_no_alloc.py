@@ -23,14 +23,14 @@ def say(*a):
     print(*a, flush=True)
 
 
-def _case(nr, nth, s, m, a, wp, seed):
+def _case(nr, nth, s, m, a, wp, seed, order=2):
     wl = W.C2.with_(nr=nr, nth=nth, s=s, m=m, a=a, seed=seed, x_min=-100.0, x_max=200.0)
     probe = T.make_config(s=wl.s, m=wl.m, a=wl.a, nr=wl.nr, ntheta=wl.nth, x_min=wl.x_min, x_max=wl.x_max,
-                          weight_prec=wp)
+                          weight_prec=wp, theta_order=order)
     with T.Solver(probe) as sv:
         dt = sv.info().dt
     cfg = T.make_config(s=wl.s, m=wl.m, a=wl.a, nr=wl.nr, ntheta=wl.nth, x_min=wl.x_min, x_max=wl.x_max,
-                        weight_prec=wp, dt=dt)
+                        weight_prec=wp, dt=dt, theta_order=order)
     return wl, cfg
 
 
@@ -48,13 +48,13 @@ def _noalloc(cfg, u0, nsteps):
     return u.cpu().numpy()
 
 
-@pytest.mark.parametrize("wp", ["fp64", "fp32"])
-def test_noalloc_equals_teuk_step_two_calls_second_smaller(wp):
+@pytest.mark.parametrize("wp,order", [("fp64", 2), ("fp32", 2), ("fp64", 4)])
+def test_noalloc_equals_teuk_step_two_calls_second_smaller(wp, order):
     cases = [(1000, 96, -2, 2, 0.999, 11, 40), (300, 20, 0, 0, 0.5, 12, 25), (1000, 96, -2, 2, 0.999, 13, 10)]
     for nr, nth, s, m, a, seed, nsteps in cases:
-        wl, cfg = _case(nr, nth, s, m, a, wp, seed)
+        wl, cfg = _case(nr, nth, s, m, a, wp, seed, order)
         u0 = W.gaussian_pulse(wl)
-        say(f"noalloc {wp}: {nr}x{nth} s={s} m={m} a={a} seed={seed}, {nsteps} steps")
+        say(f"noalloc {wp} theta order {order}: {nr}x{nth} s={s} m={m} a={a} seed={seed}, {nsteps} steps")
         ref = _reference(cfg, u0, nsteps)
         got = _noalloc(cfg, u0, nsteps)
         assert np.all(np.isfinite(got))
