@@ -180,33 +180,58 @@ def bench_single(args, torch, T, W):
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
 
-    def run(wp, state="fp64", nsteps=None, nwarm=None, integrator="rk3", every=None, graph=0, theta_order=2):
-        """Warm up, then time `nsteps` steps with HIP events on the solver's
-        stream.  Returns (seconds, wall seconds, info, waveform samples)."""
-        nsteps = steps if nsteps is None else nsteps
-        nwarm = warmup if nwarm is None else nwarm
-        sv = T.Solver(solver_config(T, wl, wp, nwarm + nsteps, args.workgroups, state=state,
-                                    integrator=integrator, every=every, theta_order=theta_order), stream=stream)
+    def make(wp, total, state="fp64", integrator="rk3", every=None, theta_order=2):
+        """A solver of the workload with the initial data set (host work: tables,
+        bound, upload)."""
+        sv = T.Solver(solver_config(T, wl, wp, total, args.workgroups, state=state, integrator=integrator,
+                                    every=every, theta_order=theta_order), stream=stream)
         sv.set_initial(u0)
-        log(f"{state}/{wp}/{integrator}{' graph ' + str(graph) if graph else ''}: warmup {nwarm} steps")
+        return sv
+
+    def warm(sv, nwarm, graph=0, label=""):
+        """Queue the warmup steps on the stream (behind whatever it holds) and
+        capture the graph, if asked, at the sampling phase they leave (host
+        work, done while the GPU still runs what was queued before)."""
+        log(f"{label}{' graph ' + str(graph) if graph else ''}: warmup {nwarm} steps")
         sv.step(nwarm)
         if graph:
-            sv.set_graph(graph)          # captured here, at the current sampling phase (untimed)
+            sv.set_graph(graph)
+
+    def time_steps(sv, nsteps, label="", then=None):
+        """Synchronize, then time exactly `nsteps` steps of a warmed solver
+        with HIP events on the solver's stream, and synchronize.  `then`
+        queues the next run's warmup behind the timed steps (after the closing
+        event).  Returns (seconds, wall seconds)."""
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
-        log(f"{state}/{wp}/{integrator}: timing {nsteps} steps")
+        log(f"{label}: timing {nsteps} steps")
         w0 = time.perf_counter()
         ev0.record(stream)
         sv.step(nsteps)
         ev1.record(stream)
+        if then is not None:
+            then()
         torch.cuda.synchronize()
-        wall = time.perf_counter() - w0
-        sec = ev0.elapsed_time(ev1) / 1e3
+        return ev0.elapsed_time(ev1) / 1e3, time.perf_counter() - w0
+
+    def finish(sv):
+        """Guard, counters and waveform of a timed solver; releases it."""
         sv.check_finite()
         info = sv.info()
         _, wave = sv.waveform()
         sv.close()
+        return info, wave
+
+    def run(wp, state="fp64", nsteps=None, nwarm=None, integrator="rk3", every=None, graph=0, theta_order=2):
+        """make + time_steps + finish: (seconds, wall seconds, info, waveform samples)."""
+        nsteps = steps if nsteps is None else nsteps
+        nwarm = warmup if nwarm is None else nwarm
+        sv = make(wp, nwarm + nsteps, state, integrator, every, theta_order)
+        label = f"{state}/{wp}/{integrator}"
+        warm(sv, nwarm, graph, label)
+        sec, wall = time_steps(sv, nsteps, label)
+        info, wave = finish(sv)
         return sec, wall, info, wave
 
     # Launch shapes from the project's autotuner (it times stage-kernel
@@ -227,24 +252,88 @@ def bench_single(args, torch, T, W):
             tuned["rk3_theta4"] = {"workgroups": ti.workgroups, "segs_per_strip": ti.segs,
                                    "us_per_step": ti.us_per_step, "us_per_step_default": ti.us_per_step_default}
 
+    # Every timed solver of the headline and of the legs compared with it is
+    # created here, before any timing.  The GPU's clock drops within about
+    # 10 ms of idling and takes tens of milliseconds of load to recover
+    # (measured: 20 steps after 5 warmup steps take 96.5-99 us each when the
+    # GPU idled < 3 ms before the warmup, 105-113 us after 10 ms - 1 s), and
+    # creating a solver of this grid idles it for longer than that.  So the
+    # timed runs follow each other with no idle GPU between them: each run's
+    # warmup (and graph capture) is queued while the run before it is still
+    # on the GPU -- the headline's behind the last reduced-precision run --
+    # and short runs time the kernels at the clock of a long solve.
+    graph = args.graph if args.graph >= 0 else (50 if c1 else 10)
+    other = 0 if graph else (50 if c1 else 10)   # the other launch mode (a multiple of the 10-step cadence)
+    n4, w4 = max(steps // 6, 1), warmup // 6
+    hs = make(weights, warmup + steps)
+    # (name, solver, timed steps, warmup steps, graph chunk, label), timed in this order
+    chain = [("headline", hs, steps, warmup, graph, f"fp64/{weights}/rk3 (headline)")]
+    if not c1 and weights == "fp64" and not args.no_blocked:
+        chain.append(("blocked", make("fp64", warmup + steps, integrator="rk3_blocked"), steps, warmup, 0,
+                      "fp64/fp64/rk3_blocked"))
+    if not args.no_graph_leg:
+        chain.append(("graph", make(weights, warmup + steps), steps, warmup, other,
+                      f"fp64/{weights}/rk3 (other launch mode)"))
+    if not args.no_theta4:
+        chain.append(("theta4", make(weights, warmup + steps, theta_order=4), steps, warmup, graph,
+                      f"fp64/{weights}/rk3 theta order 4"))
+    if weights == "fp64" and not args.no_pipelined:
+        chain.append(("pipelined", make("fp64", warmup + steps, integrator="rk3_pipelined"), steps, warmup, 0,
+                      "fp64/fp64/rk3_pipelined"))
+    if not c1 and weights == "fp64" and not args.no_rk104:
+        chain.append(("rk104", make("fp64", n4 + w4, integrator="rk104", every=5), n4, w4, 0,
+                      "fp64/fp64/rk104"))
+
+    def warm_link(i):
+        _, sv, _, nw, g, label = chain[i]
+        warm(sv, nw, g, label)
+
     # Reduced-precision weights over the workload's full length (the waveform
     # at x_e needs the pulse to have passed it), before the headline timing:
     # speed and waveform error (relative L2 over every sample) against FP64.
+    # The last of these runs is left in flight with the headline's warmup
+    # queued behind it.
     mixed = None
+    tail = None
     if weights == "fp64" and not args.no_mixed:
         full = wl.steps if args.mixed_steps <= 0 else args.mixed_steps
         sec64f, _, _, wave64f = run("fp64", nsteps=full, nwarm=0)
         mixed = {"steps": full, "fp64": {"value": 3.0 * wl.points * full / sec64f, "seconds": sec64f}}
-        for wp in ("fp32", "fp16", "bf16"):
+        for wp in ("fp32", "fp16"):
             sec_w, _, _, wave_w = run(wp, nsteps=full, nwarm=0)
+            mixed[wp] = (sec_w, wave_w)
+        sv_t = make("bf16", full)
+        torch.cuda.synchronize()
+        log(f"fp64/bf16/rk3: timing {full} steps (the headline's warmup queued behind them)")
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        sv_t.step(full)
+        t1.record(stream)
+        tail = (sv_t, t0, t1)
+
+    # the chain: headline, then the legs compared with it
+    warm_link(0)
+    timed = {}
+    for i, (name, sv, nst, _, _, label) in enumerate(chain):
+        nxt = (lambda j=i + 1: warm_link(j)) if i + 1 < len(chain) else None
+        timed[name] = time_steps(sv, nst, label, then=nxt)
+    gpu_s, wall = timed["headline"]
+    if tail is not None:
+        sv_t, t0, t1 = tail
+        mixed["bf16"] = (t0.elapsed_time(t1) / 1e3, finish(sv_t)[1])
+        for wp in ("fp32", "fp16", "bf16"):
+            sec_w, wave_w = mixed[wp]
             mixed[wp] = {"value": 3.0 * wl.points * full / sec_w, "seconds": sec_w,
                          "speedup_vs_fp64": sec64f / sec_w,
                          "waveform_rel_l2_vs_fp64": float(np.linalg.norm(wave_w - wave64f) / np.linalg.norm(wave64f))}
         mixed["waveform"] = (f"{wave64f.shape[0]} samples x {wl.nth} rows at r* = {wl.x_e}, t = 0 .. "
                              f"{full} steps; the FP64 run is the parity-tested path")
+    info, wave = finish(hs)
+    results = {name: timed[name] + finish(sv) for name, sv, *_ in chain[1:]}
+    do_graph_leg, do_theta4 = "graph" in results, "theta4" in results
+    do_pipe, do_blocked, do_rk104 = "pipelined" in results, "blocked" in results, "rk104" in results
 
-    graph = args.graph if args.graph >= 0 else (50 if c1 else 10)
-    gpu_s, wall, info, wave = run(weights, graph=graph)
     pu = 3.0 * wl.points * steps
     # 3 stage launches per step; the sample kernel (one per 10 steps) is
     # included in the time and is < 0.5 % of it.
@@ -264,24 +353,22 @@ def bench_single(args, torch, T, W):
         out["autotuner"] = tuned
     if mixed is not None:
         out["mixed_precision"] = mixed
-    if not args.no_graph_leg:
-        # the same steps with the other launch mode (graph replay vs one launch per stage)
-        other = 0 if graph else (50 if c1 else 10)   # a multiple of the waveform cadence (10 steps)
-        sec_o, _, _, wave_o = run(weights, graph=other)
+    if do_graph_leg:
+        sec_o, _, _, wave_o = results["graph"]
         out["graph"] = {"chunk_steps": other, "ms_per_step": sec_o / steps * 1e3, "value": pu / sec_o,
                         "speedup_vs_headline": gpu_s / sec_o, "waveform_identical": bool(np.array_equal(wave_o, wave))}
-    if not args.no_theta4:
+    if do_theta4:
         # the same workload with fourth-order theta differences (two rows
         # ahead and behind; the same HBM traffic per point, a smaller dt)
-        sec4, _, info4, _ = run(weights, graph=graph, theta_order=4)
+        sec4, _, info4, _ = results["theta4"]
         out["theta4"] = {"steps": steps, "dt": info4.dt, "ms_per_step": sec4 / steps * 1e3, "value": pu / sec4,
                          "speed_vs_second_order": gpu_s / sec4,
                          "simulated_time_per_s_vs_second_order": (info4.dt / sec4) / (info.dt / gpu_s),
                          "hbm_frac": roofline(wl.points, sec4 / (3 * steps), None)["frac"]}
-    if weights == "fp64" and not args.no_pipelined:
+    if do_pipe:
         # the same steps in one cooperative launch per waveform interval (tiles
         # wait for their neighbours' previous stage only)
-        secp, _, infop, wavep = run("fp64", integrator="rk3_pipelined")
+        secp, _, infop, wavep = results["pipelined"]
         out["pipelined"] = {"steps": steps, "ms_per_step": secp / steps * 1e3, "value": pu / secp,
                             "speedup_vs_headline": gpu_s / secp, "workgroups": infop.workgroups,
                             "waveform_identical": bool(np.array_equal(wavep, wave)),
@@ -291,11 +378,11 @@ def bench_single(args, torch, T, W):
             log("cpu baseline (oracle)")
             out["cpu_baseline"] = cpu_baseline(wl, u0, args.cpu_seconds)
         return out
-    if weights == "fp64" and not args.no_blocked:
+    if do_blocked:
         # Temporal blocking: the same SSP-RK(3,3) step as one launch per step
         # (u(1), u(2) in LDS; 64 B of HBM traffic per point-step; "traffic" is
         # the measured bytes per step).
-        secb, _, infob, waveb = run("fp64", integrator="rk3_blocked")
+        secb, _, infob, waveb = results["blocked"]
         out["blocked"] = {
             "steps": steps, "ms_per_step": secb / steps * 1e3, "value": pu / secb, "unit": "point-updates/s",
             "speedup_vs_three_launch": gpu_s / secb, "tiles": infob.workgroups,
@@ -304,13 +391,12 @@ def bench_single(args, torch, T, W):
                     "frac": 64.0 * wl.points * steps / secb / 1e9 / HBM_PEAK_GBS,
                     "traffic": measured_traffic("fp64", "bytes_per_blocked_step")},
         }
-    if weights == "fp64" and not args.no_rk104:
+    if do_rk104:
         # SSP-RK(10,4) (Sec. 3.2) over the same simulated time: its default step
         # is 6x the SSP-RK(3,3) step (SSP coefficients 6 and 1), ten stages per
         # step.  Waveforms compared at common sample times (every 5th step of
         # SSP-RK(10,4) = every 30th of SSP-RK(3,3)).
-        n4, w4 = max(steps // 6, 1), warmup // 6
-        sec4, _, info4, wave4 = run("fp64", nsteps=n4, nwarm=w4, integrator="rk104", every=5)
+        sec4, _, info4, wave4 = results["rk104"]
         ref = wave[::3][: wave4.shape[0]]
         m = min(ref.shape[0], wave4.shape[0])
         stages = 10 * n4

@@ -852,6 +852,14 @@ static teuk_status capture_chunk(teuk_solver* h)
         h->gexec = nullptr;
         return hip_fail(h, e, "hipGraphInstantiate");
     }
+    // move the graph's launch resources to the device now, so that the first
+    // replay costs what later ones do
+    e = (int)hipGraphUpload(h->gexec, h->stream);
+    if (e) {
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+        return hip_fail(h, e, "hipGraphUpload");
+    }
     h->graph_phase = phase;
     return TEUK_OK;
 }
@@ -1327,6 +1335,12 @@ static teuk_status capture_block(teuk_group* g, size_t bi)
     if (e) {
         g->gexec[bi] = nullptr;
         return gfail(g, TEUK_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString((hipError_t)e));
+    }
+    e = (int)hipGraphUpload(g->gexec[bi], g->stream);   // first replay as cheap as later ones
+    if (e) {
+        (void)hipGraphExecDestroy(g->gexec[bi]);
+        g->gexec[bi] = nullptr;
+        return gfail(g, TEUK_ERR_DEVICE, std::string("hipGraphUpload: ") + hipGetErrorString((hipError_t)e));
     }
     g->gphase[bi] = phase;
     return TEUK_OK;

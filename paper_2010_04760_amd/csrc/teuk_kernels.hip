@@ -249,6 +249,17 @@ struct Weno<TEUK_W_FP16> : WenoLow<LowF16, true> {};
 template <>
 struct Weno<TEUK_W_BF16> : WenoLow<LowBF16, true> {};
 
+// x of lane l + 1 (lane 63 keeps its own), by a DPP wavefront shift: no LDS
+// round trip, unlike __shfl_down.  Used wherever a lane takes the interface
+// flux of the lane after it.
+__device__ __forceinline__ double next_lane(double x)
+{
+    int lo = __double2loint(x), hi = __double2hiint(x);
+    lo = __builtin_amdgcn_update_dpp(lo, lo, 0x130 /* wave_shl:1 */, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(hi, hi, 0x130 /* wave_shl:1 */, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Barrier that orders LDS only.  __syncthreads() is also a workgroup fence on
@@ -366,22 +377,19 @@ __device__ __forceinline__ double ld_async_c(unsigned voff, const double* sbase)
     }
 }
 
-// One radial strip [j0, j0 + 63) marched over the theta rows [k0, k1), upward
-// (dir = +1, from k0) or downward (dir = -1, from k1 - 1).  Rows are staged in
-// a two-row LDS ring: while row k is computed from LDS, the loads of row
-// k + 2 dir and of u^n at row k are already in flight and are consumed at the
-// end of the iteration, so each wave always has its next rows' memory traffic
-// overlapping its arithmetic.
-//
-// Chart T: the Phi rows move with speed +b (f^+ fluxes), the pi rows with -b
-// (f^- fluxes), and the coefficients are rebuilt from the radial and polar
-// tables.  Chart H: the ten coefficients of the point are read from the
-// per-point table, and each row takes the flux side of the sign of its own
-// speed at the point (speed >= 0: f^+, speed < 0: f^-); a wave whose lanes
-// disagree computes both sides and each lane differences its own.
-template <int WP, int kMode, int kChart>
-__device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][kRow], int strip, int k0, int k1,
-                                            int dir)
+// Hyperboloidal chart: one radial strip [j0, j0 + 63) marched over the theta
+// rows [k0, k1), upward (dir = +1, from k0) or downward (dir = -1, from
+// k1 - 1).  Rows are staged in a two-row LDS ring: while row k is computed
+// from LDS, the loads of row k + 2 dir and of u^n at row k are already in
+// flight and are consumed at the end of the iteration, so each wave always has
+// its next rows' memory traffic overlapping its arithmetic.  The ten
+// coefficients of the point are read from the per-point table, and each row
+// takes the flux side of the sign of its own speed at the point (speed >= 0:
+// f^+, speed < 0: f^-); a wave whose lanes disagree computes both sides and
+// each lane differences its own.
+template <int WP, int kMode>
+__device__ __forceinline__ void march_strip_h(const StageArgs& A, double (*s)[4][kRow], int strip, int k0, int k1,
+                                              int dir)
 {
     const int l = threadIdx.x;
     const int nr = A.nr, nth = A.nth;
@@ -398,16 +406,6 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
     const double* __restrict__ ukp[4] = {A.uk, A.uk + P, A.uk + 2 * P, A.uk + 3 * P};
     const double* unp[4] = {A.un, A.un + P, A.un + 2 * P, A.un + 3 * P};   // read where reads_un<kMode>()
     double* outp[4] = {A.out, A.out + P, A.out + 2 * P, A.out + 3 * P};
-
-    double rt[kNRT];
-    if constexpr (kChart == kChartT) {
-#pragma unroll
-        for (int i = 0; i < kNRT; ++i) rt[i] = ldb(A.rtab + (size_t)i * nr, oc);
-    }
-    // The polar table is read-only for the whole launch: reading it through the
-    // constant address space makes its (uniform) loads scalar.
-    const __attribute__((address_space(4))) double* tt =
-        (const __attribute__((address_space(4))) double*)A.ttab;
 
     const int n = k1 - k0;
     const int first = dir > 0 ? k0 : k1 - 1;
@@ -459,15 +457,6 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
         const int k = first + dir * i;
         const int b = i & 1;
         const size_t row = (size_t)k * nr;
-        double sn2 = 0.0, cs = 0.0, cot = 0.0, th = 0.0;
-        if constexpr (kChart == kChartT) {
-            // polar factors of the row: uniform, read before the vector loads are
-            // queued so that waiting for them never waits for the prefetch
-            sn2 = tt[kSn2 * nth + k];
-            cs = tt[kCs * nth + k];
-            cot = tt[kCot * nth + k];
-            th = tt[kTh * nth + k];
-        }
         // next rows' traffic, consumed at the end of this iteration
         const bool pre = i + 2 < nst;
         if (pre) load_row(k + 2 * dir);
@@ -479,33 +468,24 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
             n3 = ldb(unp[3] + row, oc);
         }
         double hc[kNCH];
-        if constexpr (kChart == kChartH) {
 #pragma unroll
-            for (int q = 0; q < kNCH; ++q) hc[q] = ldb(A.ctab + (size_t)q * P + row, oc);
-        }
+        for (int q = 0; q < kNCH; ++q) hc[q] = ldb(A.ctab + (size_t)q * P + row, oc);
         lds_sync();
 
-        double dPhR = 0.0, dPhI = 0.0, dPiR = 0.0, dPiI = 0.0;
-        double fR = 0.0, fI = 0.0, gR = 0.0, gI = 0.0, fR1 = 0.0, fI1 = 0.0, gR1 = 0.0, gI1 = 0.0;
-        if constexpr (kChart == kChartT) {
-            // differenced below, inside the active-lane branch
-            fR = Weno<WP>::flux6(s[b][0][l], s[b][0][l + 1], s[b][0][l + 2], s[b][0][l + 3], s[b][0][l + 4], A.eps);
-            fI = Weno<WP>::flux6(s[b][1][l], s[b][1][l + 1], s[b][1][l + 2], s[b][1][l + 3], s[b][1][l + 4], A.eps);
-            gR = Weno<WP>::flux6(s[b][2][l + 5], s[b][2][l + 4], s[b][2][l + 3], s[b][2][l + 2], s[b][2][l + 1], A.eps);
-            gI = Weno<WP>::flux6(s[b][3][l + 5], s[b][3][l + 4], s[b][3][l + 3], s[b][3][l + 2], s[b][3][l + 1], A.eps);
-        } else {
+        double dPhR, dPhI, dPiR, dPiI;
+        {
             // upwind side per lane and row: speed >= 0 -> f^+, speed < 0 -> f^-
             const bool up1 = hc[kHLam1] >= 0.0, up2 = hc[kHLam2] >= 0.0;
             auto deriv = [&](int p, bool up, bool any_up, bool any_dn) {
                 double fp = 0.0, fm = 0.0, d = 0.0;
                 if (any_up) {
                     fp = Weno<WP>::flux6(s[b][p][l], s[b][p][l + 1], s[b][p][l + 2], s[b][p][l + 3], s[b][p][l + 4], A.eps);
-                    const double dp = __shfl_down(fp, 1) - fp;
+                    const double dp = next_lane(fp) - fp;
                     if (up) d = dp;
                 }
                 if (any_dn) {
                     fm = Weno<WP>::flux6(s[b][p][l + 5], s[b][p][l + 4], s[b][p][l + 3], s[b][p][l + 2], s[b][p][l + 1], A.eps);
-                    const double dm = __shfl_down(fm, 1) - fm;
+                    const double dm = next_lane(fm) - fm;
                     if (!up) d = dm;
                 }
                 return d * A.inv6dx;
@@ -527,27 +507,11 @@ __device__ __forceinline__ void march_strip(const StageArgs& A, double (*s)[4][k
             ahR = A.parity * phR;
             ahI = A.parity * phI;
         }
-        if constexpr (kChart == kChartT) {
-            fR1 = __shfl_down(fR, 1);
-            fI1 = __shfl_down(fI, 1);
-            gR1 = __shfl_down(gR, 1);
-            gI1 = __shfl_down(gI, 1);
-        }
 
         if (active) {
-            double lam1, lam2n, m3r, m3i, btr, bti, cr, ci, ath, bth;   // lam2n = -lam2
-            if constexpr (kChart == kChartT) {
-                dPhR = (fR1 - fR) * A.inv6dx;
-                dPhI = (fI1 - fI) * A.inv6dx;
-                dPiR = (gR1 - gR) * A.inv6dx;
-                dPiI = (gI1 - gI) * A.inv6dx;
-                const PointCoef c = point_coef(rt, sn2, cs, cot, th, rsq64(sigma2(rt, sn2)));
-                lam1 = c.b; lam2n = c.b; m3r = c.m3r; m3i = c.m3i; btr = c.btr; bti = c.bti;
-                cr = c.cr; ci = c.ci; ath = c.ath; bth = c.bth;
-            } else {
-                lam1 = hc[kHLam1]; lam2n = -hc[kHLam2]; m3r = hc[kHM3r]; m3i = hc[kHM3i];
-                btr = hc[kHBtr]; bti = hc[kHBti]; cr = hc[kHCr]; ci = hc[kHCi]; ath = hc[kHAth]; bth = hc[kHBth];
-            }
+            const double lam1 = hc[kHLam1], lam2n = -hc[kHLam2], m3r = hc[kHM3r], m3i = hc[kHM3i];
+            const double btr = hc[kHBtr], bti = hc[kHBti], cr = hc[kHCr], ci = hc[kHCi];
+            const double ath = hc[kHAth], bth = hc[kHBth];
 
             // rows k+1 and k-1
             const double upR = dir > 0 ? ahR : bhR, upI = dir > 0 ? ahI : bhI;
@@ -720,6 +684,11 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
             n2 = ld_async_c<kCoh>(oc, unp[2] + row);
             n3 = ld_async_c<kCoh>(oc, unp[3] + row);
         }
+        // 1/Sigma of the point: its dependent chain (reciprocal square root and
+        // two Newton steps) is started here, where it overlaps the row's loads
+        // (the empty asm keeps the compiler from sinking it to its use)
+        const double vsig = rsq64(sigma2(rt, sn2));
+        asm volatile("" : : "v"(vsig));
         issue_row(i + 3);
         constexpr int it = reads_un<kMode>() ? 16 : 12;
         if constexpr (kTh4) vm_wait<it>();
@@ -755,10 +724,10 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
                 ah2I = A.parity * bhI;
             }
         }
-        const double fR1 = __shfl_down(fR, 1);
-        const double fI1 = __shfl_down(fI, 1);
-        const double gR1 = __shfl_down(gR, 1);
-        const double gI1 = __shfl_down(gI, 1);
+        const double fR1 = next_lane(fR);
+        const double fI1 = next_lane(fI);
+        const double gR1 = next_lane(gR);
+        const double gI1 = next_lane(gI);
 
         if (reads_un<kMode>()) vm_wait<12>(n0, n1, n2, n3);
         if (active) {
@@ -766,7 +735,7 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
             const double dPhI = (fI1 - fI) * A.inv6dx;
             const double dPiR = (gR1 - gR) * A.inv6dx;
             const double dPiI = (gI1 - gI) * A.inv6dx;
-            const PointCoef c = point_coef(rt, sn2, cs, cot, th, rsq64(sigma2(rt, sn2)));
+            const PointCoef c = point_coef(rt, sn2, cs, cot, th, vsig);
             const double upR = dir > 0 ? ahR : bhR, upI = dir > 0 ? ahI : bhI;
             const double dnR = dir > 0 ? bhR : ahR, dnI = dir > 0 ? bhI : ahI;
             double d1R, d1I, d2R, d2I;
@@ -846,7 +815,7 @@ __device__ __forceinline__ void march(const StageArgs& A, char* lds, int strip, 
     if constexpr (kChart == kChartT || kChart == kChartT4)
         march_strip_t<WP, kMode, kLevel, kCoh, kChart == kChartT4>(A, lds, strip, k0, k1, dir);
     else
-        march_strip<WP, kMode, kChart>(A, reinterpret_cast<double (*)[4][kRow]>(lds), strip, k0, k1, dir);
+        march_strip_h<WP, kMode>(A, reinterpret_cast<double (*)[4][kRow]>(lds), strip, k0, k1, dir);
 }
 
 template <int WP, int kMode, int kChart>
@@ -1105,8 +1074,8 @@ __global__ __launch_bounds__(kBThreads) void blocked_step_kernel(StageArgs A)
         const double fI = Weno<WP>::flux6(w[1][0], w[1][1], w[1][2], w[1][3], w[1][4], A.eps);
         const double gR = Weno<WP>::flux6(w[2][5], w[2][4], w[2][3], w[2][2], w[2][1], A.eps);
         const double gI = Weno<WP>::flux6(w[3][5], w[3][4], w[3][3], w[3][2], w[3][1], A.eps);
-        const double fR1 = __shfl_down(fR, 1), fI1 = __shfl_down(fI, 1);
-        const double gR1 = __shfl_down(gR, 1), gI1 = __shfl_down(gI, 1);
+        const double fR1 = next_lane(fR), fI1 = next_lane(fI);
+        const double gR1 = next_lane(gR), gI1 = next_lane(gI);
         const double sn2 = tt[kSn2 * nth + k], cs = tt[kCs * nth + k];
         const double cot = tt[kCot * nth + k], th = tt[kTh * nth + k];
         const double phR = w[0][3], phI = w[1][3], piR = w[2][3], piI = w[3][3];
