@@ -188,20 +188,26 @@ def bench_single(args, torch, T, W):
         sv.set_initial(u0)
         return sv
 
-    def warm(sv, nwarm, graph=0, label=""):
-        """Queue the warmup steps on the stream (behind whatever it holds) and
-        capture the graph, if asked, at the sampling phase they leave (host
-        work, done while the GPU still runs what was queued before)."""
-        log(f"{label}{' graph ' + str(graph) if graph else ''}: warmup {nwarm} steps")
+    def warm(sv, nwarm, label=""):
+        """Queue the warmup steps on the stream (behind whatever it holds)."""
+        log(f"{label}: warmup {nwarm} steps")
         sv.step(nwarm)
+
+    def capture(sv, graph, label=""):
+        """Capture the solver's graph at the sampling phase its warmup leaves."""
         if graph:
+            log(f"{label}: graph capture of {graph} steps")
             sv.set_graph(graph)
 
-    def time_steps(sv, nsteps, label="", then=None):
+    def time_steps(sv, nsteps, label="", before=None, after=None):
         """Synchronize, then time exactly `nsteps` steps of a warmed solver
-        with HIP events on the solver's stream, and synchronize.  `then`
-        queues the next run's warmup behind the timed steps (after the closing
-        event).  Returns (seconds, wall seconds)."""
+        with HIP events on the solver's stream, and synchronize.  `before`
+        runs after the timed launches are queued and before the closing
+        synchronization (the next run's plain warmup launches, so that the
+        GPU does not idle between runs); `after` runs after it (host work that
+        would slow timed launches still being fed to the GPU on a
+        launch-bound grid: graph captures, cooperative launches).  Returns
+        (seconds, wall seconds)."""
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
@@ -210,10 +216,13 @@ def bench_single(args, torch, T, W):
         ev0.record(stream)
         sv.step(nsteps)
         ev1.record(stream)
-        if then is not None:
-            then()
+        if before is not None:
+            before()
         torch.cuda.synchronize()
-        return ev0.elapsed_time(ev1) / 1e3, time.perf_counter() - w0
+        wall = time.perf_counter() - w0
+        if after is not None:
+            after()
+        return ev0.elapsed_time(ev1) / 1e3, wall
 
     def finish(sv):
         """Guard, counters and waveform of a timed solver; releases it."""
@@ -229,7 +238,8 @@ def bench_single(args, torch, T, W):
         nwarm = warmup if nwarm is None else nwarm
         sv = make(wp, nwarm + nsteps, state, integrator, every, theta_order)
         label = f"{state}/{wp}/{integrator}"
-        warm(sv, nwarm, graph, label)
+        warm(sv, nwarm, label)
+        capture(sv, graph, label)
         sec, wall = time_steps(sv, nsteps, label)
         info, wave = finish(sv)
         return sec, wall, info, wave
@@ -258,41 +268,51 @@ def bench_single(args, torch, T, W):
     # (measured: 20 steps after 5 warmup steps take 96.5-99 us each when the
     # GPU idled < 3 ms before the warmup, 105-113 us after 10 ms - 1 s), and
     # creating a solver of this grid idles it for longer than that.  So the
-    # timed runs follow each other with no idle GPU between them: each run's
-    # warmup (and graph capture) is queued while the run before it is still
-    # on the GPU -- the headline's behind the last reduced-precision run --
-    # and short runs time the kernels at the clock of a long solve.
+    # timed runs follow each other with the GPU kept busy: each run's warmup
+    # steps are queued behind the run before it -- the headline's behind the
+    # last reduced-precision run -- and short runs time the kernels at the
+    # clock of a long solve.
     graph = args.graph if args.graph >= 0 else (50 if c1 else 10)
     other = 0 if graph else (50 if c1 else 10)   # the other launch mode (a multiple of the 10-step cadence)
-    n4, w4 = max(steps // 6, 1), warmup // 6
+    # The legs compared with the headline time at least 500 C2 steps (about
+    # 50 ms), whatever K is: over 20 steps their times scatter by 10-15 %.
+    lsteps = steps if c1 else max(steps, 500)
+    n4, w4 = max(lsteps // 6, 1), warmup // 6
     hs = make(weights, warmup + steps)
     # (name, solver, timed steps, warmup steps, graph chunk, label), timed in this order
     chain = [("headline", hs, steps, warmup, graph, f"fp64/{weights}/rk3 (headline)")]
     if not c1 and weights == "fp64" and not args.no_blocked:
-        chain.append(("blocked", make("fp64", warmup + steps, integrator="rk3_blocked"), steps, warmup, 0,
+        chain.append(("blocked", make("fp64", warmup + lsteps, integrator="rk3_blocked"), lsteps, warmup, 0,
                       "fp64/fp64/rk3_blocked"))
     if not args.no_graph_leg:
-        chain.append(("graph", make(weights, warmup + steps), steps, warmup, other,
+        chain.append(("graph", make(weights, warmup + lsteps), lsteps, warmup, other,
                       f"fp64/{weights}/rk3 (other launch mode)"))
     if not args.no_theta4:
-        chain.append(("theta4", make(weights, warmup + steps, theta_order=4), steps, warmup, graph,
+        chain.append(("theta4", make(weights, warmup + lsteps, theta_order=4), lsteps, warmup, graph,
                       f"fp64/{weights}/rk3 theta order 4"))
     if weights == "fp64" and not args.no_pipelined:
-        chain.append(("pipelined", make("fp64", warmup + steps, integrator="rk3_pipelined"), steps, warmup, 0,
+        chain.append(("pipelined", make("fp64", warmup + lsteps, integrator="rk3_pipelined"), lsteps, warmup, 0,
                       "fp64/fp64/rk3_pipelined"))
     if not c1 and weights == "fp64" and not args.no_rk104:
         chain.append(("rk104", make("fp64", n4 + w4, integrator="rk104", every=5), n4, w4, 0,
                       "fp64/fp64/rk104"))
 
-    def warm_link(i):
-        _, sv, _, nw, g, label = chain[i]
-        warm(sv, nw, g, label)
+    def link(i):
+        """(before, after) callables that warm up chain[i] behind the run before
+        it: plain warmup launches before that run's closing synchronization,
+        a cooperative (pipelined) warmup and the graph capture after it."""
+        if i >= len(chain):
+            return None, None
+        name, sv, _, nw, g, label = chain[i]
+        if name == "pipelined":
+            return None, lambda: warm(sv, nw, label)
+        return (lambda: warm(sv, nw, label)), (lambda: capture(sv, g, label))
 
     # Reduced-precision weights over the workload's full length (the waveform
     # at x_e needs the pulse to have passed it), before the headline timing:
     # speed and waveform error (relative L2 over every sample) against FP64.
-    # The last of these runs is left in flight with the headline's warmup
-    # queued behind it.
+    # The headline's warmup follows the last of these runs directly (its
+    # solver is finished afterwards).
     mixed = None
     tail = None
     if weights == "fp64" and not args.no_mixed:
@@ -303,25 +323,23 @@ def bench_single(args, torch, T, W):
             sec_w, _, _, wave_w = run(wp, nsteps=full, nwarm=0)
             mixed[wp] = (sec_w, wave_w)
         sv_t = make("bf16", full)
-        torch.cuda.synchronize()
-        log(f"fp64/bf16/rk3: timing {full} steps (the headline's warmup queued behind them)")
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        t0.record(stream)
-        sv_t.step(full)
-        t1.record(stream)
-        tail = (sv_t, t0, t1)
+        b0, a0 = link(0)
+        tail = (sv_t, time_steps(sv_t, full, "fp64/bf16/rk3", before=b0, after=a0)[0])
+    else:
+        b0, a0 = link(0)
+        for f in (b0, a0):
+            if f is not None:
+                f()
 
     # the chain: headline, then the legs compared with it
-    warm_link(0)
     timed = {}
     for i, (name, sv, nst, _, _, label) in enumerate(chain):
-        nxt = (lambda j=i + 1: warm_link(j)) if i + 1 < len(chain) else None
-        timed[name] = time_steps(sv, nst, label, then=nxt)
+        b, a = link(i + 1)
+        timed[name] = time_steps(sv, nst, label, before=b, after=a)
     gpu_s, wall = timed["headline"]
     if tail is not None:
-        sv_t, t0, t1 = tail
-        mixed["bf16"] = (t0.elapsed_time(t1) / 1e3, finish(sv_t)[1])
+        sv_t, sec_t = tail
+        mixed["bf16"] = (sec_t, finish(sv_t)[1])
         for wp in ("fp32", "fp16", "bf16"):
             sec_w, wave_w = mixed[wp]
             mixed[wp] = {"value": 3.0 * wl.points * full / sec_w, "seconds": sec_w,
@@ -353,25 +371,37 @@ def bench_single(args, torch, T, W):
         out["autotuner"] = tuned
     if mixed is not None:
         out["mixed_precision"] = mixed
+    t_step = gpu_s / steps                   # headline seconds per step
+    lpu = 3.0 * wl.points * lsteps           # point-updates of a leg
+
+    def same_prefix(a, b):
+        # the runs start from the same state with the same dt: their common
+        # samples must agree
+        m = min(a.shape[0], b.shape[0])
+        return a[:m], b[:m]
+
     if do_graph_leg:
         sec_o, _, _, wave_o = results["graph"]
-        out["graph"] = {"chunk_steps": other, "ms_per_step": sec_o / steps * 1e3, "value": pu / sec_o,
-                        "speedup_vs_headline": gpu_s / sec_o, "waveform_identical": bool(np.array_equal(wave_o, wave))}
+        wo, wh = same_prefix(wave_o, wave)
+        out["graph"] = {"chunk_steps": other, "steps": lsteps, "ms_per_step": sec_o / lsteps * 1e3,
+                        "value": lpu / sec_o, "speedup_vs_headline": t_step / (sec_o / lsteps),
+                        "waveform_identical": bool(np.array_equal(wo, wh))}
     if do_theta4:
         # the same workload with fourth-order theta differences (two rows
         # ahead and behind; the same HBM traffic per point, a smaller dt)
         sec4, _, info4, _ = results["theta4"]
-        out["theta4"] = {"steps": steps, "dt": info4.dt, "ms_per_step": sec4 / steps * 1e3, "value": pu / sec4,
-                         "speed_vs_second_order": gpu_s / sec4,
-                         "simulated_time_per_s_vs_second_order": (info4.dt / sec4) / (info.dt / gpu_s),
-                         "hbm_frac": roofline(wl.points, sec4 / (3 * steps), None)["frac"]}
+        out["theta4"] = {"steps": lsteps, "dt": info4.dt, "ms_per_step": sec4 / lsteps * 1e3, "value": lpu / sec4,
+                         "speed_vs_second_order": t_step / (sec4 / lsteps),
+                         "simulated_time_per_s_vs_second_order": (info4.dt * lsteps / sec4) / (info.dt / t_step),
+                         "hbm_frac": roofline(wl.points, sec4 / (3 * lsteps), None)["frac"]}
     if do_pipe:
         # the same steps in one cooperative launch per waveform interval (tiles
         # wait for their neighbours' previous stage only)
         secp, _, infop, wavep = results["pipelined"]
-        out["pipelined"] = {"steps": steps, "ms_per_step": secp / steps * 1e3, "value": pu / secp,
-                            "speedup_vs_headline": gpu_s / secp, "workgroups": infop.workgroups,
-                            "waveform_identical": bool(np.array_equal(wavep, wave)),
+        wp_, wh = same_prefix(wavep, wave)
+        out["pipelined"] = {"steps": lsteps, "ms_per_step": secp / lsteps * 1e3, "value": lpu / secp,
+                            "speedup_vs_headline": t_step / (secp / lsteps), "workgroups": infop.workgroups,
+                            "waveform_identical": bool(np.array_equal(wp_, wh)),
                             "launches": "one per waveform interval (every %d steps)" % wl.every}
     if c1:
         if not args.no_cpu_baseline:
@@ -383,12 +413,13 @@ def bench_single(args, torch, T, W):
         # (u(1), u(2) in LDS; 64 B of HBM traffic per point-step; "traffic" is
         # the measured bytes per step).
         secb, _, infob, waveb = results["blocked"]
+        wb, wh = same_prefix(waveb, wave)
         out["blocked"] = {
-            "steps": steps, "ms_per_step": secb / steps * 1e3, "value": pu / secb, "unit": "point-updates/s",
-            "speedup_vs_three_launch": gpu_s / secb, "tiles": infob.workgroups,
-            "waveform_rel_diff_vs_three_launch": float(np.max(np.abs(waveb - wave)) / np.max(np.abs(wave))),
-            "hbm": {"bytes_per_point_step": 64, "achieved_GBs": 64.0 * wl.points * steps / secb / 1e9,
-                    "frac": 64.0 * wl.points * steps / secb / 1e9 / HBM_PEAK_GBS,
+            "steps": lsteps, "ms_per_step": secb / lsteps * 1e3, "value": lpu / secb, "unit": "point-updates/s",
+            "speedup_vs_three_launch": t_step / (secb / lsteps), "tiles": infob.workgroups,
+            "waveform_rel_diff_vs_three_launch": float(np.max(np.abs(wb - wh)) / max(np.max(np.abs(wh)), 1e-300)),
+            "hbm": {"bytes_per_point_step": 64, "achieved_GBs": 64.0 * wl.points * lsteps / secb / 1e9,
+                    "frac": 64.0 * wl.points * lsteps / secb / 1e9 / HBM_PEAK_GBS,
                     "traffic": measured_traffic("fp64", "bytes_per_blocked_step")},
         }
     if do_rk104:
@@ -404,7 +435,7 @@ def bench_single(args, torch, T, W):
         out["rk104"] = {
             "steps": n4, "warmup": w4, "dt": info4.dt, "ms_per_step": sec4 / n4 * 1e3,
             "value": wl.points * stages / sec4, "unit": "point-updates/s",
-            "simulated_time_per_s_vs_rk3": (n4 * info4.dt / sec4) / (steps * info.dt / gpu_s),
+            "simulated_time_per_s_vs_rk3": (n4 * info4.dt / sec4) / (info.dt / t_step),
             "waveform_rel_l2_vs_rk3": float(np.linalg.norm(wave4[:m] - ref[:m]) / np.linalg.norm(ref[:m])),
             "hbm": {"bytes_per_point_step": RK104_BYTES_PER_POINT_STEP,
                     "achieved_GBs": RK104_BYTES_PER_POINT_STEP * wl.points * n4 / sec4 / 1e9,
