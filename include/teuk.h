@@ -347,11 +347,12 @@ teuk_status teuk_host_coefficients(const teuk_config* cfg, double* out, size_t c
  * segments that its workgroups march), with segs derived from a workgroup
  * budget: cfg->workgroups, or by default the number of stage workgroups the
  * GPU holds at once.  teuk_tune times the stage kernels of cfg for a set of
- * budgets from 1/4 to 4 times that default (one per distinct segs), each the
+ * budgets from 1/4 to 4 times that default and those giving segments of 2, 4
+ * and 8 rows (one per distinct segs), each the
  * best of three runs of `steps` steps (0: chosen to take about 2 ms) on a
  * scratch solver of the same grid, chart, precisions and integrator with a
- * smooth synthetic state of order one, and remembers the fastest budget for that launch class (device, chart,
- * weight and state precision, integrator, scheme, nr, ntheta) for the rest of
+ * smooth synthetic state of order one, and remembers the fastest budget for that launch class (device, chart
+ * and theta order, weight and state precision, integrator, scheme, nr, ntheta) for the rest of
  * the process: a later teuk_create of that class with workgroups = 0 uses it
  * (teuk_info reports the workgroups in use).  The tiling does not change any
  * point's arithmetic, so results are bitwise independent of the choice.  The

@@ -137,12 +137,18 @@ teuk_status teuk_tune(const teuk_config* cfg, int32_t steps, teuk_tune_info_t* o
     const long long resident = blocked ? teuk::blocked_grid() : teuk::stage_grid(cfg->weight_prec, false, teuk::kernel_chart(*cfg));
     if (resident <= 0) return tfail(TEUK_ERR_UNSUPPORTED, "occupancy query failed");
 
-    // candidate budgets around the resident count, one per distinct segment count
+    // candidate budgets around the resident count, one per distinct segment
+    // count, and on grids too small to fill the GPU (where every budget near
+    // the resident count gives one segment per row) longer segments of 2, 4
+    // and 8 rows
     const double mult[] = {0.25, 0.375, 0.5, 0.625, 0.75, 0.875, 1.0, 1.25, 1.5, 2.0, 3.0, 4.0};
+    std::vector<long long> raw;
+    for (double f : mult) raw.push_back(std::max(1LL, (long long)(f * (double)resident)));
+    for (int rows : {2, 4, 8})
+        if (cfg->ntheta >= 2 * rows) raw.push_back((long long)nstrips * (cfg->ntheta / rows));
     std::vector<int> budgets;
     std::vector<int> seen;
-    for (double f : mult) {
-        const long long b = std::max(1LL, (long long)(f * (double)resident));
+    for (long long b : raw) {
         const int s = segs_for(b, nstrips, cfg->ntheta, !blocked);
         if (std::find(seen.begin(), seen.end(), s) != seen.end()) continue;
         seen.push_back(s);
