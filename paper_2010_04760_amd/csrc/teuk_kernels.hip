@@ -684,11 +684,14 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
             n2 = ld_async_c<kCoh>(oc, unp[2] + row);
             n3 = ld_async_c<kCoh>(oc, unp[3] + row);
         }
-        // 1/Sigma of the point: its dependent chain (reciprocal square root and
-        // two Newton steps) is started here, where it overlaps the row's loads
-        // (the empty asm keeps the compiler from sinking it to its use)
+        // 1/Sigma of the point.  In the single-solve launch its dependent chain
+        // (reciprocal square root and two Newton steps) is started here, where
+        // it overlaps the row's loads (the empty asm keeps the compiler from
+        // sinking it to its use); the batched launch, whose tiles start as
+        // slots free up, measured 0.7 % slower on C4 with that, and leaves the
+        // placement to the compiler.
         const double vsig = rsq64(sigma2(rt, sn2));
-        asm volatile("" : : "v"(vsig));
+        if constexpr (kLevel) asm volatile("" : : "v"(vsig));
         issue_row(i + 3);
         constexpr int it = reads_un<kMode>() ? 16 : 12;
         if constexpr (kTh4) vm_wait<it>();
@@ -724,10 +727,13 @@ __device__ __forceinline__ void march_strip_t(const StageArgs& A, char* ring, in
                 ah2I = A.parity * bhI;
             }
         }
-        const double fR1 = next_lane(fR);
-        const double fI1 = next_lane(fI);
-        const double gR1 = next_lane(gR);
-        const double gI1 = next_lane(gI);
+        // the interface flux of the next lane: by DPP in the single-solve
+        // launch; the batched launch measured 1.2 % slower on C4 with the DPP
+        // moves (VALU work) than with ds_bpermute (LDS work)
+        const double fR1 = kLevel ? next_lane(fR) : __shfl_down(fR, 1);
+        const double fI1 = kLevel ? next_lane(fI) : __shfl_down(fI, 1);
+        const double gR1 = kLevel ? next_lane(gR) : __shfl_down(gR, 1);
+        const double gI1 = kLevel ? next_lane(gI) : __shfl_down(gI, 1);
 
         if (reads_un<kMode>()) vm_wait<12>(n0, n1, n2, n3);
         if (active) {
