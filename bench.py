@@ -272,7 +272,11 @@ def bench_single(args, torch, T, W):
     # steps are queued behind the run before it -- the headline's behind the
     # last reduced-precision run -- and short runs time the kernels at the
     # clock of a long solve.
-    graph = args.graph if args.graph >= 0 else (50 if c1 else 10)
+    # Headline launch mode: graph replay where launches bound the step (C1,
+    # 11 us per step), one launch per stage where kernels do (C2: replaying a
+    # 10-step graph measured 0.5 % slower than launching); the graph leg
+    # reports the other mode.
+    graph = args.graph if args.graph >= 0 else (50 if c1 else 0)
     other = 0 if graph else (50 if c1 else 10)   # the other launch mode (a multiple of the 10-step cadence)
     # The legs compared with the headline time at least 500 C2 steps (about
     # 50 ms), whatever K is: over 20 steps their times scatter by 10-15 %.
@@ -835,7 +839,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="C1/C2: skip the launch-shape autotuner")
     ap.add_argument("--graph", type=int, default=-1,
                     help="C1/C2/C4/C5: steps per captured HIP graph of the headline run (0: one launch per "
-                         "stage; default: 50 for C1, 10 for C2, 0 for C4/C5)")
+                         "stage; default: 50 for C1, 0 for C2, C4 and C5)")
     ap.add_argument("--no-graph-leg", action="store_true",
                     help="C1/C2/C4: skip the run in the other launch mode (graph vs launch by launch)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/FP16/BF16-weight runs")
