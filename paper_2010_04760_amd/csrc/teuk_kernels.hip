@@ -1005,7 +1005,10 @@ __global__ __launch_bounds__(kWave) void pipe_kernel(PipeArgs P)
 // computes u(1) at row r, u(2) at row r-1 and u^{n+1} at row r-2.  Radial
 // ghosts of u(1) and u(2) are the end values, read by clamping the point index
 // to the points inside the grid.  The arithmetic of each point and stage is
-// the three-launch stage kernel's, term for term.
+// the three-launch stage kernel's, term for term, except that the per-point
+// coefficients of a row are built once, by stage 1, and reused by stages 2
+// and 3 when the march reaches that row for them (a lane keeps its radial
+// point through all three stages).
 constexpr int kBW = 114;                 // output points per tile
 constexpr int kBLead = 6;                // first output point of a tile
 constexpr int kBThreads = 2 * kWave;     // two waves
@@ -1074,22 +1077,19 @@ __global__ __launch_bounds__(kBThreads) void blocked_step_kernel(StageArgs A)
     // one stage at one row for this lane: w[p][t] = input of plane p at j - 3 + t,
     // dn / up = input Phi at the own point on rows k - 1 / k + 1
     struct Out { double v[4]; };
-    auto stage = [&](const double (&w)[4][6], double dnR, double dnI, double upR, double upI, int k, double ca,
-                     double cb, const double (&un)[4], bool first) {
+    auto stage = [&](const double (&w)[4][6], double dnR, double dnI, double upR, double upI, const PointCoef& c,
+                     double ca, double cb, const double (&un)[4], bool first) {
         const double fR = Weno<WP>::flux6(w[0][0], w[0][1], w[0][2], w[0][3], w[0][4], A.eps);
         const double fI = Weno<WP>::flux6(w[1][0], w[1][1], w[1][2], w[1][3], w[1][4], A.eps);
         const double gR = Weno<WP>::flux6(w[2][5], w[2][4], w[2][3], w[2][2], w[2][1], A.eps);
         const double gI = Weno<WP>::flux6(w[3][5], w[3][4], w[3][3], w[3][2], w[3][1], A.eps);
         const double fR1 = next_lane(fR), fI1 = next_lane(fI);
         const double gR1 = next_lane(gR), gI1 = next_lane(gI);
-        const double sn2 = tt[kSn2 * nth + k], cs = tt[kCs * nth + k];
-        const double cot = tt[kCot * nth + k], th = tt[kTh * nth + k];
         const double phR = w[0][3], phI = w[1][3], piR = w[2][3], piI = w[3][3];
         const double dPhR = (fR1 - fR) * A.inv6dx;
         const double dPhI = (fI1 - fI) * A.inv6dx;
         const double dPiR = (gR1 - gR) * A.inv6dx;
         const double dPiI = (gI1 - gI) * A.inv6dx;
-        const PointCoef c = point_coef(rt, sn2, cs, cot, th, rsq64(sigma2(rt, sn2)));
         const double d1R = (upR - dnR) * A.ih1, d1I = (upI - dnI) * A.ih1;
         const double d2R = (upR - 2.0 * phR + dnR) * A.ih2;
         const double d2I = (upI - 2.0 * phI + dnI) * A.ih2;
@@ -1120,6 +1120,10 @@ __global__ __launch_bounds__(kBThreads) void blocked_step_kernel(StageArgs A)
     double nbR = 0, nbI = 0;                 // u^n Phi on row r - 1
     double a2R = 0, a2I = 0, a1R = 0, a1I = 0, a0R = 0, a0I = 0;   // u(1) Phi on r-2, r-1, r
     double c3R = 0, c3I = 0, c2R = 0, c2I = 0, c1R = 0, c1I = 0;   // u(2) Phi on r-3, r-2, r-1
+    // per-point coefficients of rows r, r - 1, r - 2, built by stage 1 and
+    // reused by stages 2 and 3 (the same point and row one and two steps of
+    // the march later)
+    PointCoef pc0{}, pc1{}, pc2{};
     {
         const int kb = r1lo - 1;
         if (kb >= 0) {
@@ -1178,7 +1182,12 @@ __global__ __launch_bounds__(kBThreads) void blocked_step_kernel(StageArgs A)
                 upI = A.parity * w[1][3];
             }
             const double none[4] = {0, 0, 0, 0};
-            const Out o = stage(w, nbR, nbI, upR, upI, r, 0.0, 1.0, none, true);
+            const double sn2 = tt[kSn2 * nth + r], cs = tt[kCs * nth + r];
+            const double cot = tt[kCot * nth + r], th = tt[kTh * nth + r];
+            pc2 = pc1;
+            pc1 = pc0;
+            pc0 = point_coef(rt, sn2, cs, cot, th, rsq64(sigma2(rt, sn2)));
+            const Out o = stage(w, nbR, nbI, upR, upI, pc0, 0.0, 1.0, none, true);
             if (!dup) {
 #pragma unroll
                 for (int p = 0; p < 4; ++p) s1[b][p][l] = o.v[p];
@@ -1195,6 +1204,8 @@ __global__ __launch_bounds__(kBThreads) void blocked_step_kernel(StageArgs A)
             un2[0] = un1[0]; un2[1] = un1[1]; un2[2] = un1[2]; un2[3] = un1[3];
             un1[0] = un0[0]; un1[1] = un0[1]; un1[2] = un0[2]; un1[3] = un0[3];
             a2R = a1R; a2I = a1I; a1R = a0R; a1I = a0I;
+            pc2 = pc1;
+            pc1 = pc0;
         }
         if (r2 >= r2lo && r2 < r2hi) {
             // ---- stage 2 at row r - 1: u(2) = 3/4 u^n + 1/4 (u(1) + dt F(u(1)))
@@ -1206,7 +1217,7 @@ __global__ __launch_bounds__(kBThreads) void blocked_step_kernel(StageArgs A)
                 for (int t = 0; t < 6; ++t) w[p][t] = s1[b][p][cl(l - 3 + t)];
             const double dnR = r2 - 1 >= 0 ? a2R : A.parity * a1R, dnI = r2 - 1 >= 0 ? a2I : A.parity * a1I;
             const double upR = r2 + 1 < nth ? a0R : A.parity * a1R, upI = r2 + 1 < nth ? a0I : A.parity * a1I;
-            const Out o = stage(w, dnR, dnI, upR, upI, r2, 0.75, 0.25, un1, false);
+            const Out o = stage(w, dnR, dnI, upR, upI, pc1, 0.75, 0.25, un1, false);
             if (!dup) {
 #pragma unroll
                 for (int p = 0; p < 4; ++p) s2[b][p][l] = o.v[p];
@@ -1226,7 +1237,7 @@ __global__ __launch_bounds__(kBThreads) void blocked_step_kernel(StageArgs A)
                 for (int t = 0; t < 6; ++t) w[p][t] = s2[b][p][cl(l - 3 + t)];
             const double dnR = r3 - 1 >= 0 ? c3R : A.parity * c2R, dnI = r3 - 1 >= 0 ? c3I : A.parity * c2I;
             const double upR = r3 + 1 < nth ? c1R : A.parity * c2R, upI = r3 + 1 < nth ? c1I : A.parity * c2I;
-            const Out o = stage(w, dnR, dnI, upR, upI, r3, 1.0 / 3.0, 2.0 / 3.0, un2, false);
+            const Out o = stage(w, dnR, dnI, upR, upI, pc2, 1.0 / 3.0, 2.0 / 3.0, un2, false);
             if (out_lane) {
                 const size_t row = (size_t)r3 * nr;
 #pragma unroll
