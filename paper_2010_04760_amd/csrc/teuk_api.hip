@@ -231,7 +231,20 @@ bool validate(const teuk_config* c, std::string& err)
 // one so that neighbouring segments pair up, and at most one per theta row.
 int pick_segs(const teuk_config& c, int nstrips, int weight_prec, bool first)
 {
-    long long cap = c.workgroups > 0 ? c.workgroups : stage_grid(weight_prec, first, kernel_chart(c));
+    // The stages of a solve take the same tiling (consecutive launches then
+    // march the same tiles and meet at the same rows, whose lines are still in
+    // L2), sized for the stage kernel that holds the fewer workgroups at once,
+    // when the two stage kernels hold nearly as many (FP32 weights: stage 1
+    // fits 17 workgroups per CU by LDS, stages 2-3 16 by VGPRs); when they
+    // differ by a whole wave per SIMD (BF16 weights: 4 and 3), each stage
+    // fills the GPU with its own count, which measured faster there.
+    long long cap = c.workgroups;
+    if (cap <= 0) {
+        const long long g1 = stage_grid(weight_prec, true, kernel_chart(c));
+        const long long g2 = stage_grid(weight_prec, false, kernel_chart(c));
+        const long long lo = g1 < g2 ? g1 : g2, hi = g1 < g2 ? g2 : g1;
+        cap = 8 * hi <= 9 * lo ? lo : (first ? g1 : g2);
+    }
     if (cap <= 0) return 0;
     long long segs = cap / nstrips;
     if (segs > c.ntheta) segs = c.ntheta;

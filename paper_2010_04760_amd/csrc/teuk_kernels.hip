@@ -137,24 +137,17 @@ struct Weno<TEUK_W_FP64> {
 // IS_k, alpha_k and omega_0, omega_1 are formed in the low format; omega_2 is
 // the FP64 complement and the candidate fluxes stay FP64.
 //
-// The weights use the ratio form
+// The 16-bit weights use the ratio form
 //     alpha'_k = d_k (tau_min / tau_k)^2,   tau_k = eps + IS_k,
 // which equals alpha_k tau_min^2 (so omega is unchanged in exact arithmetic)
 // and keeps every intermediate in [0, 1] whatever the magnitude of the data.
-// rho_k = 1 where tau_k equals tau_min (also when both are zero).
+// rho_k = 1 where tau_k equals tau_min (also when both are zero).  FP32 has
+// the range for the FP64 form and takes it (Weno<TEUK_W_FP32> below).
 
 // Arithmetic in the low format: every result rounded to it.  ratio(a, b) is
-// a / b for 0 <= a < b.  In the 16-bit formats it is a true division: after
-// the power-of-two scaling eps can underflow to zero, so a flat stencil gives
-// tau_min = 0 next to a tau_k below 2^-16 whose reciprocal overflows, and
-// 0 * inf would poison the weights.  In FP32, tau_k >= eps keeps 1/tau_k finite.
-struct LowF32 {
-    typedef float T;
-    __device__ static T cvt(float x) { return x; }
-    __device__ static T rcp(T x) { return __builtin_amdgcn_rcpf(x); }
-    __device__ static T ratio(T a, T b) { return a * __builtin_amdgcn_rcpf(b); }
-    __device__ static float f(T x) { return x; }
-};
+// a / b for 0 <= a < b, a true division: after the power-of-two scaling eps
+// can underflow to zero, so a flat stencil gives tau_min = 0 next to a tau_k
+// below 2^-16 whose reciprocal overflows, and 0 * inf would poison the weights.
 struct LowF16 {
     typedef _Float16 T;
     __device__ static T cvt(float x) { return (_Float16)x; }
@@ -242,8 +235,46 @@ struct WenoLow {
     }
 };
 
+// FP32 weights take the FP64 form above -- common denominator, one
+// reciprocal (v_rcp_f32, 1 ulp) -- evaluated in FP32 from the six FP64
+// stencil differences, with omega_2 the FP64 complement.  FP32 has the range
+// for it over most of the data: with t_k = (4 eps + 4 IS_k)^2 the denominator
+// is at least 2560 eps^4 and stays finite for differences up to about 1e4.  It
+// must also stay well above the subnormals, where the reciprocal overflows to
+// inf (and 0 * inf is a NaN) or loses its precision: below 2^-100 -- every
+// flat stencil once eps is under about 4e-9 -- and above 3e38 the lane takes
+// the FP64 weights instead.  From 2^-100 on, a product that is subnormal or
+// flushed to zero moves its weight by at most 2^-26 absolute.
 template <>
-struct Weno<TEUK_W_FP32> : WenoLow<LowF32, false> {};
+struct Weno<TEUK_W_FP32> {
+    __device__ __forceinline__ static double flux6(double v0, double v1, double v2, double v3, double v4,
+                                                    double eps)
+    {
+        const double d0 = v0 - 2.0 * v1 + v2;
+        const double d1 = v1 - 2.0 * v2 + v3;
+        const double d2 = v2 - 2.0 * v3 + v4;
+        const double e0 = v0 - 4.0 * v1 + 3.0 * v2;
+        const double e1 = v1 - v3;
+        const double e2 = 3.0 * v2 - 4.0 * v3 + v4;
+        const float D0 = (float)d0, D1 = (float)d1, D2 = (float)d2;
+        const float E0 = (float)e0, E1 = (float)e1, E2 = (float)e2;
+        constexpr float c = 13.0f / 3.0f;
+        const float eps4 = (float)(4.0 * eps);
+        float t0 = __builtin_fmaf(c * D0, D0, __builtin_fmaf(E0, E0, eps4));
+        float t1 = __builtin_fmaf(c * D1, D1, __builtin_fmaf(E1, E1, eps4));
+        float t2 = __builtin_fmaf(c * D2, D2, __builtin_fmaf(E2, E2, eps4));
+        t0 *= t0;
+        t1 *= t1;
+        t2 *= t2;
+        const float p12 = t1 * t2, p02 = t0 * t2, p01 = t0 * t1;
+        const float den = p12 + (6.0f * p02 + 3.0f * p01);
+        const Candidates q(v0, v1, v2, v3, d0, d1, d2);
+        if (!(den >= 0x1p-100f && den <= 3.0e38f)) return Weno<TEUK_W_FP64>::flux6(v0, v1, v2, v3, v4, eps);
+        const float inv = __builtin_amdgcn_rcpf(den);
+        const double w0 = (double)(p12 * inv), w1 = (double)((6.0f * p02) * inv);
+        return q.q2 + (w0 * q.dq0 + w1 * q.dq1);
+    }
+};
 template <>
 struct Weno<TEUK_W_FP16> : WenoLow<LowF16, true> {};
 template <>

@@ -10,7 +10,11 @@ one in FP64 and every candidate-flux combination stays consistent.  Checks:
   boundary ghosts, while on rough data they differ (the low path is in use);
 * error against the FP64 oracle of a full C1 run (1000 steps), waveform
   relative L2: FP32 <= 1e-6 (the bar set for the method), FP16 and BF16 held
-  to the looser bars below, which sit above the measured errors.
+  to the looser bars below, which sit above the measured errors;
+* every epsilon the configuration accepts, on data whose smoothness
+  indicators run through every magnitude down to exact zeros: F(u) stays
+  finite, equals the FP64 path's where the data are flat, and stays within
+  the bars below of it elsewhere.
 """
 import numpy as np
 import pytest
@@ -34,8 +38,8 @@ def cfg_for(prob, dt, **kw):
                          x_max=prob.x_max, dt=dt, **kw)
 
 
-def rhs(prob, u, prec):
-    with T.Solver(cfg_for(prob, 0.01, weight_prec=prec)) as sv:
+def rhs(prob, u, prec, **kw):
+    with T.Solver(cfg_for(prob, 0.01, weight_prec=prec, **kw)) as sv:
         sv.set_initial(u)
         return sv.rhs()
 
@@ -106,3 +110,36 @@ def test_flat_stencil_next_to_a_jump_stays_finite(prec):
     Flo = rhs(prob, u, prec)
     assert np.all(np.isfinite(Flo))
     assert np.max(np.abs(Flo - F64)) <= 0.1 * np.max(np.abs(F64))
+
+
+# measured over the sweep: FP32 <= 2e-10, FP16 1.2e-6, BF16 1.1e-5 of max |F|; the
+# bars leave a factor of about 100 to the weights' rounding (2^-23, 2^-10, 2^-7
+# relative, times corrections that are a small part of F)
+EPS_BAR = {"fp32": 1e-7, "fp16": 1e-4, "bf16": 1e-3}
+
+
+@pytest.mark.parametrize("prec", LOW)
+@pytest.mark.parametrize("eps", [1e-30, 1e-13, 1e-11, 1e-10, 1e-8, 1e-6, 1e2])
+def test_every_eps_stays_finite_and_close(prec, eps):
+    """The FP32 weights' common denominator is at least 2560 eps^4 on a flat
+    stencil, which is subnormal or zero in FP32 for eps below about 4e-9
+    (its reciprocal would overflow); there the lane must take the FP64
+    weights.  The data: a Gaussian whose tails take IS_k through every
+    magnitude down to ~1e-50, then exact zeros over the outer third."""
+    say("case eps sweep", prec, eps)
+    prob = S.Problem(-2, 2, 0.9, 400, 12, -40.0, 60.0, eps=eps)
+    x = prob.x()
+    prof = np.exp(-(x / 4.0) ** 2)
+    prof[x > 30.0] = 0.0
+    ang = W.angular_profile(-2, 2, prob.theta())
+    u = np.zeros((4, prob.nth, prob.nr))
+    for p in range(4):
+        u[p] = ang[:, None] * prof[None, :] * (1.0 + 0.25 * p)
+    F64 = rhs(prob, u, "fp64", weno_eps=eps)
+    Flo = rhs(prob, u, prec, weno_eps=eps)
+    assert np.all(np.isfinite(Flo)), (prec, eps)
+    flat = x > 31.0                        # every radial stencil reads zeros only
+    assert np.array_equal(Flo[:, :, flat], F64[:, :, flat])
+    rel = float(np.max(np.abs(Flo - F64))) / float(np.max(np.abs(F64)))
+    say("eps sweep", prec, eps, "max |F_low - F_64| / max |F_64|", rel)
+    assert rel <= EPS_BAR[prec], (prec, eps, rel)
