@@ -93,7 +93,12 @@ enum { TEUK_CHART_TORTOISE = 0, TEUK_CHART_HYPERBOLOIDAL = 1 };
 
 /* Precision of the WENO smoothness indicators and nonlinear weights
  * (Sec. 3.1.3).  The six stencil differences, the candidate fluxes and
- * everything after them stay FP64; omega_2 = 1 - omega_0 - omega_1 in FP64. */
+ * everything after them stay FP64; omega_2 = 1 - omega_0 - omega_1 in FP64.
+ * FP32 forms the weights over one common denominator; a point where that
+ * denominator leaves [2^-100, 3e38] in FP32 (a flat stencil once weno_eps is
+ * below about 4e-9, or differences above about 1e4) takes the FP64 weights.
+ * FP16 and BF16 scale the differences by a power of two and form each weight
+ * as a ratio, so they stay finite over the whole range of weno_eps. */
 enum { TEUK_W_FP64 = 0, TEUK_W_FP32 = 1, TEUK_W_FP16 = 2, TEUK_W_BF16 = 3,
        TEUK_W_DD = 4 /* double-double weights: TEUK_S_DD only */ };
 
