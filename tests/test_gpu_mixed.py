@@ -119,7 +119,7 @@ EPS_BAR = {"fp32": 1e-7, "fp16": 1e-4, "bf16": 1e-3}
 
 
 @pytest.mark.parametrize("prec", LOW)
-@pytest.mark.parametrize("eps", [1e-30, 1e-13, 1e-11, 1e-10, 1e-8, 1e-6, 1e2])
+@pytest.mark.parametrize("eps", [1e-30, 1e-13, 1e-11, 1e-10, 1e-8, 1e-6, 1e2, 1e30])
 def test_every_eps_stays_finite_and_close(prec, eps):
     """The FP32 weights' common denominator is at least 2560 eps^4 on a flat
     stencil, which is subnormal or zero in FP32 for eps below about 4e-9

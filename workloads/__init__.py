@@ -137,6 +137,20 @@ def random_state(nr: int, nth: int, seed: int, smooth: bool = False) -> np.ndarr
     return u
 
 
+def separable_state(nr: int, nth: int, seed: int) -> np.ndarray:
+    """A seeded state [4][nth][nr] whose plane p is the outer product of a
+    random theta profile and a random radial profile (standard normal, plus
+    one on both): rough in both directions, yet drawn from only 4 (nr + nth)
+    numbers, so that grids of billions of points are cheap to build."""
+    rng = np.random.default_rng(seed)
+    a = 1.0 + rng.standard_normal((4, nth))
+    b = 1.0 + rng.standard_normal((4, nr))
+    u = np.empty((4, nth, nr))
+    for p in range(4):
+        np.multiply(a[p][:, None], b[p][None, :], out=u[p])
+    return u
+
+
 def batch_workloads(n: int = 64, seed0: int = 1000, steps: int = 2000) -> List[Workload]:
     """The batched mix: uneven grids and (s, m, a) per solve, seeded per solve.
 
