@@ -416,7 +416,11 @@ teuk_status teuk_step_noalloc(const teuk_config* cfg, double* u, int64_t nsteps,
  * and per background; such solves share nothing, so a group advances all of
  * its members in one stage-kernel launch per SSP-RK stage (one per weight
  * precision present and per cache block of members) instead of three
- * launches per member per step.  Each
+ * launches per member per step.  A cache block whose every member fills the
+ * GPU by itself (63-point strips x theta rows at least the stage kernel's
+ * resident workgroups) has no launches to save: with workgroups = 0 it runs
+ * its members' own single-solve stage launches, member after member within
+ * each stage, which are faster on such grids.  Each
  * member keeps its own grid, coefficients, dt, waveform ring and counters, and
  * its results are bitwise those of teuk_step on the member alone: the tiles
  * of a member run the single-solve stage arithmetic unchanged.
@@ -432,7 +436,7 @@ typedef struct teuk_group teuk_group;   /* opaque; owned by the library */
 typedef struct {
     int32_t members;         /* solvers in the group                                 */
     int32_t classes;         /* (weight precision, chart) classes present            */
-    int64_t workgroups;      /* workgroups per stage, summed over the launches (blocks) */
+    int64_t workgroups;      /* workgroups per stage (stages 2-3), summed over the launches */
     int64_t tiles;           /* tiles (one strip x one theta segment) per stage        */
     int64_t units;           /* strip-rows per stage (63 radial points x 1 theta row)  */
     int64_t points;          /* grid points over all members                          */

@@ -79,6 +79,19 @@ constexpr long long kPipeSpinTicks = 200000000;   // 2 s of the 100 MHz real-tim
 #endif
 constexpr long long kGroupBlockBytes = (long long)TEUK_GROUP_BLOCK_MB << 20;
 
+// A cache block whose every member fills the GPU by itself (strips x rows at
+// least the stage kernel's resident workgroups) is stepped by its members' own
+// stage launches, member after member within each stage, instead of the
+// batched launch (unless the caller fixed the batched launch's workgroup
+// count): the single-solve launch keeps every workgroup resident from
+// the start and carries the issue-priority steps and the DPP flux shift, which
+// the batched launch, dispatching short tiles as slots free up, cannot use.
+// Same arithmetic at every point, so the results are bitwise those of the
+// batched launch.
+#ifndef TEUK_GROUP_SOLO
+#define TEUK_GROUP_SOLO 1
+#endif
+
 // One cache block: members [first, first + n) of the class order (their stage
 // descriptors are consecutive in d_args), tile prefix sums from d_start + start.
 struct GroupBlock {
@@ -87,6 +100,8 @@ struct GroupBlock {
     long long tiles = 0, units = 0;
     size_t start = 0;
     int grid = 0;
+    bool solo = false;   // members stepped by their own single-solve launches
+    long long solo_wg = 0;   // their stage-2/3 workgroups, summed over the members
 };
 
 struct teuk_group {
@@ -653,6 +668,27 @@ static StageArgs stage_args(const teuk_solver* h)
     return a;
 }
 
+// Stage `stage` (1..3) of one SSP-RK(3,3) step of h, from a = stage_args(h).
+// Consecutive launches march their theta segments in opposite directions (flip
+// alternates with the launch count 3 steps + stage), so that a stage starts on
+// the rows the previous one wrote last, which are still in the XCD's L2.  The
+// arithmetic of every point is the same either way.
+static void rk3_stage(const teuk_solver* h, StageArgs& a, int stage)
+{
+    const int flip = (int)(h->steps & 1);
+    if (stage == 1) {            // u1 = u + dt F(u)
+        a.uk = h->u[0]; a.un = h->u[0]; a.out = h->u[1]; a.ca = 0.0; a.cb = 1.0;
+        a.segs = h->segs[0]; a.flip = flip;
+    } else if (stage == 2) {     // u2 = 3/4 u + 1/4 (u1 + dt F(u1))
+        a.uk = h->u[1]; a.un = h->u[0]; a.out = h->u[2]; a.ca = 0.75; a.cb = 0.25;
+        a.segs = h->segs[1]; a.flip = flip ^ 1;
+    } else {                     // u = 1/3 u + 2/3 (u2 + dt F(u2)), in place (u^n read at the own point only)
+        a.uk = h->u[2]; a.un = h->u[0]; a.out = h->u[0]; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0;
+        a.segs = h->segs[1]; a.flip = flip;
+    }
+    a.grid = h->nstrips * a.segs;
+}
+
 // One stage launch of the solver's radial scheme.
 static int run_stage(const teuk_solver* h, const StageArgs& a, int stage)
 {
@@ -798,22 +834,11 @@ static teuk_status step_eager(teuk_solver* h, int64_t nsteps)
         return TEUK_OK;
     }
     for (int64_t n = 0; n < nsteps; ++n) {
-        // Consecutive launches march their theta segments in opposite
-        // directions (flip alternates with the launch count 3 steps + stage),
-        // so that a stage starts on the rows the previous one wrote last,
-        // which are still in the XCD's L2.  The arithmetic of every point is
-        // the same either way.
-        const int flip = (int)(h->steps & 1);
-        // u1 = u + dt F(u)
-        a.uk = h->u[0]; a.un = h->u[0]; a.out = h->u[1]; a.ca = 0.0; a.cb = 1.0; a.segs = h->segs[0]; a.grid = h->nstrips * h->segs[0];
-        a.flip = flip;
-        int e = run_stage(h, a, 1);
-        // u2 = 3/4 u + 1/4 (u1 + dt F(u1))
-        if (!e) { a.uk = h->u[1]; a.un = h->u[0]; a.out = h->u[2]; a.ca = 0.75; a.cb = 0.25; a.segs = h->segs[1]; a.grid = h->nstrips * h->segs[1];
-                  a.flip = flip ^ 1; e = run_stage(h, a, 2); }
-        // u = 1/3 u + 2/3 (u2 + dt F(u2)), in place (u^n is read only at the own point)
-        if (!e) { a.uk = h->u[2]; a.un = h->u[0]; a.out = h->u[0]; a.ca = 1.0 / 3.0; a.cb = 2.0 / 3.0; a.segs = h->segs[1]; a.grid = h->nstrips * h->segs[1];
-                  a.flip = flip; e = run_stage(h, a, 3); }
+        int e = 0;
+        for (int stage = 1; stage <= 3 && !e; ++stage) {
+            rk3_stage(h, a, stage);
+            e = run_stage(h, a, stage);
+        }
         if (e) return hip_fail(h, e, "stage launch");
         ++h->steps;
         if (c.extract_every > 0 && h->steps % c.extract_every == 0) {
@@ -1130,6 +1155,7 @@ static teuk_status group_upload(teuk_group* g)
     for (int c = 0; c < kClasses; ++c) {
         GroupBlock blk;
         long long bytes = 0;
+        bool all_fill = true;
         auto open_block = [&]() {
             blk = GroupBlock();
             blk.cls = c;
@@ -1137,9 +1163,11 @@ static teuk_status group_upload(teuk_group* g)
             blk.start = soff;
             g->h_start[soff] = 0;
             bytes = 0;
+            all_fill = true;
         };
         auto close_block = [&]() {
             blk.grid = (int)(g->workgroups > 0 && g->workgroups < blk.tiles ? g->workgroups : blk.tiles);
+            blk.solo = TEUK_GROUP_SOLO && all_fill && g->workgroups == 0;
             g->blocks.push_back(blk);
             soff += (size_t)blk.n + 1;
         };
@@ -1150,10 +1178,15 @@ static teuk_status group_upload(teuk_group* g)
                 close_block();
                 open_block();
             }
+            if (TEUK_GROUP_SOLO) {
+                const long long resident = stage_grid(h->cfg.weight_prec, false, kernel_chart(h->cfg));
+                all_fill = all_fill && resident > 0 && (long long)h->nstrips * h->cfg.ntheta >= resident;
+            }
             StageArgs a = stage_args(h);
             a.segs = group_segs(h->cfg.ntheta, g->rows);
             a.grid = 0;                                  // set per launch
             blk.tiles += (long long)h->nstrips * a.segs;
+            blk.solo_wg += (long long)h->nstrips * h->segs[1];
             blk.units += (long long)h->nstrips * h->cfg.ntheta;
             if (blk.tiles > (1LL << 31) - 1)
                 return gfail(g, TEUK_ERR_CAPACITY, "group block too large for one launch (2^31 - 1 tiles)");
@@ -1264,8 +1297,18 @@ static teuk_status group_block_eager(teuk_group* g, size_t bi, int64_t nsteps, h
     const GroupBlock& b = g->blocks[bi];
     for (int64_t n = 0; n < nsteps; ++n) {
         for (int stage = 1; stage <= 3; ++stage) {
-            const int e = launch_group_stage(g->d_args + (stage - 1) * cap + b.first, g->d_start + b.start, b.n,
-                                             b.tiles, b.grid, stage, b.cls % 4, b.cls / 4, stream);
+            int e = 0;
+            if (b.solo) {
+                for (int k = b.first; k < b.first + b.n && !e; ++k) {
+                    const teuk_solver* h = g->order[(size_t)k];
+                    StageArgs a = stage_args(h);
+                    rk3_stage(h, a, stage);
+                    e = launch_stage(a, stage, h->cfg.weight_prec, kernel_chart(h->cfg), stream);
+                }
+            } else {
+                e = launch_group_stage(g->d_args + (stage - 1) * cap + b.first, g->d_start + b.start, b.n,
+                                       b.tiles, b.grid, stage, b.cls % 4, b.cls / 4, stream);
+            }
             if (e) return gfail(g, TEUK_ERR_DEVICE, std::string("group stage launch: ") +
                                                        hipGetErrorString((hipError_t)e));
         }
@@ -1547,8 +1590,8 @@ teuk_status teuk_group_info(const teuk_group* g, teuk_group_info_t* info)
     for (const GroupBlock& b : g->blocks) {
         info->classes += !seen[b.cls];
         seen[b.cls] = true;
-        info->workgroups += b.grid;
-        info->tiles += b.tiles;
+        info->workgroups += b.solo ? b.solo_wg : b.grid;
+        info->tiles += b.solo ? b.solo_wg : b.tiles;
         info->units += b.units;
     }
     info->points = g->points;
