@@ -736,6 +736,40 @@ def bench_batched(args, torch, T, W):
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     gpu_s = ev0.elapsed_time(ev1) / 1e3
+    blocked = None
+    if not args.no_blocked:
+        # the same solves with the temporally blocked step (one launch per
+        # step and member, each member a cache block of its own), from the
+        # initial data for as many steps; compared with the group above at
+        # equal steps on three members
+        log(f"C4: the same solves with the blocked step, warmup {warmup} + {steps} steps")
+        bmembers = []
+        for w in mix:
+            sv = T.Solver(solver_config(T, w, weights, warmup + steps, integrator="rk3_blocked"), stream=stream)
+            sv.set_initial(W.gaussian_pulse(w))
+            bmembers.append(sv)
+        bg = T.Group(len(mix), stream=stream)
+        for sv in bmembers:
+            bg.add(sv)
+        bg.step(warmup)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        bg.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        b_s = ev0.elapsed_time(ev1) / 1e3
+        diff = 0.0
+        for i in (0, len(mix) // 2, len(mix) - 1):
+            ref = members[i].state()
+            diff = max(diff, float(np.max(np.abs(bmembers[i].state() - ref))) / float(np.max(np.abs(ref))))
+        for sv in bmembers:
+            sv.check_finite()
+        bg.close()
+        for sv in bmembers:
+            sv.close()
+        blocked = {"steps": steps, "ms_per_step": b_s / steps * 1e3, "value": 3.0 * points * steps / b_s,
+                   "speedup_vs_headline": gpu_s / b_s, "state_rel_diff_vs_three_launch": diff,
+                   "compared": "members 0, 32, 63 after warmup + steps steps"}
     other = None
     if not args.no_graph_leg:
         # the same number of steps in the other launch mode
@@ -773,6 +807,8 @@ def bench_batched(args, torch, T, W):
     }
     if tuned:
         out["autotuner"] = tuned
+    if blocked:
+        out["blocked_members"] = blocked
     if other:
         out["graph"] = other
     if not args.no_cpu_baseline:
@@ -847,7 +883,7 @@ def main():
                     help="C1/C2: steps of each weight-precision run (0: the workload's full length, which the "
                          "waveform comparison needs; fewer for profiling)")
     ap.add_argument("--no-rk104", action="store_true", help="C2: skip the SSP-RK(10,4) run")
-    ap.add_argument("--no-blocked", action="store_true", help="C2: skip the temporally blocked run")
+    ap.add_argument("--no-blocked", action="store_true", help="C2, C4: skip the temporally blocked run")
     ap.add_argument("--no-pipelined", action="store_true", help="C1/C2: skip the pipelined-step run")
     ap.add_argument("--no-theta4", action="store_true",
                     help="C1/C2: skip the run with fourth-order theta differences")

@@ -125,7 +125,9 @@ enum { TEUK_RK_SSP33 = 0, TEUK_RK_SSP104 = 1, TEUK_RK_SSP33_BLOCKED = 2, TEUK_RK
  * values two rows and six points beyond its outputs and the stage-2 values one
  * row and three points beyond (workgroups, when > 0, sets the tile count).
  * The result is the same arithmetic as TEUK_RK_SSP33, point by point.
- * Tortoise chart, FP64 state, WENO5 with FP64 weights, single solves. */
+ * Tortoise chart, FP64 state, WENO5 with FP64 or FP32 weights.  In a group
+ * such a solve is a cache block of its own, stepped by its own blocked
+ * launches. */
 /* TEUK_RK_SSP33_PIPELINED: SSP-RK(3,3), the steps between two waveform samples
  * (at most 1000) in one persistent cooperative launch.  Each workgroup takes
  * the tiles of the three-launch step (63-point strips by theta segments) of
@@ -460,9 +462,11 @@ teuk_status teuk_group_create(const teuk_device_ctx* ctx, int32_t max_members, i
                               int32_t rows_per_tile, teuk_group** out);
 
 /* Add a solver (after teuk_set_initial) to the group.  Synchronises the group's
- * stream and uploads the members' descriptors.  Errors: INVALID_ARG (NULL,
- * other stream, already in a group), CAPACITY (group full), STATE (no initial
- * data), UNSUPPORTED (double-double state), DEVICE. */
+ * stream and uploads the members' descriptors.  Members step with SSP-RK(3,3),
+ * three-launch (TEUK_RK_SSP33) or temporally blocked (TEUK_RK_SSP33_BLOCKED),
+ * and WENO5.  Errors: INVALID_ARG (NULL, other stream, already in a group),
+ * CAPACITY (group full), STATE (no initial data), UNSUPPORTED (double-double
+ * state, another integrator or scheme), DEVICE. */
 teuk_status teuk_group_add(teuk_group* g, teuk_solver* h);
 
 /* Remove a member (synchronises the group's stream).  The solver stays valid
@@ -485,8 +489,9 @@ teuk_status teuk_group_step(teuk_group* g, int64_t nsteps);
  * runs all of a call's steps before the next block starts.  Adding or removing
  * a member drops the graphs; they are recaptured on the next step.  This
  * call captures every block's graph at once.  Every
- * member's extract_every must divide chunk_steps (else teuk_group_step returns
- * INVALID_ARG).  chunk_steps = 0 turns it off; at most 4096.
+ * member's extract_every must divide chunk_steps, and chunk_steps must be even
+ * when a member takes the blocked step (else this call and teuk_group_step
+ * return INVALID_ARG).  chunk_steps = 0 turns it off; at most 4096.
  * Errors: INVALID_ARG, DEVICE (capture). */
 teuk_status teuk_group_set_graph(teuk_group* g, int32_t chunk_steps);
 

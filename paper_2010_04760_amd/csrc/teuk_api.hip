@@ -10,6 +10,7 @@
 #include <new>
 #include <string>
 #include <utility>
+#include <array>
 #include <vector>
 
 #include "teuk_coef.h"
@@ -57,6 +58,7 @@ struct teuk_solver {
     hipStream_t cap_stream = nullptr;               // private stream the chunk is captured on
     hipGraphExec_t gexec = nullptr;                 // the captured chunk, or null
     long long graph_phase = -1;                     // steps % extract_every when it was captured
+    const double* graph_u0 = nullptr;               // the state buffer u[0] when it was captured
     std::string err;
 };
 
@@ -289,6 +291,7 @@ void drop_graph(teuk_solver* h)
         h->gexec = nullptr;
     }
     h->graph_phase = -1;
+    h->graph_u0 = nullptr;
 }
 
 void free_solver(teuk_solver* h)
@@ -398,9 +401,10 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     if (cfg->scheme != TEUK_SCHEME_WENO5 && (dd || cfg->weight_prec != TEUK_W_FP64))
         return fail(nullptr, TEUK_ERR_UNSUPPORTED, "comparison schemes: FP64 state and weights only");
     if (cfg->integrator == TEUK_RK_SSP33_BLOCKED &&
-        (chartH || dd || cfg->scheme != TEUK_SCHEME_WENO5 || cfg->weight_prec != TEUK_W_FP64))
+        (chartH || dd || cfg->scheme != TEUK_SCHEME_WENO5 ||
+         (cfg->weight_prec != TEUK_W_FP64 && cfg->weight_prec != TEUK_W_FP32)))
         return fail(nullptr, TEUK_ERR_UNSUPPORTED,
-                    "temporal blocking: tortoise chart, FP64 state, WENO5 with FP64 weights only");
+                    "temporal blocking: tortoise chart, FP64 state, WENO5 with FP64 or FP32 weights only");
     if (cfg->integrator == TEUK_RK_SSP33_PIPELINED &&
         (chartH || dd || cfg->scheme != TEUK_SCHEME_WENO5 || cfg->weight_prec == TEUK_W_DD))
         return fail(nullptr, TEUK_ERR_UNSUPPORTED, "pipelined steps: tortoise chart, FP64 state, WENO5 only");
@@ -493,7 +497,7 @@ teuk_status teuk_create(const teuk_config* cfg, const teuk_device_ctx* ctx, teuk
     }
     if (cfg->integrator == TEUK_RK_SSP33_BLOCKED) {
         h->bstrips = (cfg->nr + kBlockedPoints - 1) / kBlockedPoints;
-        long long cap = eff.workgroups > 0 ? eff.workgroups : blocked_grid();
+        long long cap = eff.workgroups > 0 ? eff.workgroups : blocked_grid(cfg->weight_prec);
         long long segs = cap / h->bstrips;
         if (segs > cfg->ntheta) segs = cfg->ntheta;
         if (segs < 1) segs = 1;
@@ -689,6 +693,24 @@ static void rk3_stage(const teuk_solver* h, StageArgs& a, int stage)
     a.grid = h->nstrips * a.segs;
 }
 
+// One temporally blocked SSP-RK(3,3) step of h on `stream`: u^n in u[0], u^{n+1}
+// written to u[1], then the two buffers trade roles.
+static int blocked_step_once(teuk_solver* h, hipStream_t stream)
+{
+    StageArgs a = stage_args(h);
+    a.nstrips = h->bstrips;
+    a.segs = h->bsegs;
+    a.grid = h->bstrips * h->bsegs;
+    a.ca = 0.0;
+    a.cb = 1.0;
+    a.uk = h->u[0];
+    a.un = h->u[0];
+    a.out = h->u[1];
+    const int e = launch_blocked_step(a, h->cfg.weight_prec, stream);
+    if (!e) std::swap(h->u[0], h->u[1]);             // u^{n+1} is the new state buffer
+    return e;
+}
+
 // One stage launch of the solver's radial scheme.
 static int run_stage(const teuk_solver* h, const StageArgs& a, int stage)
 {
@@ -775,18 +797,9 @@ static teuk_status step_eager(teuk_solver* h, int64_t nsteps)
     }
     StageArgs a = stage_args(h);
     if (c.integrator == TEUK_RK_SSP33_BLOCKED) {
-        a.nstrips = h->bstrips;
-        a.segs = h->bsegs;
-        a.grid = h->bstrips * h->bsegs;
-        a.ca = 0.0;
-        a.cb = 1.0;
         for (int64_t n = 0; n < nsteps; ++n) {
-            a.uk = h->u[0];
-            a.un = h->u[0];
-            a.out = h->u[1];
-            const int e = launch_blocked_step(a, c.weight_prec, h->stream);
+            const int e = blocked_step_once(h, h->stream);
             if (e) return hip_fail(h, e, "blocked step launch");
-            std::swap(h->u[0], h->u[1]);             // u^{n+1} is the new state buffer
             ++h->steps;
             if (c.extract_every > 0 && h->steps % c.extract_every == 0) {
                 teuk_status st = record_sample(h);
@@ -856,7 +869,10 @@ static teuk_status capture_chunk(teuk_solver* h)
 {
     const long long every = h->cfg.extract_every;
     const long long phase = every > 0 ? h->steps % every : 0;
-    if (h->gexec && h->graph_phase == phase) return TEUK_OK;
+    // the graph holds the buffer roles of its capture: the blocked step trades
+    // u[0] and u[1] every step, so an odd number of eager steps since needs
+    // a new capture even where the sampling phase is unchanged
+    if (h->gexec && h->graph_phase == phase && h->graph_u0 == h->u[0]) return TEUK_OK;
     drop_graph(h);
     int e = 0;
     if (!h->cap_stream) {
@@ -899,6 +915,7 @@ static teuk_status capture_chunk(teuk_solver* h)
         return hip_fail(h, e, "hipGraphUpload");
     }
     h->graph_phase = phase;
+    h->graph_u0 = h->u[0];
     return TEUK_OK;
 }
 
@@ -1155,7 +1172,7 @@ static teuk_status group_upload(teuk_group* g)
     for (int c = 0; c < kClasses; ++c) {
         GroupBlock blk;
         long long bytes = 0;
-        bool all_fill = true;
+        bool all_fill = true, blocked = false;
         auto open_block = [&]() {
             blk = GroupBlock();
             blk.cls = c;
@@ -1164,20 +1181,24 @@ static teuk_status group_upload(teuk_group* g)
             g->h_start[soff] = 0;
             bytes = 0;
             all_fill = true;
+            blocked = false;
         };
         auto close_block = [&]() {
             blk.grid = (int)(g->workgroups > 0 && g->workgroups < blk.tiles ? g->workgroups : blk.tiles);
-            blk.solo = TEUK_GROUP_SOLO && all_fill && g->workgroups == 0;
+            blk.solo = blocked || (TEUK_GROUP_SOLO && all_fill && g->workgroups == 0);
             g->blocks.push_back(blk);
             soff += (size_t)blk.n + 1;
         };
         open_block();
         for (teuk_solver* h : g->mem) {
             if (h->cfg.weight_prec + 4 * kernel_chart(h->cfg) != c) continue;
-            if (blk.n > 0 && bytes + (long long)h->bytes > g->block_bytes) {
+            // a member with the blocked step is a block of its own, stepped by its own launches
+            const bool bl = h->cfg.integrator == TEUK_RK_SSP33_BLOCKED;
+            if (blk.n > 0 && (bl || blocked || bytes + (long long)h->bytes > g->block_bytes)) {
                 close_block();
                 open_block();
             }
+            blocked = bl;
             if (TEUK_GROUP_SOLO) {
                 const long long resident = stage_grid(h->cfg.weight_prec, false, kernel_chart(h->cfg));
                 all_fill = all_fill && resident > 0 && (long long)h->nstrips * h->cfg.ntheta >= resident;
@@ -1186,7 +1207,7 @@ static teuk_status group_upload(teuk_group* g)
             a.segs = group_segs(h->cfg.ntheta, g->rows);
             a.grid = 0;                                  // set per launch
             blk.tiles += (long long)h->nstrips * a.segs;
-            blk.solo_wg += (long long)h->nstrips * h->segs[1];
+            blk.solo_wg += bl ? (long long)h->bstrips * h->bsegs : (long long)h->nstrips * h->segs[1];
             blk.units += (long long)h->nstrips * h->cfg.ntheta;
             if (blk.tiles > (1LL << 31) - 1)
                 return gfail(g, TEUK_ERR_CAPACITY, "group block too large for one launch (2^31 - 1 tiles)");
@@ -1254,8 +1275,9 @@ teuk_status teuk_group_add(teuk_group* g, teuk_solver* h)
     if (!g) return gfail(nullptr, TEUK_ERR_INVALID_ARG, "group is NULL");
     if (!h) return gfail(g, TEUK_ERR_INVALID_ARG, "solver is NULL");
     if (h->dd) return gfail(g, TEUK_ERR_UNSUPPORTED, "double-double solvers are not group members");
-    if (h->cfg.integrator != TEUK_RK_SSP33 || h->cfg.scheme != TEUK_SCHEME_WENO5)
-        return gfail(g, TEUK_ERR_UNSUPPORTED, "group members step with SSP-RK(3,3) and WENO5");
+    if ((h->cfg.integrator != TEUK_RK_SSP33 && h->cfg.integrator != TEUK_RK_SSP33_BLOCKED) ||
+        h->cfg.scheme != TEUK_SCHEME_WENO5)
+        return gfail(g, TEUK_ERR_UNSUPPORTED, "group members step with SSP-RK(3,3), three-launch or blocked, and WENO5");
     if (h->group) return gfail(g, TEUK_ERR_INVALID_ARG, "solver already belongs to a group");
     if (h->stream != g->stream) return gfail(g, TEUK_ERR_INVALID_ARG, "solver and group use different streams");
     if (h->device != g->device) return gfail(g, TEUK_ERR_INVALID_ARG, "solver and group are on different devices");
@@ -1295,8 +1317,14 @@ static teuk_status group_block_eager(teuk_group* g, size_t bi, int64_t nsteps, h
 {
     const size_t cap = (size_t)g->cap;
     const GroupBlock& b = g->blocks[bi];
+    const bool blocked = b.solo && g->order[(size_t)b.first]->cfg.integrator == TEUK_RK_SSP33_BLOCKED;
     for (int64_t n = 0; n < nsteps; ++n) {
-        for (int stage = 1; stage <= 3; ++stage) {
+        if (blocked) {   // a block of one member with the blocked step: one launch per step
+            const int e = blocked_step_once(g->order[(size_t)b.first], stream);
+            if (e) return gfail(g, TEUK_ERR_DEVICE, std::string("blocked step launch: ") +
+                                                       hipGetErrorString((hipError_t)e));
+        }
+        for (int stage = 1; stage <= 3 && !blocked; ++stage) {
             int e = 0;
             if (b.solo) {
                 for (int k = b.first; k < b.first + b.n && !e; ++k) {
@@ -1342,7 +1370,7 @@ static void drop_group_graphs(teuk_group* g)
 }
 
 // The graph of graph_chunk steps of block bi, captured for its members'
-// current sampling phases (recaptured when they differ).
+// current sampling phases and state buffers (recaptured when they differ).
 static teuk_status capture_block(teuk_group* g, size_t bi)
 {
     const GroupBlock& b = g->blocks[bi];
@@ -1353,7 +1381,11 @@ static teuk_status capture_block(teuk_group* g, size_t bi)
         const long long every = h->cfg.extract_every;
         if (every > 0 && chunk % every != 0)
             return gfail(g, TEUK_ERR_INVALID_ARG, "graph mode: chunk_steps must be a multiple of every member's extract_every");
+        if (h->cfg.integrator == TEUK_RK_SSP33_BLOCKED && chunk % 2 != 0)
+            return gfail(g, TEUK_ERR_INVALID_ARG,
+                         "graph mode: a member with the blocked step swaps two buffers per step: chunk_steps must be even");
         phase.push_back(every > 0 ? h->steps % every : 0);
+        phase.push_back((long long)(uintptr_t)h->u[0]);   // buffer roles (the blocked step trades them)
     }
     if (g->gexec[bi] && g->gphase[bi] == phase) return TEUK_OK;
     int e = 0;
@@ -1370,15 +1402,22 @@ static teuk_status capture_block(teuk_group* g, size_t bi)
         }
     }
     std::vector<std::pair<long long, long long>> saved;
-    for (int k = b.first; k < b.first + b.n; ++k) saved.emplace_back(g->order[(size_t)k]->steps, g->order[(size_t)k]->samples);
+    std::vector<std::array<double*, 3>> saved_u;
+    for (int k = b.first; k < b.first + b.n; ++k) {
+        const teuk_solver* h = g->order[(size_t)k];
+        saved.emplace_back(h->steps, h->samples);
+        saved_u.push_back({h->u[0], h->u[1], h->u[2]});
+    }
     e = (int)hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e) return gfail(g, TEUK_ERR_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString((hipError_t)e));
     const teuk_status st = group_block_eager(g, bi, chunk, g->cap_stream);
     hipGraph_t graph = nullptr;
     e = (int)hipStreamEndCapture(g->cap_stream, &graph);
     for (int k = b.first; k < b.first + b.n; ++k) {
-        g->order[(size_t)k]->steps = saved[(size_t)(k - b.first)].first;
-        g->order[(size_t)k]->samples = saved[(size_t)(k - b.first)].second;
+        teuk_solver* h = g->order[(size_t)k];
+        h->steps = saved[(size_t)(k - b.first)].first;
+        h->samples = saved[(size_t)(k - b.first)].second;
+        for (int i = 0; i < 3; ++i) h->u[i] = saved_u[(size_t)(k - b.first)][(size_t)i];
     }
     if (st != TEUK_OK) {
         if (graph) (void)hipGraphDestroy(graph);

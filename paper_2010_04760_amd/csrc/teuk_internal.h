@@ -107,12 +107,13 @@ int launch_dt_bound(const double* rtab, const double* ttab, const double* ctab, 
 int launch_guard(const double* u, long long n, int* flag, void* stream);
 int launch_coef_dump(const double* rtab, const double* ttab, const double* ctab, int nr, int nth, double* out,
                      void* stream);
-// Temporal blocking: one whole SSP-RK(3,3) step (tortoise chart, FP64
-// weights) from a.uk into a.out (distinct buffers), tiles of kBlockedPoints
-// radial points by a.nth / a.segs rows, a.grid = a.nstrips * a.segs
-// workgroups.  blocked_grid() is the resident workgroup count.
+// Temporal blocking: one whole SSP-RK(3,3) step (tortoise chart, FP64 or
+// FP32 weights) from a.uk into a.out (distinct buffers), tiles of
+// kBlockedPoints radial points by a.nth / a.segs rows, a.grid = a.nstrips *
+// a.segs workgroups.  blocked_grid(weight_prec) is the resident workgroup
+// count (0 for a precision without a blocked kernel).
 constexpr int kBlockedPoints = 114;
-int blocked_grid();
+int blocked_grid(int weight_prec);
 int launch_blocked_step(const StageArgs& a, int weight_prec, void* stream);
 // Pipelined steps (tortoise chart, FP64 state, WENO5): nsteps SSP-RK(3,3)
 // steps in one cooperative launch of `grid` workgroups (at most pipe_grid(),

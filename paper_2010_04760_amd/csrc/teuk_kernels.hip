@@ -1526,14 +1526,17 @@ int launch_stage(const StageArgs& a, int stage, int weight_prec, int chart, void
     return (int)hipGetLastError();
 }
 
-int blocked_grid()
+int blocked_grid(int weight_prec)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, blocked_step_kernel<TEUK_W_FP64>, kBThreads, 0) !=
-            hipSuccess || per_cu < 1)
-        return 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (weight_prec == TEUK_W_FP64)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, blocked_step_kernel<TEUK_W_FP64>, kBThreads, 0);
+    else if (weight_prec == TEUK_W_FP32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, blocked_step_kernel<TEUK_W_FP32>, kBThreads, 0);
+    if (e != hipSuccess || per_cu < 1) return 0;
     return cus * per_cu;
 }
 
@@ -1547,6 +1550,8 @@ int launch_blocked_step(const StageArgs& a, int weight_prec, void* stream)
     hipStream_t st = (hipStream_t)stream;
     if (weight_prec == TEUK_W_FP64)
         hipLaunchKernelGGL(blocked_step_kernel<TEUK_W_FP64>, grid, block, 0, st, a);
+    else if (weight_prec == TEUK_W_FP32)
+        hipLaunchKernelGGL(blocked_step_kernel<TEUK_W_FP32>, grid, block, 0, st, a);
     else
         return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();

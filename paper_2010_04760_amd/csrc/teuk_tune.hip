@@ -134,7 +134,7 @@ teuk_status teuk_tune(const teuk_config* cfg, int32_t steps, teuk_tune_info_t* o
     const bool blocked = cfg->integrator == TEUK_RK_SSP33_BLOCKED;
     const int strip = blocked ? teuk::kBlockedPoints : teuk::kStripPoints;
     const int nstrips = (cfg->nr + strip - 1) / strip;
-    const long long resident = blocked ? teuk::blocked_grid() : teuk::stage_grid(cfg->weight_prec, false, teuk::kernel_chart(*cfg));
+    const long long resident = blocked ? teuk::blocked_grid(cfg->weight_prec) : teuk::stage_grid(cfg->weight_prec, false, teuk::kernel_chart(*cfg));
     if (resident <= 0) return tfail(TEUK_ERR_UNSUPPORTED, "occupancy query failed");
 
     // candidate budgets around the resident count, one per distinct segment

@@ -10,7 +10,16 @@ radial sizes around the 114-point tile (smaller than one tile, one tile, a
 tile plus one point, the 127 points one workgroup spans, two tiles and one
 more point, several tiles), theta sizes from 2 rows, tile counts from one
 tile per strip to one row per tile, both pole parities, a = M, the waveform
-samples, the C2 grid at full size, and the configurations not offered."""
+samples, the C2 grid at full size, and the configurations not offered.
+
+FP32 weights: the blocked step and the three-launch step both form the
+weights in FP32 from the same FP64 differences, so a difference of one FP64
+ulp in a difference (from a different fused multiply-add) can move a weight
+by one FP32 ulp in one kernel and not the other.  Each is held to the
+reduced-precision bar against the FP64 oracle (1e-6 of the state's scale
+after 200 steps of a Gaussian pulse), and the two to 1e-9 of each other after
+three steps of rough data (measured far below: the weights multiply the
+candidate differences, which are small against the flux)."""
 import numpy as np
 import pytest
 
@@ -109,10 +118,39 @@ def test_c2_full_size():
     assert se <= TOL and max(pe) <= TOL_PLANE, (se, pe)
 
 
+@pytest.mark.parametrize("grid", [GRIDS[1], GRIDS[3], GRIDS[5], GRIDS[8]])
+def test_fp32_weights_against_three_launch(grid):
+    nr, nth, s, m, a = grid
+    say("case blocked fp32", grid)
+    prob = S.Problem(s, m, a, nr, nth, -30.0, 50.0)
+    dt = 0.4 * S.TeukOracle(prob).dt_bound(1.0)
+    u0 = W.random_state(nr, nth, seed=nr + 7 * nth, smooth=True)
+    ref3, _, _ = run(prob, dt, u0, 3, "rk3", weight_prec="fp32")
+    got, inf, _ = run(prob, dt, u0, 3, "rk3_blocked", weight_prec="fp32")
+    rel = float(np.max(np.abs(got - ref3))) / float(np.max(np.abs(ref3)))
+    say("  tiles", inf.workgroups, "max |blocked - three-launch| / max", rel)
+    assert rel <= 1e-9, rel
+
+
+def test_fp32_weights_reduced_precision_bar():
+    say("case blocked fp32 against the oracle")
+    wl = W.C1.with_(nr=400, nth=24)
+    prob = S.Problem(wl.s, wl.m, wl.a, wl.nr, wl.nth, wl.x_min, wl.x_max)
+    o = S.TeukOracle(prob)
+    dt = o.dt_bound(0.5)
+    u0 = W.gaussian_pulse(wl)
+    ref, _ = o.evolve(u0, dt, 200)
+    got, _, _ = run(prob, dt, u0, 200, "rk3_blocked", weight_prec="fp32")
+    err = float(np.max(np.abs(got - ref))) / float(np.max(np.abs(ref)))
+    say("  error", err)
+    assert err <= 1e-6, err
+
+
 def test_not_offered():
     say("case blocked unsupported")
     prob = S.Problem(0, 0, 0.5, 64, 4, -10.0, 10.0)
-    for kw in (dict(weight_prec="fp32"), dict(scheme="weno3"), dict(state="dd", weight_prec="dd")):
+    for kw in (dict(weight_prec="fp16"), dict(weight_prec="bf16"), dict(scheme="weno3"),
+               dict(state="dd", weight_prec="dd")):
         with pytest.raises(T.TeukError) as ei:
             T.teuk_create(cfg_for(prob, 0.0, "rk3_blocked", **kw))
         assert ei.value.status == T.TEUK_ERR_UNSUPPORTED
@@ -121,8 +159,3 @@ def test_not_offered():
     with pytest.raises(T.TeukError) as ei:
         T.teuk_create(ch)
     assert ei.value.status == T.TEUK_ERR_UNSUPPORTED
-    with T.Solver(cfg_for(prob, 0.0, "rk3_blocked")) as sv, T.Group(2) as g:
-        sv.set_initial(W.random_state(64, 4, seed=1))
-        with pytest.raises(T.TeukError) as ei:
-            g.add(sv)
-        assert ei.value.status == T.TEUK_ERR_UNSUPPORTED

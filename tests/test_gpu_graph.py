@@ -70,6 +70,26 @@ def test_single_solve_graph_equals_eager(integrator, chunk, every):
     b.close()
 
 
+@pytest.mark.parametrize("every", [0, 3])
+def test_blocked_graph_after_odd_eager_steps(every):
+    """The blocked step trades its two state buffers every step, and a graph
+    holds the buffers of its capture.  With no waveform, or an odd sampling
+    interval, an odd number of eager steps between replays leaves the
+    sampling phase unchanged but the buffers traded: the next replay must
+    recapture (it would otherwise start from the stale buffer)."""
+    wl = W.C1.with_(nr=300, nth=24)
+    kw = dict(extract_every=every, max_samples=9 if every else 0, x_extract=10.0)
+    a, b = _pair(wl, integrator="rk3_blocked", **kw)
+    a.set_graph(6)
+    for n in (3, 6, 9, 12, 5, 7, 6):
+        say(f"blocked every {every}: step {n}")
+        a.step(n)
+        b.step(n)
+        _same(a, b)
+    a.close()
+    b.close()
+
+
 def test_chart_h_graph_equals_eager():
     wl = W.C3H.with_(nr=240, nth=16)
     a, b = _pair(wl, extract_every=5, max_samples=9, x_extract=19.0)

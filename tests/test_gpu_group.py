@@ -288,3 +288,44 @@ def test_group_errors():
         g.step(2)                              # empty group: no-op
         for sv in (fresh, sv_side):
             sv.close()
+
+
+@pytest.mark.parametrize("chunk", [0, 4])
+def test_blocked_members_bitwise(chunk):
+    """Members with the temporally blocked step (FP64 and FP32 weights) beside
+    three-launch members: each blocked member is a cache block of its own,
+    stepped by its own blocked launches (which trade its two state buffers
+    every step), so the group must still equal every member stepped alone,
+    eagerly and in graph mode (an even chunk; an odd one is refused)."""
+    say("case group with blocked members, graph chunk", chunk)
+    # sampling intervals of 1 and 0, so that only the buffer swaps forbid an odd chunk
+    specs = [(300, 17, -2, 1, 1.0, "fp32", 1, "rk3_blocked"), (200, 9, 0, 2, 0.7, "fp64", 1, "rk3"),
+             (513, 12, -2, 2, 0.999, "fp64", 0, "rk3_blocked"), (130, 33, 0, 0, 0.5, "fp32", 0, "rk3")]
+    alone, members = [], []
+    g = T.Group(len(specs))
+    for i, (nr, nth, s_, m, a, wp, every, integ) in enumerate(specs):
+        cfg = T.make_config(s=s_, m=m, a=a, nr=nr, ntheta=nth, x_min=-30.0, x_max=50.0, weight_prec=wp,
+                            x_extract=10.0, extract_every=every, max_samples=64 if every else 0, integrator=integ)
+        u0 = W.random_state(nr, nth, seed=70 + i, smooth=True)
+        ref = T.Solver(cfg)
+        ref.set_initial(u0)
+        for n in (3, 8, 5):
+            ref.step(n)
+        alone.append(snapshot(ref))
+        ref.close()
+        sv = T.Solver(cfg)
+        sv.set_initial(u0)
+        g.add(sv)
+        members.append(sv)
+    if chunk:
+        with pytest.raises(T.TeukError) as ei:
+            g.set_graph(chunk + 1)
+        assert ei.value.status == T.TEUK_ERR_INVALID_ARG
+        g.set_graph(chunk)
+    for n in (3, 8, 5):
+        g.step(n)
+    for i, sv in enumerate(members):
+        assert_same(snapshot(sv), alone[i], ("blocked member", i, chunk))
+    g.close()
+    for sv in members:
+        sv.close()
