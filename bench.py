@@ -285,8 +285,9 @@ def bench_single(args, torch, T, W):
     hs = make(weights, warmup + steps)
     # (name, solver, timed steps, warmup steps, graph chunk, label), timed in this order
     chain = [("headline", hs, steps, warmup, graph, f"fp64/{weights}/rk3 (headline)")]
-    if not c1 and weights == "fp64" and not args.no_blocked:
-        chain.append(("blocked", make("fp64", warmup + lsteps, integrator="rk3_blocked"), lsteps, warmup, 0,
+    if weights == "fp64" and not args.no_blocked:
+        # in the headline's launch mode (C1: one launch per step, replayed from a graph)
+        chain.append(("blocked", make("fp64", warmup + lsteps, integrator="rk3_blocked"), lsteps, warmup, graph,
                       "fp64/fp64/rk3_blocked"))
     if not args.no_graph_leg:
         chain.append(("graph", make(weights, warmup + lsteps), lsteps, warmup, other,
@@ -407,11 +408,6 @@ def bench_single(args, torch, T, W):
                             "speedup_vs_headline": t_step / (secp / lsteps), "workgroups": infop.workgroups,
                             "waveform_identical": bool(np.array_equal(wp_, wh)),
                             "launches": "one per waveform interval (every %d steps)" % wl.every}
-    if c1:
-        if not args.no_cpu_baseline:
-            log("cpu baseline (oracle)")
-            out["cpu_baseline"] = cpu_baseline(wl, u0, args.cpu_seconds)
-        return out
     if do_blocked:
         # Temporal blocking: the same SSP-RK(3,3) step as one launch per step
         # (u(1), u(2) in LDS; 64 B of HBM traffic per point-step; "traffic" is
@@ -424,8 +420,13 @@ def bench_single(args, torch, T, W):
             "waveform_rel_diff_vs_three_launch": float(np.max(np.abs(wb - wh)) / max(np.max(np.abs(wh)), 1e-300)),
             "hbm": {"bytes_per_point_step": 64, "achieved_GBs": 64.0 * wl.points * lsteps / secb / 1e9,
                     "frac": 64.0 * wl.points * lsteps / secb / 1e9 / HBM_PEAK_GBS,
-                    "traffic": measured_traffic("fp64", "bytes_per_blocked_step")},
+                    "traffic": None if c1 else measured_traffic("fp64", "bytes_per_blocked_step")},
         }
+    if c1:
+        if not args.no_cpu_baseline:
+            log("cpu baseline (oracle)")
+            out["cpu_baseline"] = cpu_baseline(wl, u0, args.cpu_seconds)
+        return out
     if do_rk104:
         # SSP-RK(10,4) (Sec. 3.2) over the same simulated time: its default step
         # is 6x the SSP-RK(3,3) step (SSP coefficients 6 and 1), ten stages per
