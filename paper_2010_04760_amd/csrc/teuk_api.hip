@@ -1173,6 +1173,8 @@ static teuk_status group_upload(teuk_group* g)
         GroupBlock blk;
         long long bytes = 0;
         bool all_fill = true, blocked = false;
+        // resident workgroups of the class's stage-2/3 kernel (class c = weight precision + 4 launch class)
+        const long long resident = TEUK_GROUP_SOLO ? stage_grid(c % 4, false, c / 4) : 0;
         auto open_block = [&]() {
             blk = GroupBlock();
             blk.cls = c;
@@ -1199,10 +1201,8 @@ static teuk_status group_upload(teuk_group* g)
                 open_block();
             }
             blocked = bl;
-            if (TEUK_GROUP_SOLO) {
-                const long long resident = stage_grid(h->cfg.weight_prec, false, kernel_chart(h->cfg));
+            if (TEUK_GROUP_SOLO)
                 all_fill = all_fill && resident > 0 && (long long)h->nstrips * h->cfg.ntheta >= resident;
-            }
             StageArgs a = stage_args(h);
             a.segs = group_segs(h->cfg.ntheta, g->rows);
             a.grid = 0;                                  // set per launch
