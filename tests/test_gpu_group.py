@@ -329,3 +329,50 @@ def test_blocked_members_bitwise(chunk):
     g.close()
     for sv in members:
         sv.close()
+
+
+@pytest.mark.parametrize("chunk", [0, 6])
+def test_solo_blocks_bitwise(chunk):
+    """Members that each fill the GPU (strips x rows above the resident
+    workgroups) form solo cache blocks, stepped by their own single-solve
+    launches member after member: the group must still equal every member
+    stepped alone, eagerly and from captured graphs, and report the members'
+    own launch shapes.  With the batched launch's workgroup count fixed by the
+    caller the same members take the batched launch, with the same results."""
+    say("case solo cache blocks, graph chunk", chunk)
+    specs = [(4096, 72, -2, 2, 0.9, "fp64", 3), (4200, 70, 0, 1, 0.6, "fp32", 2), (4150, 66, -2, 0, 0.99, "fp64", 0)]
+    alone, cfgs, u0s = [], [], []
+    for i, (nr, nth, s_, m, a, wp, every) in enumerate(specs):
+        cfg = T.make_config(s=s_, m=m, a=a, nr=nr, ntheta=nth, x_min=-100.0, x_max=300.0, weight_prec=wp,
+                            x_extract=30.0, extract_every=every, max_samples=64 if every else 0)
+        u0 = W.random_state(nr, nth, seed=90 + i, smooth=True)
+        with T.Solver(cfg) as ref:
+            ref.set_initial(u0)
+            for n in (4, 12, 7):
+                ref.step(n)
+            alone.append(snapshot(ref))
+            own_wg = ref.info().workgroups
+        cfgs.append(cfg)
+        u0s.append(u0)
+    for wg in (0, 1000):
+        members = []
+        g = T.Group(len(specs), workgroups=wg)
+        for cfg, u0 in zip(cfgs, u0s):
+            sv = T.Solver(cfg)
+            sv.set_initial(u0)
+            g.add(sv)
+            members.append(sv)
+        inf = g.info()
+        if wg == 0:
+            # the two FP64 members (about 28 MB each) share one solo block, the FP32 member has its
+            # own; each is launched with its own tiling, so the reported workgroups equal the tiles
+            assert inf.workgroups == inf.tiles
+        if chunk:
+            g.set_graph(chunk)
+        for n in (4, 12, 7):
+            g.step(n)
+        for i, sv in enumerate(members):
+            assert_same(snapshot(sv), alone[i], ("solo block member", i, wg, chunk))
+        g.close()
+        for sv in members:
+            sv.close()
