@@ -132,6 +132,20 @@ def test_fp32_weights_against_three_launch(grid):
     assert rel <= 1e-9, rel
 
 
+def test_fp32_weights_c2_full_size():
+    wl = W.C2
+    say("case blocked fp32 C2 full size")
+    prob = S.Problem(wl.s, wl.m, wl.a, wl.nr, wl.nth, wl.x_min, wl.x_max)
+    u0 = W.gaussian_pulse(wl)
+    g3, i3, _ = run(prob, 0.0, u0, 3, "rk3", weight_prec="fp32")
+    gb, ib, _ = run(prob, 0.0, u0, 3, "rk3_blocked", weight_prec="fp32")
+    rel = float(np.max(np.abs(gb - g3))) / float(np.max(np.abs(g3)))
+    say("  tiles", ib.workgroups, "max |blocked - three-launch| / max", rel)
+    assert ib.dt == i3.dt and rel <= 1e-9, rel
+    oref, _ = S.TeukOracle(prob).evolve(u0, i3.dt, 3)
+    assert float(np.max(np.abs(gb - oref))) / float(np.max(np.abs(oref))) <= 1e-6
+
+
 def test_fp32_weights_reduced_precision_bar():
     say("case blocked fp32 against the oracle")
     wl = W.C1.with_(nr=400, nth=24)

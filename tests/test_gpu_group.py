@@ -340,11 +340,12 @@ def test_solo_blocks_bitwise(chunk):
     own launch shapes.  With the batched launch's workgroup count fixed by the
     caller the same members take the batched launch, with the same results."""
     say("case solo cache blocks, graph chunk", chunk)
-    specs = [(4096, 72, -2, 2, 0.9, "fp64", 3), (4200, 70, 0, 1, 0.6, "fp32", 2), (4150, 66, -2, 0, 0.99, "fp64", 0)]
+    specs = [(4096, 72, -2, 2, 0.9, "fp64", 3, 2), (4200, 70, 0, 1, 0.6, "fp32", 2, 2),
+             (4150, 66, -2, 0, 0.99, "fp64", 0, 2), (4100, 68, -2, 1, 0.8, "fp64", 1, 4)]
     alone, cfgs, u0s = [], [], []
-    for i, (nr, nth, s_, m, a, wp, every) in enumerate(specs):
+    for i, (nr, nth, s_, m, a, wp, every, order) in enumerate(specs):
         cfg = T.make_config(s=s_, m=m, a=a, nr=nr, ntheta=nth, x_min=-100.0, x_max=300.0, weight_prec=wp,
-                            x_extract=30.0, extract_every=every, max_samples=64 if every else 0)
+                            x_extract=30.0, extract_every=every, max_samples=64 if every else 0, theta_order=order)
         u0 = W.random_state(nr, nth, seed=90 + i, smooth=True)
         with T.Solver(cfg) as ref:
             ref.set_initial(u0)
@@ -364,8 +365,9 @@ def test_solo_blocks_bitwise(chunk):
             members.append(sv)
         inf = g.info()
         if wg == 0:
-            # the two FP64 members (about 28 MB each) share one solo block, the FP32 member has its
-            # own; each is launched with its own tiling, so the reported workgroups equal the tiles
+            # the two second-order FP64 members (about 28 MB each) share one solo block, the FP32 and
+            # the fourth-order members have their own; each is launched with its own tiling, so the
+            # reported workgroups equal the tiles
             assert inf.workgroups == inf.tiles
         if chunk:
             g.set_graph(chunk)
