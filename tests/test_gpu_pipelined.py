@@ -47,6 +47,7 @@ CASES = [
     ("extremal 2000x40 s=-2 m=2", W.C2.with_(nr=2000, nth=40, a=1.0, x_min=-150.0, x_max=250.0, seed=63), {}),
     ("fp32 weights 1000x64", W.C2.with_(nr=1000, nth=64, x_min=-100.0, x_max=200.0, seed=64), {"weight_prec": "fp32"}),
     ("fp16 weights 640x33 m=1", W.C2.with_(nr=640, nth=33, m=1, x_min=-100.0, x_max=200.0, seed=65), {"weight_prec": "fp16"}),
+    ("bf16 weights 900x18 m=3", W.C2.with_(nr=900, nth=18, m=3, x_min=-100.0, x_max=200.0, seed=66), {"weight_prec": "bf16"}),
 ]
 
 
