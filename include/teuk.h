@@ -497,7 +497,7 @@ teuk_status teuk_group_set_graph(teuk_group* g, int32_t chunk_steps);
 
 /* Tune the group's tile height and cache-block size on its current members.
  * Times rows_per_tile in {4, 8, 16, 32, 64} by cache blocks of
- * {128, 256, 384, 512} MiB of member footprint (and the group's current
+ * {32, 64, 128, 256, 384, 512} MiB of member footprint (and the group's current
  * shape), each the best of two runs of `steps` steps (0: chosen to take about
  * 20 ms) on clones of the members -- same grids, classes and step sizes,
  * starting from the members' current states, no waveform rings -- so the

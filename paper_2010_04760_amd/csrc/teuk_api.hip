@@ -1556,7 +1556,9 @@ teuk_status teuk_group_tune(teuk_group* g, int32_t steps, teuk_group_tune_info_t
         }
     }
     const int rows_c[] = {4, 8, 16, 32, 64};
-    const long long mib_c[] = {128, 256, 384, 512};
+    // small blocks matter once members fill the GPU by themselves (solo blocks: a block
+    // of one member runs all its steps alone, with its state in the last-level cache)
+    const long long mib_c[] = {32, 64, 128, 256, 384, 512};
     int best_rows = g->rows;
     long long best_bytes = g->block_bytes;
     double best_us = 0.0, default_us = 0.0;
